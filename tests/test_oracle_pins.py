@@ -1,0 +1,336 @@
+"""Pins of the oracle's GHK integrals, E-step, M-step and EM against
+closed forms, brute-force Monte Carlo and the textbook t-mixture EM."""
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize, special as sp, stats
+
+from paper_2005_06848_amd import inputs
+import refmath
+
+
+# ---------------------------------------------------------------- q = 1 ----
+@pytest.mark.parametrize("h,dof", [(0.7, 6.0), (-2.0, 9.0), (3.0, 12.0), (-0.4, 5.2)])
+def test_ghk_q1_closed_form_rqmc(orc, h, dof):
+    """T_1(h; 1, dof) = stdtr(dof, h) and the truncated Student-t moments,
+    from 32 random digital shifts of 4096 Sobol points: |mean - exact| < 5 SE."""
+    res = []
+    for s in range(32):
+        u = inputs.qmc_points(4096, 1, seed=7000 + s)
+        lt, ev, evv = orc.ghk([h], [[1.0]], dof, u)
+        res.append([math.exp(lt), ev[0], evv[0, 0]])
+    res = np.array(res)
+    mean = res.mean(0)
+    se = res.std(0, ddof=1) / math.sqrt(len(res))
+    m1, m2 = refmath.t_trunc_moments_upper(h, dof)
+    exact = np.array([sp.stdtr(dof, h), m1, m2])
+    assert np.all(np.abs(mean - exact) < 5 * se + 1e-12), (mean, exact, se)
+    assert se[0] < 3e-4 * exact[0]
+
+
+def test_ghk_q1_converges(orc):
+    u = inputs.qmc_points(2 ** 16, 1)
+    lt, _, _ = orc.ghk([0.9], [[1.0]], 7.0, u, moments=False)
+    assert math.exp(lt) == pytest.approx(sp.stdtr(7.0, 0.9), rel=1e-5)
+
+
+# ---------------------------------------------------------------- q = 2 ----
+@pytest.mark.parametrize("h1,h2,rho,dof", [(0.5, -0.3, 0.4, 6.0), (1.5, 0.8, -0.6, 10.0),
+                                           (-1.0, -0.7, 0.7, 8.0), (-2.2, 1.3, 0.2, 12.0)])
+def test_ghk_q2_bivariate_t(orc, h1, h2, rho, dof):
+    """T_2 against Owen's-T bivariate normal integrated over the chi scale."""
+    exact = refmath.t2_cdf(h1, h2, rho, dof)
+    C = np.array([[1.0, 0.0], [rho, math.sqrt(1 - rho * rho)]])
+    res = []
+    for s in range(16):
+        u = inputs.qmc_points(4096, 2, seed=9000 + s)
+        lt, _, _ = orc.ghk([h1, h2], C, dof, u, moments=False)
+        res.append(math.exp(lt))
+    res = np.array(res)
+    se = res.std(ddof=1) / 4
+    assert abs(res.mean() - exact) < 5 * se + 1e-12
+    assert abs(res.mean() / exact - 1) < 1e-3
+
+
+def test_bivariate_reference_against_scipy():
+    """The test's own bivariate-t reference agrees with scipy's (randomised) cdf."""
+    R = [[1.0, 0.4], [0.4, 1.0]]
+    ref = stats.multivariate_t(loc=[0, 0], shape=R, df=6.0).cdf([0.5, -0.3],
+                                                                  maxpts=4_000_000, random_state=1)
+    assert refmath.t2_cdf(0.5, -0.3, 0.4, 6.0) == pytest.approx(ref, abs=2e-5)
+
+
+# ------------------------------------------------- brute-force moments ----
+@pytest.mark.parametrize("q,n_draws", [(2, 10_000_000), (4, 4_000_000), (6, 4_000_000)])
+def test_truncated_moments_bruteforce(orc, q, n_draws):
+    rng = np.random.default_rng(42 + q)
+    A = rng.standard_normal((q, q + 2))
+    S = A @ A.T / (q + 2)
+    d = np.sqrt(np.diag(S))
+    R = S / np.outer(d, d)
+    C = np.linalg.cholesky(R)
+    h = rng.uniform(-0.3, 1.5, size=q)
+    dof = 7.5
+    u = inputs.qmc_points(2 ** 14, q)
+    lt, ev, evv = orc.ghk(h, C, dof, u)
+    P, m1, m2, seP, se1, se2 = refmath.mc_truncated_t(h, R, dof, n_draws, seed=100 + q)
+    # QMC error of the oracle is far below the Monte Carlo error at these sizes
+    assert abs(math.exp(lt) - P) < 5 * seP + 2e-4 * P
+    assert np.all(np.abs(ev - m1) < 5 * se1 + 2e-3)
+    assert np.all(np.abs(evv - m2) < 5 * se2 + 5e-3)
+
+
+# ------------------------------------------------- density, p = q = 1 ----
+def test_density_pq1_closed_form(orc):
+    """CFUST with p = q = 1 equals the univariate skew-t written with t functions."""
+    par = dict(pi=[1.0], mu=[[0.4]], Sigma=[[[0.8]]], Delta=[[[1.3]]], nu=[5.0])
+    y = np.linspace(-6, 9, 41)[:, None]
+    u = inputs.qmc_points(2 ** 17, 1)
+    _, lf = orc.loglik(y, par, u, want_logf=True)
+    ref = refmath.skew_t_pq1_logpdf(y[:, 0], 0.4, 0.8, 1.3, 5.0)
+    # the left tail has T_1 ~ 1e-3, where the QMC relative error is largest
+    assert np.max(np.abs(lf[:, 0] - ref)) < 1e-4
+    assert np.max(np.abs(np.exp(lf[:, 0]) - np.exp(ref))) < 2e-6 * np.exp(ref).max()
+
+
+def test_density_integrates_to_one(orc):
+    """eq. (2) is a density: for p = q = 1 it integrates to 1 (GL quadrature after y = tan t)."""
+    par = dict(pi=[1.0], mu=[[-0.3]], Sigma=[[[1.1]]], Delta=[[[-0.9]]], nu=[6.0])
+    x, w = np.polynomial.legendre.leggauss(600)
+    t = x * (math.pi / 2) * (1 - 1e-9)
+    y = 2.0 * np.tan(t)
+    jac = 2.0 / np.cos(t) ** 2 * (math.pi / 2) * (1 - 1e-9)
+    u = inputs.qmc_points(2 ** 13, 1)
+    _, lf = orc.loglik(y[:, None], par, u, want_logf=True)
+    total = np.sum(w * jac * np.exp(lf[:, 0]))
+    assert total == pytest.approx(1.0, abs=2e-5)
+
+
+# ------------------------------------ hidden-variable posterior, p=q=2 ----
+def test_pair_expectations_against_latent_mc(orc):
+    """f(y), e2, e3, e4 of one component against importance sampling of the
+    hidden-variable model (W ~ Gamma, U = |U0|/sqrt(W), Y|W,U ~ N(mu + Delta U, Sigma/W))."""
+    mu = np.array([0.5, -1.0])
+    Sigma = np.array([[1.0, 0.3], [0.3, 0.7]])
+    Delta = np.array([[1.2, -0.4], [0.3, 0.9]])
+    nu = 6.0
+    par = dict(pi=[1.0], mu=[mu], Sigma=[Sigma], Delta=[Delta], nu=[nu])
+    u = inputs.qmc_points(2 ** 14, 2)
+    ys = np.array([[1.1, -0.2], [0.0, -1.5], [2.5, 0.8]])
+    out = orc.estep(ys, par, u)
+    for j, y in enumerate(ys):
+        mc = refmath.mc_cfust_posterior(y, mu, Sigma, Delta, nu, 4_000_000, seed=300 + j)
+        f = math.exp(out["logf"][j, 0])
+        assert abs(f - mc["f"]) < 5 * mc["f_se"] + 1e-4 * f
+        assert abs(out["e2"][j, 0] - mc["e2"]) < 5 * mc["e2_se"] + 1e-3
+        assert np.all(np.abs(out["e3"][j, 0] - mc["e3"]) < 5 * mc["e3_se"] + 2e-3)
+        assert np.all(np.abs(out["e4"][j, 0] - mc["e4"]) < 5 * mc["e4_se"] + 4e-3)
+
+
+# ------------------------------------------------ Delta = 0: t-mixture ----
+def test_delta_zero_reduces_to_t_mixture_em(orc):
+    c = inputs.random_case(11, 400, 3, 2, 2, 256)
+    par = {k: np.array(v) for k, v in c["params"].items()}
+    par["Delta"] = np.zeros_like(par["Delta"])
+    fit = orc.em_fit(c["y"], par, c["u"], max_iter=6, tol=0.0, fix_delta_zero=True)
+    ref = refmath.t_mixture_em(c["y"], par["pi"], par["mu"], par["Sigma"], par["nu"], 6)
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-11)
+    np.testing.assert_allclose(fit["pi"], ref["pi"], rtol=1e-10)
+    np.testing.assert_allclose(fit["mu"], ref["mu"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(fit["Sigma"], ref["Sigma"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(fit["nu"], ref["nu"], rtol=1e-9)
+    np.testing.assert_array_equal(fit["Delta"], 0.0)
+
+
+def test_delta_zero_pair_values(orc):
+    """Delta = 0: T_A = T_B = 2^-q exactly, f = t_p and e2 = (nu+p)/(nu+d)."""
+    c = inputs.random_case(12, 50, 4, 3, 2, 512)
+    par = {k: np.array(v) for k, v in c["params"].items()}
+    par["Delta"] = np.zeros_like(par["Delta"])
+    out = orc.estep(c["y"], par, c["u"])
+    for i in range(2):
+        lt = stats.multivariate_t(par["mu"][i], par["Sigma"][i], df=par["nu"][i]).logpdf(c["y"])
+        np.testing.assert_allclose(out["logf"][:, i], np.log(par["pi"][i]) + lt, rtol=1e-13)
+        r = c["y"] - par["mu"][i]
+        d = np.einsum("nj,jk,nk->n", r, np.linalg.inv(par["Sigma"][i]), r)
+        np.testing.assert_allclose(out["e2"][:, i], (par["nu"][i] + 4) / (par["nu"][i] + d), rtol=1e-12)
+        a = (par["nu"][i] + 4) / 2
+        b = (par["nu"][i] + d) / 2
+        np.testing.assert_allclose(out["e1"][:, i], sp.digamma(a) - np.log(b), rtol=1e-12, atol=1e-13)
+
+
+# ----------------------------------------------------- M-step, complete data ----
+def test_mstep_complete_data_regression(orc):
+    """With complete-data statistics (known w and u, tau = 1) the CM-steps are
+    a weighted mean, a weighted least-squares regression of y on u, its
+    residual covariance and the gamma maximum-likelihood shape."""
+    rng = np.random.default_rng(5)
+    n, p, q = 20000, 3, 2
+    mu_t = np.array([1.0, -2.0, 0.5])
+    Sg_t = np.array([[1.0, 0.2, 0.1], [0.2, 0.8, -0.3], [0.1, -0.3, 1.5]])
+    D_t = np.array([[1.5, 0.0], [-0.7, 1.1], [0.4, -0.6]])
+    nu_t = 7.0
+    w = rng.gamma(nu_t / 2, 2 / nu_t, size=n)
+    uu = np.abs(rng.standard_normal((n, q))) / np.sqrt(w)[:, None]
+    y = mu_t + uu @ D_t.T + (rng.standard_normal((n, p)) @ np.linalg.cholesky(Sg_t).T) / np.sqrt(w)[:, None]
+    mu_old = np.array([0.7, -1.5, 0.2])
+    D_old = np.array([[1.0, 0.1], [-0.5, 1.0], [0.2, -0.2]])
+
+    def complete_stats(mu0):
+        r = y - mu0
+        S = orc.stats_size(p, q)
+        st = np.zeros(S)
+        o3, o4 = 2, 2 + p
+        o5 = o4 + q
+        o6 = o5 + q * (q + 1) // 2
+        o7 = o6 + p * q
+        st[0] = n
+        st[1] = w.sum()
+        st[o3:o3 + p] = (w[:, None] * r).sum(0)
+        st[o4:o4 + q] = (w[:, None] * uu).sum(0)
+        k = 0
+        for a in range(q):
+            for b in range(a, q):
+                st[o5 + k] = (w * uu[:, a] * uu[:, b]).sum()
+                k += 1
+        st[o6:o6 + p * q] = (r[:, :, None] * (w[:, None] * uu)[:, None, :]).sum(0).ravel()
+        k = 0
+        for a in range(p):
+            for b in range(a, p):
+                st[o7 + k] = (w * r[:, a] * r[:, b]).sum()
+                k += 1
+        st[-1] = (np.log(w) - w).sum()
+        return st[None, :]
+
+    old = dict(pi=[1.0], mu=[mu_old], Sigma=[Sg_t], Delta=[D_old], nu=[5.0])
+    new = orc.mstep(complete_stats(mu_old), n, old)
+    mu_ref = np.average(y - uu @ D_old.T, axis=0, weights=w)
+    sw = np.sqrt(w)[:, None]
+    coef, *_ = np.linalg.lstsq(sw * uu, sw * (y - mu_ref), rcond=None)
+    D_ref = coef.T
+    res = y - mu_ref - uu @ D_ref.T
+    Sg_ref = (w[:, None] * res).T @ res / n
+    nll = lambda v: -np.sum(v / 2 * np.log(v / 2) - sp.gammaln(v / 2) + (v / 2 - 1) * np.log(w) - v / 2 * w)
+    nu_ref = optimize.minimize_scalar(nll, bounds=(1, 200), method="bounded",
+                                      options=dict(xatol=1e-11)).x
+    np.testing.assert_allclose(new["mu"][0], mu_ref, rtol=1e-11)
+    np.testing.assert_allclose(new["Delta"][0], D_ref, rtol=1e-9)
+    np.testing.assert_allclose(new["Sigma"][0], Sg_ref, rtol=1e-9)
+    assert new["nu"][0] == pytest.approx(nu_ref, rel=1e-7)
+    assert new["pi"][0] == 1.0
+    # cycling the CM-steps converges to the complete-data MLE, near the truth
+    par = new
+    for _ in range(60):
+        par = orc.mstep(complete_stats(par["mu"][0]), n, par)
+    np.testing.assert_allclose(par["Delta"][0], D_t, atol=0.1)
+    np.testing.assert_allclose(par["mu"][0], mu_t, atol=0.1)
+    assert abs(par["nu"][0] - nu_t) < 1.0
+
+
+# ------------------------------------------------------------ invariances ----
+def test_affine_and_permutation_invariance(orc):
+    c = inputs.random_case(13, 60, 3, 3, 3, 512)
+    par = c["params"]
+    out = orc.estep(c["y"], par, c["u"])
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((3, 3)) + 2 * np.eye(3)
+    b = rng.standard_normal(3)
+    par2 = dict(pi=par["pi"], mu=par["mu"] @ A.T + b,
+                Sigma=np.einsum("ab,ibc,dc->iad", A, par["Sigma"], A),
+                Delta=np.einsum("ab,ibc->iac", A, par["Delta"]), nu=par["nu"])
+    out2 = orc.estep(c["y"] @ A.T + b, par2, c["u"])
+    np.testing.assert_allclose(out2["tau"], out["tau"], atol=1e-11)
+    np.testing.assert_allclose(out2["logf"], out["logf"] - np.log(abs(np.linalg.det(A))), atol=1e-10)
+    for k in ("e2", "e3", "e4"):
+        np.testing.assert_allclose(out2[k], out[k], rtol=1e-9, atol=1e-10)
+    perm = [2, 0, 1]
+    par3 = {k: np.asarray(v)[perm] for k, v in par.items()}
+    out3 = orc.estep(c["y"], par3, c["u"])
+    np.testing.assert_allclose(out3["tau"], out["tau"][:, perm], atol=1e-15)
+    np.testing.assert_allclose(out3["e4"], out["e4"][:, perm], rtol=1e-15)
+    assert out3["loglik"] == pytest.approx(out["loglik"], rel=1e-15)
+
+
+def test_estep_properties(orc):
+    c = inputs.random_case(14, 80, 3, 2, 3, 512)
+    out = orc.estep(c["y"], c["params"], c["u"])
+    np.testing.assert_allclose(out["tau"].sum(1), 1.0, rtol=1e-14)
+    assert np.all(out["e2"] > 0)
+    assert np.all(out["e3"] > 0)
+    # Cauchy-Schwarz: e2 e4 - e3 e3^T is positive semidefinite
+    for j in range(80):
+        for i in range(3):
+            M = out["e2"][j, i] * out["e4"][j, i] - np.outer(out["e3"][j, i], out["e3"][j, i])
+            assert np.linalg.eigvalsh(M).min() > -1e-9 * np.abs(M).max()
+    # stats are the tau-weighted sums of the per-pair values
+    st = out["stats"]
+    np.testing.assert_allclose(st[:, 0], out["tau"].sum(0), rtol=1e-13)
+    np.testing.assert_allclose(st[:, 1], (out["tau"] * out["e2"]).sum(0), rtol=1e-13)
+    np.testing.assert_allclose(st[:, -1], (out["tau"] * (out["e1"] - out["e2"])).sum(0), rtol=1e-12)
+    assert out["loglik"] == pytest.approx(orc.loglik(c["y"], c["params"], c["u"]), rel=1e-14)
+
+
+def test_deep_tail_observation_is_finite(orc):
+    c = inputs.random_case(15, 5, 2, 2, 2, 256)
+    y = c["y"].copy()
+    # far out along the direction where the skewing integral is tiny
+    y[0] = c["params"]["mu"][0] - 4000.0 * c["params"]["Delta"][0].sum(1)
+    out = orc.estep(y, c["params"], c["u"])
+    assert np.all(np.isfinite(out["logf"]))
+    assert np.all(np.isfinite(out["tau"]))
+    np.testing.assert_allclose(out["tau"].sum(1), 1.0, rtol=1e-14)
+
+
+def test_empty_input(orc):
+    c = inputs.random_case(16, 0, 2, 2, 2, 64)
+    out = orc.estep(c["y"].reshape(0, 2), c["params"], c["u"])
+    assert out["loglik"] == 0.0
+    assert np.all(out["stats"] == 0.0)
+
+
+def test_invalid_inputs(orc):
+    c = inputs.random_case(17, 10, 2, 2, 2, 64)
+    bad = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    bad["nu"][1] = -1.0
+    with pytest.raises(orc.OracleError) as e:
+        orc.estep(c["y"], bad, c["u"])
+    assert e.value.code == orc.EINVAL
+    bad = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    bad["Sigma"][1] = -np.eye(2) * 5
+    with pytest.raises(orc.OracleError) as e:
+        orc.estep(c["y"], bad, c["u"])
+    assert e.value.code == orc.ENOTPD and e.value.bad == 1
+    y = c["y"].copy()
+    y[3, 1] = np.nan
+    with pytest.raises(orc.OracleError) as e:
+        orc.estep(y, c["params"], c["u"])
+    assert e.value.code == orc.ENONFINITE
+
+
+# ---------------------------------------------------------------- EM ----
+def test_em_monotone_fixed_nu(orc):
+    """With nu held fixed the ECM steps for mu, Delta, Sigma, pi do not lower
+    the (QMC) log-likelihood beyond the integration slack."""
+    c = inputs.config(1)
+    fit = orc.em_fit(c["y"], c["init"], c["u"], max_iter=8, tol=0.0, nu_mode=orc.NU_FIXED)
+    d = np.diff(fit["trace"])
+    assert np.all(d > -1e-3 * abs(fit["trace"][0]) * 1e-3), d
+    assert fit["trace"][-1] > fit["trace"][0]
+
+
+def test_aitken_geometric_sequence(orc):
+    """For l_k = l* - C r^k the corrected rule (denominator 1 - a) returns l* exactly."""
+    for lstar, C, r in [(-100.0, 5.0, 0.5), (-2211.3, 40.0, 0.9), (12.0, 1.0, 0.1)]:
+        l = [lstar - C * r ** k for k in range(3)]
+        assert orc.aitken_linf(*l) == pytest.approx(lstar, rel=1e-13)
+
+
+def test_resume_equals_straight_run(orc):
+    c = inputs.config(1)
+    full = orc.em_fit(c["y"], c["init"], c["u"], max_iter=4, tol=0.0)
+    a = orc.em_fit(c["y"], c["init"], c["u"], max_iter=2, tol=0.0)
+    b = orc.em_fit(c["y"], a, c["u"], max_iter=2, tol=0.0)
+    for k in ("pi", "mu", "Sigma", "Delta", "nu"):
+        np.testing.assert_array_equal(b[k], full[k])
+    np.testing.assert_array_equal(b["trace"], full["trace"][2:])
