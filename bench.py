@@ -1,0 +1,165 @@
+"""Benchmark: CFUST mixture EM iterations on one MI355X.
+
+One step = one EM iteration of the whole hot path on the n=20000, p=q=4,
+g=3, N=4096 workload (FP64): per-component precompute and chi-square tables,
+the fused pair kernel (Mahalanobis distance, both GHK integrals, the
+conditional expectations), responsibilities, log-likelihood, the eight
+partial sums, and the M-step.  The metric is E-step (observation x component)
+evaluations per second.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one
+GPU (the path would shard by observations with one all-reduce of the partial
+sums per iteration).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "cfust-em n=20000 p=4 q=4 g=3 N=4096 fp64"
+PEAK_FP64_VALU_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic FP64 flops per (observation, component) pair of the pair kernel
+# at p=q=4, N=4096: executed FP64 VALU flops per pair counted once with
+# rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA = 2) on the
+# first correct version of the kernel, then frozen (see profiles/).
+FLOPS_PER_PAIR = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-obs", type=int, default=500,
+                    help="observations of the workload timed on the CPU oracle")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size (traffic calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2005_06848_amd import inputs, native
+
+    L = native.lib()
+    dev = torch.device("cuda:0")
+    c = inputs.config(2)
+    n, p, q, g, N = c["n"], c["p"], c["q"], c["g"], c["n_qmc"]
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y = T(c["y"])
+    u = T(c["u"])
+    init = {k: T(v) for k, v in c["init"].items()}
+    par = {k: v.clone() for k, v in init.items()}
+    S = native.stats_size(p, q)
+    stats = torch.empty((g, S), dtype=torch.float64, device=dev)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = native.alloc_workspace(n, p, q, g, N, args.precision)
+    prof = native.prof_buffer()
+    opts = native.make_opts(precision=args.precision, workspace=ws, prof=prof)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    out = native.EstepOut(None, None, None, None, None, None, P(stats), P(ll), -1)
+    bad = ctypes.c_int(-1)
+    pp = [P(par[k]) for k in ("pi", "mu", "Sigma", "Delta", "nu")]
+
+    def step():
+        rc = L.cfust_estep(P(y), n, p, q, g, pp[0], pp[1], pp[2], pp[3], pp[4], P(u), N,
+                           ctypes.byref(opts), ctypes.byref(out))
+        if rc:
+            raise native.CfustError(rc, "cfust_estep", out.bad_component)
+        rc = L.cfust_mstep(P(stats), n, p, q, g, pp[1], pp[3], pp[4], ctypes.byref(opts),
+                           pp[0], pp[1], pp[2], pp[3], pp[4], ctypes.byref(bad))
+        if rc:
+            raise native.CfustError(rc, "cfust_mstep", bad.value)
+
+    print(f"[bench] warmup {args.warmup} steps: {WORKLOAD}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for k in par:
+        par[k].copy_(init[k])
+    for s in range(4):
+        prof[s] = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs = n * g
+    value = pairs / (ms_per_step * 1e-3)
+    pair_ms = prof[1] / args.steps
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, pair kernel {pair_ms:.3f} ms, "
+          f"prepare {prof[0] / args.steps:.3f} ms, stats {prof[2] / args.steps:.3f} ms, "
+          f"mstep {prof[3] / args.steps:.3f} ms", file=sys.stderr, flush=True)
+
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib * (1 << 20)
+        a = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe {args.copy_probe_mib} MiB done", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (pair kernel): ALU-bound (FP64 VALU)
+    roof = None
+    if FLOPS_PER_PAIR is not None:
+        ach = FLOPS_PER_PAIR * pairs / (pair_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VALU_TFLOPS, 4),
+                "traffic": None, "kernel": "pair_kernel<double,4,true>",
+                "kernel_ms": round(pair_ms, 4), "flops_per_pair": FLOPS_PER_PAIR}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "kernel": "pair_kernel<double,4,true>",
+                "kernel_ms": round(pair_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        m = min(args.cpu_obs, n)
+        print(f"[bench] cpu baseline: oracle E-step on {m} observations", file=sys.stderr, flush=True)
+        tc0 = time.perf_counter()
+        oracle.estep(c["y"][:m], c["init"], c["u"], want=())
+        tc = time.perf_counter() - tc0
+        cpu = {"value": round(m * g / tc, 3), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} observations of the workload ({m * g} pairs), full N={N}, "
+                         f"E-step incl. tau and partial sums, single thread, {tc:.1f} s"}
+
+    line = {
+        "metric": "E-step (obs x comp) evals/sec at stated tol; FP32/surrogate vs FP64 QMC speedup",
+        "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": n, "p": p, "q": q, "g": g, "n_qmc": N,
+                   "step": "one EM iteration (E-step + M-step)", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

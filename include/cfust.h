@@ -1,0 +1,160 @@
+/*
+ * cfust.h -- C ABI of the MI355X (gfx950) library for the EM algorithm of
+ * finite mixtures of canonical fundamental skew-t (CFUST) distributions
+ * (Lee, McLachlan & Leemaqz, "Multi-Node EM Algorithm for Finite Mixture
+ * Models": section 2 eq. (1)-(4); section 3, Algorithms 2-4).
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer (HIP global memory) unless the
+ *    comment says "host".  All arrays are C row-major float64:
+ *      y[n][p]           observations
+ *      pi[g]             mixing proportions (each > 0, sum 1 within 1e-12)
+ *      mu[g][p]          locations
+ *      Sigma[g][p][p]    scale matrices (symmetric positive definite)
+ *      Delta[g][p][q]    skewness matrices
+ *      nu[g]             degrees of freedom (> 0)
+ *      u[n_qmc][q+1]     quasi-Monte Carlo points in the open unit interval;
+ *                        column 0 drives the chi-square scale, column m the
+ *                        m-th truncated-normal draw of the GHK estimator
+ *  - The caller owns every buffer.  The library allocates only its internal
+ *    workspace, stream-ordered on opts->stream, unless the caller passes one
+ *    (opts->workspace, at least cfust_workspace_size() bytes).
+ *  - Work is stream-ordered on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  Every entry point waits for its own work before returning, so
+ *    that it can report errors found on the device.
+ *  - Functions return CFUST_OK (0) or an error code; they never throw.
+ *  - Limits: 1 <= p <= 32, 1 <= q <= 8, 1 <= g <= 16, n_qmc >= 1, n >= 0.
+ *
+ * Sufficient statistics ("partial sums" of Algorithm 2) are stats[g][S] with
+ * S = cfust_stats_size(p, q) = 3 + p + q + p q + p(p+1)/2 + q(q+1)/2, per
+ * component, centred at the component's current mu:
+ *   s1 | s2 | s3[p] | s4[q] | s5[q(q+1)/2] | s6[p][q] | s7[p(p+1)/2] | s8
+ *   s1 = sum_j tau_ij              s2 = sum_j tau_ij e2_ij
+ *   s3 = sum_j tau_ij e2_ij r_ij   s4 = sum_j tau_ij e3_ij
+ *   s5 = sum_j tau_ij e4_ij        s6 = sum_j tau_ij r_ij e3_ij^T
+ *   s7 = sum_j tau_ij e2_ij r_ij r_ij^T   s8 = sum_j tau_ij (e1_ij - e2_ij)
+ * with r_ij = y_j - mu_i; symmetric matrices are packed as their upper
+ * triangle, row by row.
+ */
+#ifndef CFUST_H
+#define CFUST_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFUST_OK 0
+#define CFUST_EINVAL 1      /* bad size, NULL pointer, nu <= 0, pi off the simplex */
+#define CFUST_ENOTPD 2      /* a Cholesky factorisation failed (bad_component set) */
+#define CFUST_ENONFINITE 3  /* NaN or Inf in an input or a statistic */
+#define CFUST_EHIP 4        /* a HIP runtime call failed */
+#define CFUST_ENOMEM 5      /* workspace too small or allocation failed */
+
+#define CFUST_FP64 0        /* GHK integrand in float64 */
+#define CFUST_FP32 1        /* GHK integrand in float32 with compensated sums;
+                               everything else stays float64 */
+
+#define CFUST_NU_OSL 0      /* nu update with the one-step-late E[log W | y] */
+#define CFUST_NU_FIXED 2    /* nu held fixed */
+
+typedef struct cfust_opts {
+  int precision;          /* CFUST_FP64 or CFUST_FP32 */
+  int nu_mode;            /* CFUST_NU_OSL or CFUST_NU_FIXED */
+  int fix_delta_zero;     /* nonzero: Delta held at 0 (t-mixture special case) */
+  int max_iter;           /* cfust_em_fit: maximum number of M-steps */
+  double tol;             /* cfust_em_fit: Aitken tolerance on |l_inf - l| */
+  double nu_lo, nu_hi;    /* bracket of the nu root (defaults 1 and 200) */
+  void* stream;           /* hipStream_t */
+  void* workspace;        /* optional device workspace */
+  size_t workspace_bytes;
+  double* prof_ms;        /* optional host [CFUST_PROF_SLOTS]: HIP-event times (ms) of
+                             the library's kernels on `stream` are ADDED here:
+                             [0] precompute + chi tables, [1] pair kernel (the two
+                             GHK integrals), [2] responsibilities + partial sums,
+                             [3] M-step */
+} cfust_opts;
+
+#define CFUST_PROF_SLOTS 4
+
+/* Outputs of cfust_estep.  Optional per-pair arrays may be NULL. */
+typedef struct cfust_estep_out {
+  double* tau;    /* [n][g]  posterior membership, eq. (4) (optional) */
+  double* logf;   /* [n][g]  log(pi_i f_i(y_j)), eq. (2) (optional) */
+  double* e1;     /* [n][g]  E[log W | y_j, component i] (one-step-late form) (optional) */
+  double* e2;     /* [n][g]  E[W | ...] (optional) */
+  double* e3;     /* [n][g][q]    E[W U | ...] (optional) */
+  double* e4;     /* [n][g][q][q] E[W U U^T | ...] (optional) */
+  double* stats;  /* [g][S]  partial sums (required) */
+  double* loglik; /* [1]     log-likelihood eq. (3) at the input parameters (required) */
+  int bad_component; /* host: component that failed, or -1 */
+} cfust_estep_out;
+
+/* Fills *opts with the defaults (FP64, OSL, max_iter 100, tol 1e-6, nu in [1,200]). */
+void cfust_default_opts(cfust_opts* opts);
+
+/* Number of statistics per component, S above. */
+int cfust_stats_size(int p, int q);
+
+/* Bytes of device workspace the entry points need for this problem size. */
+int cfust_workspace_size(int64_t n, int p, int q, int g, int n_qmc, int precision,
+                         size_t* bytes);
+
+/* One E-step at Psi = (pi, mu, Sigma, Delta, nu) (section 3.2, Algorithm 2):
+ * for every (observation, component) pair the CFUST log density (eq. (2))
+ * with the q-variate t CDF T_q estimated by GHK over the points u, the
+ * conditional expectations e1..e4 of the latent gamma and truncated-normal
+ * variables (section 2), the posterior membership tau (eq. (4)), the
+ * log-likelihood (eq. (3)) and the partial sums s1..s8. */
+int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                const double* mu, const double* Sigma, const double* Delta, const double* nu,
+                const double* u, int n_qmc, const cfust_opts* opts, cfust_estep_out* out);
+
+/* One M-step from the partial sums (section 3.3, Algorithm 3): conditional
+ * maximisation in the order mu (with the old Delta), Delta, Sigma, then nu
+ * (root of 1 + log(nu/2) - psi(nu/2) + s8/s1 = 0 in [nu_lo, nu_hi], clipped)
+ * and pi = s1 / n.  Outputs may alias the old parameters.
+ * bad_component: host pointer or NULL. */
+int cfust_mstep(const double* stats, int64_t n, int p, int q, int g, const double* mu_old,
+                const double* Delta_old, const double* nu_old, const cfust_opts* opts,
+                double* pi, double* mu, double* Sigma, double* Delta, double* nu,
+                int* bad_component);
+
+/* Log-likelihood eq. (3) at Psi (integral T_q of eq. (2) only).
+ * loglik: device [1]; logf: device [n][g] or NULL. */
+int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                 const double* mu, const double* Sigma, const double* Delta, const double* nu,
+                 const double* u, int n_qmc, const cfust_opts* opts, double* loglik,
+                 double* logf);
+
+/* EM fit (Algorithms 2-4).  pi, mu, Sigma, Delta, nu hold Psi^(0) on entry
+ * and the estimate on return.  Iteration t evaluates l^(t) at Psi^(t); for
+ * t >= 2 it stops when the Aitken limit l_inf = l^(t-1) +
+ * (l^(t) - l^(t-1)) / (1 - a), a = (l^(t) - l^(t-1)) / (l^(t-1) - l^(t-2)),
+ * is within opts->tol of l^(t); otherwise the M-step gives Psi^(t+1).  At
+ * most opts->max_iter M-steps.  loglik_trace: host [max_iter + 1], receives
+ * l^(0..*n_iter).  n_iter, bad_component: host. */
+int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, double* mu,
+                 double* Sigma, double* Delta, double* nu, const double* u, int n_qmc,
+                 const cfust_opts* opts, double* loglik_trace, int* n_iter,
+                 int* bad_component);
+
+/* Aitken-accelerated limit l_inf from l^(t-2), l^(t-1), l^(t) (Algorithm 4,
+ * read with the denominator 1 - a). Host scalars. */
+double cfust_aitken_linf(double l0, double l1, double l2);
+
+/* Diagnostic: evaluates a device special function elementwise on x[n]
+ * (device), writing out[n] (device).  fn: 0 Phi, 1 log Phi, 2 Phi^-1,
+ * 3 Phi^-1 from log p, 4 chi-square quantile at (x, x2 = dof), 5 digamma,
+ * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32.  x2 may be NULL unless
+ * fn is 4. */
+int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
+                       void* stream);
+
+const char* cfust_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,914 @@
+// HIP kernels of the CFUST mixture E-step / M-step for CDNA4 (gfx950).
+//
+// Data path of one E-step (section 3.2, Algorithm 2, one wave per pair):
+//   precompute_kernel  per component: Omega = Sigma + Delta Delta^T, its
+//                      Cholesky factor, B = Omega^-1 Delta, Lambda, R and its
+//                      Cholesky factor, the log normaliser (eq. (2))
+//   points_kernel      transposes the QMC points into column tables
+//   chi_kernel         chi scale tables s = sqrt(chi2^-1(u_0)/dof) for the
+//                      two integrals of every component
+//   pair_kernel        one 64-lane wave per (observation, component) pair:
+//                      lanes split the QMC points of both GHK integrals,
+//                      wave reductions, then the pair's conditional
+//                      expectations (eq. (2)-(4) and the hidden-variable model)
+//   stats_kernel       responsibilities and the eight partial sums per block
+//   reduce_kernel      fixed-order sum of the block partials
+// and of one M-step (section 3.3, Algorithm 3): mstep_kernel, one lane per
+// component.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cfust_math.hpp"
+
+namespace cfust {
+
+constexpr int kMaxP = 32;
+constexpr int kMaxQ = 8;
+constexpr int kMaxG = 16;
+
+enum Status : int {
+  kOk = 0,
+  kEInval = 1,
+  kENotPD = 2,
+  kENonFinite = 3,
+};
+
+// Layout of one component's precomputed block (doubles).
+struct CompLayout {
+  int kappa, nu, psi_a, L, B, D, Dinv, C, stride;
+  __host__ __device__ CompLayout(int p, int q) {
+    kappa = 0;
+    nu = 1;
+    psi_a = 2;
+    L = 4;
+    B = L + p * p;
+    D = B + p * q;
+    Dinv = D + q;
+    C = Dinv + q;
+    stride = (C + q * q + 3) & ~3;
+  }
+};
+
+// Layout of one component's sufficient statistics (doubles):
+// s1 | s2 | s3[p] | s4[q] | s5[q(q+1)/2] | s6[p][q] | s7[p(p+1)/2] | s8,
+// symmetric matrices as upper triangles packed row by row.
+struct StatLayout {
+  int s1, s2, s3, s4, s5, s6, s7, s8, S;
+  __host__ __device__ StatLayout(int p, int q) {
+    s1 = 0;
+    s2 = 1;
+    s3 = 2;
+    s4 = s3 + p;
+    s5 = s4 + q;
+    s6 = s5 + q * (q + 1) / 2;
+    s7 = s6 + p * q;
+    s8 = s7 + p * (p + 1) / 2;
+    S = s8 + 1;
+  }
+};
+
+// Per-pair record written by pair_kernel (doubles):
+// log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[q] | e4[q(q+1)/2]
+__host__ __device__ inline int pair_width(int q) { return 3 + q + q * (q + 1) / 2; }
+
+__host__ __device__ inline int tri_index(int a, int b, int m) {
+  // a <= b
+  return a * m - a * (a - 1) / 2 + (b - a);
+}
+
+__device__ __forceinline__ void set_status(int* status, int code, int comp) {
+  // every writer of a failing call writes a non-zero code; which one lands is
+  // immaterial, the host reports any of them
+  status[0] = code;
+  status[1] = comp;
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// per-component precompute (eq. (2)): one lane per component
+// ---------------------------------------------------------------------------
+__global__ void precompute_kernel(int p, int q, int g, const double* __restrict__ pi,
+                                  const double* __restrict__ Sigma,
+                                  const double* __restrict__ Delta, const double* __restrict__ mu,
+                                  const double* __restrict__ nu, double* __restrict__ comp,
+                                  int* status) {
+  const int i = threadIdx.x;
+  CompLayout cl(p, q);
+  if (i == 0) {
+    double s = 0.0;
+    for (int k = 0; k < g; ++k) s += pi[k];
+    if (!(fabs(s - 1.0) <= 1e-12)) set_status(status, kEInval, -1);
+  }
+  if (i >= g) return;
+  const double v = nu[i];
+  const double w = pi[i];
+  if (!isfinite(v) || !isfinite(w)) {
+    set_status(status, kENonFinite, i);
+    return;
+  }
+  if (!(v > 0.0) || !(w > 0.0)) {
+    set_status(status, kEInval, i);
+    return;
+  }
+  const double* Sg = Sigma + (size_t)i * p * p;
+  const double* Dl = Delta + (size_t)i * p * q;
+  for (int a = 0; a < p; ++a)
+    if (!isfinite(mu[i * p + a])) {
+      set_status(status, kENonFinite, i);
+      return;
+    }
+  for (int a = 0; a < p * p; ++a)
+    if (!isfinite(Sg[a])) {
+      set_status(status, kENonFinite, i);
+      return;
+    }
+  for (int a = 0; a < p * q; ++a)
+    if (!isfinite(Dl[a])) {
+      set_status(status, kENonFinite, i);
+      return;
+    }
+  double* out = comp + (size_t)i * cl.stride;
+  double* L = out + cl.L;
+  // Omega = Sigma + Delta Delta^T, Cholesky in place (lower, row-major)
+  for (int a = 0; a < p; ++a)
+    for (int b = 0; b <= a; ++b) {
+      double t = Sg[a * p + b];
+      for (int k = 0; k < q; ++k) t = fma(Dl[a * q + k], Dl[b * q + k], t);
+      L[a * p + b] = t;
+    }
+  for (int j = 0; j < p; ++j) {
+    double s = L[j * p + j];
+    for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
+    if (!(s > 0.0)) {
+      set_status(status, kENotPD, i);
+      return;
+    }
+    double ljj = sqrt(s);
+    L[j * p + j] = ljj;
+    for (int r = j + 1; r < p; ++r) {
+      double t = L[r * p + j];
+      for (int k = 0; k < j; ++k) t -= L[r * p + k] * L[j * p + k];
+      L[r * p + j] = t / ljj;
+    }
+    for (int c = j + 1; c < p; ++c) L[j * p + c] = 0.0;
+  }
+  double logdet = 0.0;
+  for (int a = 0; a < p; ++a) logdet += log(L[a * p + a]);
+  logdet *= 2.0;
+  // B = Omega^{-1} Delta by two triangular solves per column
+  double* B = out + cl.B;
+  for (int k = 0; k < q; ++k) {
+    double tmp[kMaxP];
+    for (int a = 0; a < p; ++a) {
+      double t = Dl[a * q + k];
+      for (int b = 0; b < a; ++b) t -= L[a * p + b] * tmp[b];
+      tmp[a] = t / L[a * p + a];
+    }
+    for (int a = p - 1; a >= 0; --a) {
+      double t = tmp[a];
+      for (int b = a + 1; b < p; ++b) t -= L[b * p + a] * B[b * q + k];
+      B[a * q + k] = t / L[a * p + a];
+    }
+  }
+  // Lambda = I - Delta^T B (symmetrised), D = sqrt(diag), R = D^-1 Lambda D^-1
+  double lam[kMaxQ * kMaxQ];
+  for (int k = 0; k < q; ++k)
+    for (int l = 0; l < q; ++l) {
+      double t = (k == l) ? 1.0 : 0.0;
+      for (int a = 0; a < p; ++a) t -= Dl[a * q + k] * B[a * q + l];
+      lam[k * q + l] = t;
+    }
+  for (int k = 0; k < q; ++k)
+    for (int l = 0; l < k; ++l) {
+      double t = 0.5 * (lam[k * q + l] + lam[l * q + k]);
+      lam[k * q + l] = t;
+      lam[l * q + k] = t;
+    }
+  double* D = out + cl.D;
+  double* Dinv = out + cl.Dinv;
+  for (int k = 0; k < q; ++k) {
+    if (!(lam[k * q + k] > 0.0)) {
+      set_status(status, kENotPD, i);
+      return;
+    }
+    D[k] = sqrt(lam[k * q + k]);
+    Dinv[k] = 1.0 / D[k];
+  }
+  double* C = out + cl.C;
+  for (int k = 0; k < q; ++k)
+    for (int l = 0; l < q; ++l) C[k * q + l] = (l <= k) ? lam[k * q + l] / (D[k] * D[l]) : 0.0;
+  for (int j = 0; j < q; ++j) {
+    double s = C[j * q + j];
+    for (int k = 0; k < j; ++k) s -= C[j * q + k] * C[j * q + k];
+    if (!(s > 0.0)) {
+      set_status(status, kENotPD, i);
+      return;
+    }
+    double cjj = sqrt(s);
+    C[j * q + j] = cjj;
+    for (int r = j + 1; r < q; ++r) {
+      double t = C[r * q + j];
+      for (int k = 0; k < j; ++k) t -= C[r * q + k] * C[j * q + k];
+      C[r * q + j] = t / cjj;
+    }
+  }
+  const double a_ = 0.5 * (v + p);
+  out[cl.kappa] = log(w) + q * kLn2 + lgamma(a_) - lgamma(0.5 * v) - 0.5 * p * (log(v) + kLogPi) -
+                  0.5 * logdet;
+  out[cl.nu] = v;
+  out[cl.psi_a] = digamma_(a_);
+}
+
+// ---------------------------------------------------------------------------
+// QMC point columns: uT[m][k] = u[k][m], ubT[m][k] = 1 - u[k][m] (exact)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void points_kernel(const double* __restrict__ u, int N, int q1, T* __restrict__ uT,
+                              T* __restrict__ ubT, int* status) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)N * q1) return;
+  int k = (int)(t / q1);
+  int m = (int)(t - (int64_t)k * q1);
+  double v = u[t];
+  if (!(v > 0.0 && v < 1.0)) set_status(status, kEInval, -1);
+  uT[(size_t)m * N + k] = (T)v;
+  ubT[(size_t)m * N + k] = (T)(1.0 - v);
+}
+
+// ---------------------------------------------------------------------------
+// chi scale tables: s[i][k] for dof nu_i + p (integral A) and nu_i + p + 2
+// (integral B), with 1/s for integral B.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void chi_kernel(const double* __restrict__ comp, int comp_stride, int nu_off, int p,
+                           int g, const double* __restrict__ u, int N, int q1,
+                           T* __restrict__ sA, T* __restrict__ sB, T* __restrict__ rsB,
+                           const int* __restrict__ status) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)2 * g * N) return;
+  if (status[0] != kOk) return;
+  int which = (int)(t / ((int64_t)g * N));
+  int rem = (int)(t - (int64_t)which * g * N);
+  int i = rem / N;
+  int k = rem - i * N;
+  double v = comp[(size_t)i * comp_stride + nu_off];
+  double dof = v + p + (which ? 2.0 : 0.0);
+  double s = sqrt(chi2_quantile(u[(size_t)k * q1], dof) / dof);
+  if (which == 0) {
+    sA[(size_t)i * N + k] = (T)s;
+  } else {
+    sB[(size_t)i * N + k] = (T)s;
+    rsB[(size_t)i * N + k] = (T)(1.0 / s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// accumulators of GHK weights carried with a per-lane power-of-two reference
+// ---------------------------------------------------------------------------
+// FP64: plain sums.  FP32: Neumaier-compensated sums.
+template <typename T>
+struct Acc;
+
+template <>
+struct Acc<double> {
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(double x) { s += x; }
+  __device__ __forceinline__ void scale(double f) { s *= f; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+
+template <>
+struct Acc<float> {
+  float s, c;
+  __device__ __forceinline__ void zero() {
+    s = 0.0f;
+    c = 0.0f;
+  }
+  __device__ __forceinline__ void add(float x) {
+    float t = s + x;
+    float big = fabsf(s) >= fabsf(x) ? s : x;
+    float small = fabsf(s) >= fabsf(x) ? x : s;
+    c += (big - t) + small;
+    s = t;
+  }
+  __device__ __forceinline__ void scale(float f) {
+    s *= f;
+    c *= f;
+  }
+  __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+};
+
+// ---------------------------------------------------------------------------
+// pair kernel: one wave per (observation j, component i)
+// ---------------------------------------------------------------------------
+template <typename T, int Q, bool MOM>
+__global__ __launch_bounds__(256) void pair_kernel(
+    const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
+    const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
+    const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
+    double* __restrict__ pairbuf, int W, int* status) {
+  constexpr int NT = Q * (Q + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
+  if (pair >= n * g) return;
+  if (status[0] != kOk) return;
+  const int64_t j = pair / g;
+  const int i = (int)(pair - j * g);
+  const CompLayout cl(p, Q);
+  const double* cp = comp + (size_t)i * cl.stride;
+  const double v = cp[cl.nu];
+
+  // ---- a4: Mahalanobis distance and skew projection (eq. (2)) ----
+  double r[kMaxP];
+  bool finite_ok = true;
+  for (int a = 0; a < p; ++a) {
+    double ya = y[j * p + a];
+    finite_ok = finite_ok && isfinite(ya);
+    r[a] = ya - mu[i * p + a];
+  }
+  if (!finite_ok) {
+    if (lane == 0) set_status(status, kENonFinite, -1);
+    return;
+  }
+  double d = 0.0;
+  {
+    double z[kMaxP];
+    const double* L = cp + cl.L;
+    for (int a = 0; a < p; ++a) {
+      double t = r[a];
+      for (int b = 0; b < a; ++b) t -= L[a * p + b] * z[b];
+      z[a] = t / L[a * p + a];
+      d += z[a] * z[a];
+    }
+  }
+  double c[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double t = 0.0;
+    for (int a = 0; a < p; ++a) t += cp[cl.B + a * Q + k] * r[a];
+    c[k] = t;
+  }
+  const double fa = sqrt((v + p) / (v + d));
+  const double fb = sqrt((v + p + 2.0) / (v + d));
+  // scaled bounds: ub_m = s * ht_m - sum_{l<m} Ct_ml eps_l, with
+  // ht_m = h_m / C_mm and Ct_ml = C_ml / C_mm
+  T htA[Q], htB[Q], Ct[Q][Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    double cmm = cp[cl.C + m * Q + m];
+    double hbase = c[m] * cp[cl.Dinv + m];
+    htA[m] = (T)(hbase * fa / cmm);
+    htB[m] = (T)(hbase * fb / cmm);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(cp[cl.C + m * Q + l] / cmm) : T(0);
+  }
+
+  // ---- a5 / a6: the two GHK integrals over this lane's points ----
+  const T* sAi = sA + (size_t)i * N;
+  const T* sBi = sB + (size_t)i * N;
+  const T* rsBi = rsB + (size_t)i * N;
+  Acc<T> accA;
+  accA.zero();
+  int refA = -(1 << 29);
+  Acc<T> b0, b1[Q], b2[NT];
+  b0.zero();
+#pragma unroll
+  for (int m = 0; m < Q; ++m) b1[m].zero();
+#pragma unroll
+  for (int m = 0; m < NT; ++m) b2[m].zero();
+  int refB = -(1 << 29);
+
+#pragma unroll 1
+  for (int k = lane; k < N; k += 64) {
+    T uu[Q], ub_[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      uu[m] = uT[(size_t)(m + 1) * N + k];
+      ub_[m] = ubT[(size_t)(m + 1) * N + k];
+    }
+    // integral A: dof nu+p, draws for coordinates 1..Q-1
+    {
+      const T s = sAi[k];
+      T eps[Q];
+      T prod = T(1);
+      int ex = 0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        T bnd = s * htA[m];
+#pragma unroll
+        for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
+        Coord<T> cc = norm_coord<T>(bnd);
+        prod *= cc.mant;
+        ex += cc.ex;
+        if (m < Q - 1) eps[m] = norm_draw<T>(uu[m], ub_[m], cc);
+      }
+      if (ex > refA + Prec<T>::kRescale) {
+        accA.scale(Prec<T>::ldexp_(T(1), max(refA - ex, -1000)));
+        refA = ex;
+      }
+      accA.add(Prec<T>::ldexp_(prod, ex - refA));
+    }
+    if (MOM) {
+      // integral B: dof nu+p+2, draws for all Q coordinates, moments of eps/s
+      const T s = sBi[k];
+      const T rs = rsBi[k];
+      T eps[Q];
+      T prod = T(1);
+      int ex = 0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        T bnd = s * htB[m];
+#pragma unroll
+        for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
+        Coord<T> cc = norm_coord<T>(bnd);
+        prod *= cc.mant;
+        ex += cc.ex;
+        eps[m] = norm_draw<T>(uu[m], ub_[m], cc);
+      }
+      if (ex > refB + Prec<T>::kRescale) {
+        T f = Prec<T>::ldexp_(T(1), max(refB - ex, -1000));
+        b0.scale(f);
+#pragma unroll
+        for (int m = 0; m < Q; ++m) b1[m].scale(f);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) b2[m].scale(f);
+        refB = ex;
+      }
+      T wgt = Prec<T>::ldexp_(prod, ex - refB);
+      T eh[Q];
+#pragma unroll
+      for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
+      b0.add(wgt);
+#pragma unroll
+      for (int m = 0; m < Q; ++m) b1[m].add(wgt * eh[m]);
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        T wa = wgt * eh[a];
+#pragma unroll
+        for (int b = a; b < Q; ++b) b2[t++].add(wa * eh[b]);
+      }
+    }
+  }
+
+  // ---- wave reductions with exponent alignment ----
+  double logTA, logTB = 0.0;
+  double m1[Q], m2[Q][Q];
+  {
+    int R = wave_max(refA);
+    double sc = ldexp(1.0, max(refA - R, -1100));
+    double S = wave_sum(accA.value() * sc);
+    logTA = log(S) + R * kLn2 - log((double)N);
+  }
+  if (MOM) {
+    int R = wave_max(refB);
+    double sc = ldexp(1.0, max(refB - R, -1100));
+    double S0 = wave_sum(b0.value() * sc);
+    double S1[Q], S2[Q][Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) S1[m] = wave_sum(b1[m].value() * sc);
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+#pragma unroll
+      for (int b = a; b < Q; ++b) {
+        double s2 = wave_sum(b2[t++].value() * sc);
+        S2[a][b] = s2;
+        S2[b][a] = s2;
+      }
+    logTB = log(S0) + R * kLn2 - log((double)N);
+    // E[V] = C S1/S0, E[V V^T] = C (S2/S0) C^T (V standardised, V <= h_B)
+    const double inv0 = 1.0 / S0;
+    double tmp[Q][Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      double t1 = 0.0;
+#pragma unroll
+      for (int l = 0; l <= a; ++l) t1 += cp[cl.C + a * Q + l] * S1[l];
+      m1[a] = t1 * inv0;
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int l = 0; l <= a; ++l) t2 += cp[cl.C + a * Q + l] * S2[l][b];
+        tmp[a][b] = t2 * inv0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int l = 0; l <= b; ++l) t2 += tmp[a][l] * cp[cl.C + b * Q + l];
+        m2[a][b] = t2;
+      }
+  }
+
+  // ---- a7: pair assembly (wave-uniform values; lane t stores entry t) ----
+  const double aa = 0.5 * (v + p);
+  const double bb = 0.5 * (v + d);
+  double out = cp[cl.kappa] - aa * log1p(d / v) + logTA;
+  if (MOM) {
+    const bool ok = isfinite(logTA) && isfinite(logTB);
+    const double e2 = ok ? (aa / bb) * exp(logTB - logTA) : 0.0;
+    const double sc = sqrt((v + d) / (v + p + 2.0));
+    double mx[Q], Ds[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      Ds[k] = sc * cp[cl.D + k];
+      mx[k] = Ds[k] * m1[k];
+    }
+    out = (lane == 1) ? e2 : out;
+    out = (lane == 2) ? (cp[cl.psi_a] - log(bb) - aa / bb) : out;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) out = (lane == 3 + k) ? (ok ? e2 * (c[k] - mx[k]) : 0.0) : out;
+    int t = 3 + Q;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+#pragma unroll
+      for (int b = a; b < Q; ++b) {
+        double exx = c[a] * c[b] - c[a] * mx[b] - mx[a] * c[b] + Ds[a] * m2[a][b] * Ds[b];
+        out = (lane == t) ? (ok ? e2 * exx : 0.0) : out;
+        ++t;
+      }
+  }
+  const int nw = MOM ? (3 + Q + NT) : 1;
+  if (lane < nw) pairbuf[pair * W + lane] = out;
+}
+
+// ---------------------------------------------------------------------------
+// a8 + a9: responsibilities, log-likelihood and the partial sums
+// (Algorithm 2).  Block b handles observations [b*per, min(n,(b+1)*per))
+// in tiles of kTile; thread t owns statistic entries t, t+256, ...
+// ---------------------------------------------------------------------------
+constexpr int kStatsPerBlock = 2048;  // statistic entries per block (256 threads x 8)
+
+__global__ __launch_bounds__(256) void stats_kernel(
+    const double* __restrict__ y, int64_t n, int p, int q, int g, const double* __restrict__ mu,
+    const double* __restrict__ pairbuf, int W, int64_t per_block, int tile, int with_stats,
+    double* __restrict__ partial, double* __restrict__ partial_ll, double* __restrict__ tau_out,
+    double* __restrict__ logf_out, double* __restrict__ e1_out, double* __restrict__ e2_out,
+    double* __restrict__ e3_out, double* __restrict__ e4_out, const int* __restrict__ status) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x;
+  const StatLayout sl(p, q);
+  const int GS = g * sl.S;
+  const int64_t j0 = (int64_t)blockIdx.x * per_block;
+  const int64_t j1 = min(n, j0 + per_block);
+  // LDS: tile records [tile][g][W], taus [tile][g], y tile [tile][p], ll [tile]
+  double* recs = sm;
+  double* taus = recs + tile * g * W;
+  double* ys = taus + tile * g;
+  double* lls = ys + tile * p;
+  constexpr int kPer = kStatsPerBlock / 256;
+  const int ebase = blockIdx.y * kStatsPerBlock;
+  double acc[kPer];
+  int kind[kPer], ia[kPer], xa[kPer], xb[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    acc[e] = 0.0;
+    int idx = ebase + tid + e * 256;
+    kind[e] = -1;
+    if (idx < GS && with_stats) {
+      int i = idx / sl.S;
+      int s = idx - i * sl.S;
+      ia[e] = i;
+      xa[e] = 0;
+      xb[e] = 0;
+      if (s == sl.s1) kind[e] = 1;
+      else if (s == sl.s2) kind[e] = 2;
+      else if (s < sl.s4) { kind[e] = 3; xa[e] = s - sl.s3; }
+      else if (s < sl.s5) { kind[e] = 4; xa[e] = s - sl.s4; }
+      else if (s < sl.s6) {
+        kind[e] = 5;
+        int t = s - sl.s5, a = 0;
+        while (t >= q - a) { t -= q - a; ++a; }
+        xa[e] = a;
+        xb[e] = a + t;
+      } else if (s < sl.s7) {
+        kind[e] = 6;
+        xa[e] = (s - sl.s6) / q;
+        xb[e] = (s - sl.s6) % q;
+      } else if (s < sl.s8) {
+        kind[e] = 7;
+        int t = s - sl.s7, a = 0;
+        while (t >= p - a) { t -= p - a; ++a; }
+        xa[e] = a;
+        xb[e] = a + t;
+      } else {
+        kind[e] = 8;
+      }
+    }
+  }
+  double ll_acc = 0.0;
+  const bool ok = status[0] == kOk;
+  const bool writer = blockIdx.y == 0;
+  for (int64_t t0 = j0; t0 < j1 && ok; t0 += tile) {
+    const int nt = (int)min((int64_t)tile, j1 - t0);
+    for (int x = tid; x < nt * g * W; x += 256) recs[x] = pairbuf[t0 * g * W + x];
+    for (int x = tid; x < nt * p; x += 256) ys[x] = y[t0 * p + x];
+    __syncthreads();
+    if (tid < nt) {
+      const double* rj = recs + tid * g * W;
+      double M = -INFINITY;
+      for (int i = 0; i < g; ++i) M = fmax(M, rj[i * W]);
+      double ssum = 0.0;
+      for (int i = 0; i < g; ++i) ssum += exp(rj[i * W] - M);
+      double lf = M + log(ssum);
+      lls[tid] = lf;
+      const int64_t jj = t0 + tid;
+      for (int i = 0; i < g; ++i) {
+        double ta = exp(rj[i * W] - lf);
+        taus[tid * g + i] = ta;
+        const int64_t ji = jj * g + i;
+        if (!writer) continue;
+        if (tau_out) tau_out[ji] = ta;
+        if (logf_out) logf_out[ji] = rj[i * W];
+        if (e2_out) e2_out[ji] = rj[i * W + 1];
+        if (e1_out) e1_out[ji] = rj[i * W + 1] + rj[i * W + 2];
+        if (e3_out)
+          for (int k = 0; k < q; ++k) e3_out[ji * q + k] = rj[i * W + 3 + k];
+        if (e4_out)
+          for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+              e4_out[(ji * q + a) * q + b] = rj[i * W + 3 + q + tri_index(min(a, b), max(a, b), q)];
+      }
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int x = 0; x < nt; ++x) ll_acc += lls[x];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      if (kind[e] < 0) continue;
+      const int i = ia[e];
+      const double* mui = mu + i * p;
+      double a_acc = acc[e];
+      for (int x = 0; x < nt; ++x) {
+        const double ta = taus[x * g + i];
+        const double* rec = recs + (x * g + i) * W;
+        const double* yx = ys + x * p;
+        double val;
+        switch (kind[e]) {
+          case 1: val = ta; break;
+          case 2: val = ta * rec[1]; break;
+          case 3: val = ta * rec[1] * (yx[xa[e]] - mui[xa[e]]); break;
+          case 4: val = ta * rec[3 + xa[e]]; break;
+          case 5: val = ta * rec[3 + q + tri_index(xa[e], xb[e], q)]; break;
+          case 6: val = ta * (yx[xa[e]] - mui[xa[e]]) * rec[3 + xb[e]]; break;
+          case 7: val = ta * rec[1] * (yx[xa[e]] - mui[xa[e]]) * (yx[xb[e]] - mui[xb[e]]); break;
+          default: val = ta * rec[2]; break;
+        }
+        a_acc += val;
+      }
+      acc[e] = a_acc;
+    }
+    __syncthreads();
+  }
+  if (with_stats) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+      if (kind[e] >= 0) partial[(size_t)blockIdx.x * GS + ebase + tid + e * 256] = acc[e];
+  }
+  if (tid == 0 && writer) partial_ll[blockIdx.x] = ll_acc;
+}
+
+// fixed-order reduction of the block partials: thread per entry
+__global__ void reduce_kernel(const double* __restrict__ partial, const double* __restrict__ partial_ll,
+                              int nb, int GS, double* __restrict__ stats, double* __restrict__ loglik,
+                              const int* __restrict__ status) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = status[0] == kOk;
+  if (e < GS && stats) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * GS + e];
+    stats[e] = ok ? s : NAN;
+  }
+  if (e == GS) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial_ll[b];
+    loglik[0] = ok ? s : NAN;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M-step (section 3.3, Algorithm 3): one lane per component.
+// CM order: mu (old Delta), Delta (new mu), Sigma, then nu and pi.
+// ---------------------------------------------------------------------------
+__device__ bool chol_small(double* A, int m) {
+  for (int j = 0; j < m; ++j) {
+    double s = A[j * m + j];
+    for (int k = 0; k < j; ++k) s -= A[j * m + k] * A[j * m + k];
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    double l = sqrt(s);
+    A[j * m + j] = l;
+    for (int r = j + 1; r < m; ++r) {
+      double t = A[r * m + j];
+      for (int k = 0; k < j; ++k) t -= A[r * m + k] * A[j * m + k];
+      A[r * m + j] = t / l;
+    }
+  }
+  return true;
+}
+
+// root of F(v) = 1 + log(v/2) - psi(v/2) + cst on [lo, hi] (F decreasing):
+// Newton steps kept inside a bisection bracket, to a relative step of 1e-13.
+__device__ double nu_root(double cst, double lo, double hi, double v0) {
+  auto F = [cst](double v) { return 1.0 + log(0.5 * v) - digamma_(0.5 * v) + cst; };
+  if (F(hi) >= 0.0) return hi;
+  if (F(lo) <= 0.0) return lo;
+  double v = fmin(fmax(v0, lo), hi);
+  for (int it = 0; it < 200; ++it) {
+    double f = F(v);
+    if (f > 0.0)
+      lo = v;
+    else
+      hi = v;
+    double df = 1.0 / v - 0.5 * trigamma_(0.5 * v);
+    double vn = v - f / df;
+    if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
+    double dv = fabs(vn - v);
+    v = vn;
+    if (dv <= 1e-13 * v || hi - lo <= 1e-15 * v) break;
+  }
+  return v;
+}
+
+__global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p, int q, int g,
+                             const double* mu_old, const double* Delta_old, const double* nu_old,
+                             int nu_fixed, int fix_delta_zero, double nu_lo, double nu_hi,
+                             double* pi, double* mu, double* Sigma, double* Delta, double* nu,
+                             double* __restrict__ pi_tmp, int* status) {
+  const int i = threadIdx.x;
+  const StatLayout sl(p, q);
+  __shared__ int fail;
+  if (i == 0) fail = 0;
+  __syncthreads();
+  double s5[kMaxQ * kMaxQ], L5[kMaxQ * kMaxQ], s6[kMaxP * kMaxQ], s7[kMaxP * kMaxP];
+  double Dn[kMaxP * kMaxQ], dmu[kMaxP], s3[kMaxP], s4[kMaxQ];
+  double Sg[kMaxP * kMaxP];
+  double s1 = 0.0, vnew = 0.0;
+  bool ok = true;
+  if (i < g) {
+    const double* st = stats + (size_t)i * sl.S;
+    for (int e = 0; e < sl.S; ++e)
+      if (!isfinite(st[e])) ok = false;
+    if (!ok) {
+      set_status(status, kENonFinite, i);
+      fail = 1;
+    }
+    s1 = st[sl.s1];
+    double s2 = st[sl.s2];
+    if (ok && (!(s1 > 0.0) || !(s2 > 0.0))) {
+      ok = false;
+      set_status(status, kENotPD, i);
+      fail = 1;
+    }
+    if (ok) {
+      for (int a = 0; a < p; ++a) s3[a] = st[sl.s3 + a];
+      for (int k = 0; k < q; ++k) s4[k] = st[sl.s4 + k];
+      for (int k = 0; k < q; ++k)
+        for (int l = 0; l < q; ++l) s5[k * q + l] = st[sl.s5 + tri_index(min(k, l), max(k, l), q)];
+      const double* Dold = Delta_old + (size_t)i * p * q;
+      for (int a = 0; a < p; ++a) {
+        double t = s3[a];
+        for (int k = 0; k < q; ++k) t -= Dold[a * q + k] * s4[k];
+        dmu[a] = t / s2;
+      }
+      for (int a = 0; a < p; ++a)
+        for (int k = 0; k < q; ++k) s6[a * q + k] = st[sl.s6 + a * q + k] - dmu[a] * s4[k];
+      for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b)
+          s7[a * p + b] = st[sl.s7 + tri_index(min(a, b), max(a, b), p)] - s3[a] * dmu[b] -
+                          dmu[a] * s3[b] + s2 * dmu[a] * dmu[b];
+      if (fix_delta_zero) {
+        for (int x = 0; x < p * q; ++x) Dn[x] = 0.0;
+      } else {
+        for (int x = 0; x < q * q; ++x) L5[x] = s5[x];
+        if (!chol_small(L5, q)) {
+          ok = false;
+          set_status(status, kENotPD, i);
+          fail = 1;
+        } else {
+          for (int a = 0; a < p; ++a) {
+            double tmp[kMaxQ];
+            for (int k = 0; k < q; ++k) {
+              double t = s6[a * q + k];
+              for (int l = 0; l < k; ++l) t -= L5[k * q + l] * tmp[l];
+              tmp[k] = t / L5[k * q + k];
+            }
+            for (int k = q - 1; k >= 0; --k) {
+              double t = tmp[k];
+              for (int l = k + 1; l < q; ++l) t -= L5[l * q + k] * Dn[a * q + l];
+              Dn[a * q + k] = t / L5[k * q + k];
+            }
+          }
+        }
+      }
+    }
+    if (ok) {
+      for (int a = 0; a < p; ++a)
+        for (int b = 0; b < p; ++b) {
+          double t = s7[a * p + b];
+          for (int k = 0; k < q; ++k) t -= Dn[a * q + k] * s6[b * q + k] + s6[a * q + k] * Dn[b * q + k];
+          for (int k = 0; k < q; ++k) {
+            double dk = 0.0;
+            for (int l = 0; l < q; ++l) dk += s5[k * q + l] * Dn[b * q + l];
+            t += Dn[a * q + k] * dk;
+          }
+          Sg[a * p + b] = t / s1;
+        }
+      for (int a = 0; a < p; ++a)
+        for (int b = 0; b < a; ++b) {
+          double t = 0.5 * (Sg[a * p + b] + Sg[b * p + a]);
+          Sg[a * p + b] = t;
+          Sg[b * p + a] = t;
+        }
+      double Lc[kMaxP * kMaxP];
+      for (int x = 0; x < p * p; ++x) Lc[x] = Sg[x];
+      if (!chol_small(Lc, p)) {
+        ok = false;
+        set_status(status, kENotPD, i);
+        fail = 1;
+      }
+    }
+    vnew = nu_old[i];
+    if (ok && !nu_fixed) vnew = nu_root(st[sl.s8] / s1, nu_lo, nu_hi, nu_old[i]);
+  }
+  __syncthreads();  // every lane has read its old parameters before any write
+  if (fail) return;
+  if (i < g) {
+    pi_tmp[i] = s1 / (double)n;
+    for (int a = 0; a < p; ++a) mu[i * p + a] = mu_old[i * p + a] + dmu[a];
+    for (int x = 0; x < p * q; ++x) Delta[(size_t)i * p * q + x] = Dn[x];
+    for (int x = 0; x < p * p; ++x) Sigma[(size_t)i * p * p + x] = Sg[x];
+    nu[i] = vnew;
+  }
+  __syncthreads();
+  if (i < g) {
+    double ps = 0.0;
+    for (int k = 0; k < g; ++k) ps += pi_tmp[k];
+    pi[i] = pi_tmp[i] / ps;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostic: the device special functions, elementwise
+// ---------------------------------------------------------------------------
+__global__ void special_kernel(int fn, const double* __restrict__ x, const double* __restrict__ x2,
+                               double* __restrict__ out, int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double a = x[t];
+  double r = 0.0;
+  switch (fn) {
+    case 0: {  // Phi
+      Coord<double> c = norm_coord<double>(a);
+      r = c.deep ? exp(c.lphi) : c.e;
+      break;
+    }
+    case 1: {  // log Phi
+      Coord<double> c = norm_coord<double>(a);
+      r = c.deep ? c.lphi : (a > 0.0 ? log1p(-c.ebar) : log(c.e));
+      break;
+    }
+    case 2: {  // Phi^{-1}(p) via the draw routine with u = p, Phi(ub) = 1
+      Coord<double> c;
+      c.e = 1.0;
+      c.ebar = 0.0;
+      c.deep = false;
+      c.lphi = 0.0;
+      r = norm_draw<double>(a, 1.0 - a, c);
+      break;
+    }
+    case 3: r = ninv_from_log(a); break;
+    case 4: r = chi2_quantile(a, x2[t]); break;
+    case 5: r = digamma_(a); break;
+    case 6: r = trigamma_(a); break;
+    case 7: {  // Phi in FP32
+      Coord<float> c = norm_coord<float>((float)a);
+      r = c.deep ? exp(c.lphi) : (double)c.e;
+      break;
+    }
+    case 8: {  // Phi^{-1} in FP32
+      Coord<float> c;
+      c.e = 1.0f;
+      c.ebar = 0.0f;
+      c.deep = false;
+      c.lphi = 0.0;
+      r = (double)norm_draw<float>((float)a, (float)(1.0 - a), c);
+      break;
+    }
+    default: r = NAN;
+  }
+  out[t] = r;
+}
+
+}  // namespace cfust

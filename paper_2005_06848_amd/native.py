@@ -1,0 +1,254 @@
+"""ctypes binding of libcfust.so (same names as the C ABI).
+
+Tensors must be float64, contiguous, on the GPU.  The functions return torch
+tensors on the same device; errors raise ``CfustError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import _build
+
+LIB_PATH = _build.LIB_PATH
+
+OK, EINVAL, ENOTPD, ENONFINITE, EHIP, ENOMEM = 0, 1, 2, 3, 4, 5
+FP64, FP32 = 0, 1
+NU_OSL, NU_FIXED = 0, 2
+
+
+class CfustError(RuntimeError):
+    def __init__(self, code, where, bad=-1):
+        msg = _lib().cfust_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code}, component {bad})")
+        self.code = code
+        self.bad = bad
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("nu_mode", ctypes.c_int),
+        ("fix_delta_zero", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("nu_lo", ctypes.c_double),
+        ("nu_hi", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("prof_ms", ctypes.c_void_p),
+    ]
+
+
+PROF_SLOTS = 4
+
+
+def prof_buffer():
+    """Host accumulator for the library's per-kernel HIP-event times (ms)."""
+    return (ctypes.c_double * PROF_SLOTS)()
+
+
+class EstepOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("tau", "logf", "e1", "e2", "e3", "e4", "stats", "loglik")] + [
+        ("bad_component", ctypes.c_int)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2005_06848_amd._build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i, i64, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        L.cfust_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.cfust_default_opts.restype = None
+        L.cfust_stats_size.argtypes = [i, i]
+        L.cfust_stats_size.restype = i
+        L.cfust_workspace_size.argtypes = [i64, i, i, i, i, i, ctypes.POINTER(sz)]
+        L.cfust_workspace_size.restype = i
+        L.cfust_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(EstepOut)]
+        L.cfust_estep.restype = i
+        L.cfust_mstep.argtypes = [P, i64, i, i, i, P, P, P, ctypes.POINTER(Opts), P, P, P, P, P,
+                                  ctypes.POINTER(i)]
+        L.cfust_mstep.restype = i
+        L.cfust_loglik.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, ctypes.POINTER(Opts), P, P]
+        L.cfust_loglik.restype = i
+        L.cfust_em_fit.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, ctypes.POINTER(Opts), P,
+                                   ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.cfust_em_fit.restype = i
+        L.cfust_aitken_linf.argtypes = [d, d, d]
+        L.cfust_aitken_linf.restype = d
+        L.cfust_eval_special.argtypes = [i, P, P, P, i64, P]
+        L.cfust_eval_special.restype = i
+        L.cfust_strerror.argtypes = [i]
+        L.cfust_strerror.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def lib():
+    return _lib()
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
+              nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None):
+    o = Opts()
+    _lib().cfust_default_opts(ctypes.byref(o))
+    o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+    o.nu_mode = {"osl": NU_OSL, "fixed": NU_FIXED}[nu_mode] if isinstance(nu_mode, str) else int(nu_mode)
+    o.fix_delta_zero = int(bool(fix_delta_zero))
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.nu_lo = float(nu_lo)
+    o.nu_hi = float(nu_hi)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if prof is not None:
+        o.prof_ms = ctypes.cast(prof, ctypes.c_void_p)
+    return o
+
+
+def stats_size(p, q):
+    return _lib().cfust_stats_size(p, q)
+
+
+def workspace_size(n, p, q, g, n_qmc, precision="fp64"):
+    b = ctypes.c_size_t(0)
+    prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+    rc = _lib().cfust_workspace_size(n, p, q, g, n_qmc, prec, ctypes.byref(b))
+    if rc:
+        raise CfustError(rc, "cfust_workspace_size")
+    return b.value
+
+
+def alloc_workspace(n, p, q, g, n_qmc, precision="fp64", device="cuda"):
+    nbytes = workspace_size(n, p, q, g, n_qmc, precision)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _params(params):
+    names = ("pi", "mu", "Sigma", "Delta", "nu")
+    ts = [_dev(params[k], k) for k in names]
+    g, p = ts[1].shape
+    q = ts[3].shape[2]
+    return ts, g, p, q
+
+
+def cfust_estep(y, params, u, want=("tau", "logf", "e1", "e2", "e3", "e4"), **opt):
+    """One E-step (section 3.2, Algorithm 2) on the GPU."""
+    y = _dev(y, "y")
+    u = _dev(u, "u")
+    (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
+    n = y.shape[0]
+    dev = y.device
+    out = {}
+    shapes = dict(tau=(n, g), logf=(n, g), e1=(n, g), e2=(n, g), e3=(n, g, q), e4=(n, g, q, q))
+    for k, shp in shapes.items():
+        out[k] = torch.empty(shp, dtype=torch.float64, device=dev) if k in want else None
+    stats = torch.empty((g, stats_size(p, q)), dtype=torch.float64, device=dev)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    eo = EstepOut(*[_ptr(out[k]) for k in shapes], _ptr(stats), _ptr(ll), -1)
+    o = make_opts(**opt)
+    rc = _lib().cfust_estep(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
+                            _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), ctypes.byref(eo))
+    if rc:
+        raise CfustError(rc, "cfust_estep", eo.bad_component)
+    res = {k: v for k, v in out.items() if v is not None}
+    res["stats"] = stats
+    res["loglik"] = ll
+    return res
+
+
+def cfust_mstep(stats, n, params_old, out=None, **opt):
+    """One M-step (section 3.3, Algorithm 3) on the GPU; returns new parameters."""
+    stats = _dev(stats, "stats")
+    (pi0, mu0, Sg0, D0, nu0), g, p, q = _params(params_old)
+    if out is None:
+        out = {k: torch.empty_like(v) for k, v in
+               dict(pi=pi0, mu=mu0, Sigma=Sg0, Delta=D0, nu=nu0).items()}
+    bad = ctypes.c_int(-1)
+    o = make_opts(**opt)
+    rc = _lib().cfust_mstep(_ptr(stats), int(n), p, q, g, _ptr(mu0), _ptr(D0), _ptr(nu0),
+                            ctypes.byref(o), _ptr(out["pi"]), _ptr(out["mu"]), _ptr(out["Sigma"]),
+                            _ptr(out["Delta"]), _ptr(out["nu"]), ctypes.byref(bad))
+    if rc:
+        raise CfustError(rc, "cfust_mstep", bad.value)
+    return out
+
+
+def cfust_loglik(y, params, u, want_logf=False, **opt):
+    """Log-likelihood eq. (3) on the GPU."""
+    y = _dev(y, "y")
+    u = _dev(u, "u")
+    (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
+    n = y.shape[0]
+    ll = torch.empty(1, dtype=torch.float64, device=y.device)
+    lf = torch.empty((n, g), dtype=torch.float64, device=y.device) if want_logf else None
+    o = make_opts(**opt)
+    rc = _lib().cfust_loglik(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
+                             _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), _ptr(ll), _ptr(lf))
+    if rc:
+        raise CfustError(rc, "cfust_loglik")
+    return (ll, lf) if want_logf else ll
+
+
+def cfust_em_fit(y, params0, u, max_iter=100, tol=1e-6, **opt):
+    """EM fit (Algorithms 2-4) on the GPU.  Returns the fitted parameters (new
+    tensors), the log-likelihood trace and the number of M-steps."""
+    y = _dev(y, "y")
+    u = _dev(u, "u")
+    par = {k: _dev(v, k).clone() for k, v in params0.items()}
+    (pi, mu, Sigma, Delta, nu), g, p, q = _params(par)
+    n = y.shape[0]
+    trace = (ctypes.c_double * (max_iter + 1))()
+    n_iter = ctypes.c_int(0)
+    bad = ctypes.c_int(-1)
+    o = make_opts(max_iter=max_iter, tol=tol, **opt)
+    rc = _lib().cfust_em_fit(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
+                             _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), trace,
+                             ctypes.byref(n_iter), ctypes.byref(bad))
+    if rc:
+        raise CfustError(rc, "cfust_em_fit", bad.value)
+    k = n_iter.value
+    par["trace"] = [trace[t] for t in range(k + 1)]
+    par["n_iter"] = k
+    return par
+
+
+def cfust_aitken_linf(l0, l1, l2):
+    return _lib().cfust_aitken_linf(float(l0), float(l1), float(l2))
+
+
+def cfust_eval_special(fn, x, x2=None):
+    x = _dev(x, "x")
+    out = torch.empty_like(x)
+    rc = _lib().cfust_eval_special(int(fn), _ptr(x), _ptr(x2), _ptr(out), x.numel(),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc:
+        raise CfustError(rc, "cfust_eval_special")
+    return out

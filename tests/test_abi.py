@@ -1,0 +1,67 @@
+"""The C-ABI library builds, loads and exports every symbol of include/cfust.h
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cfust.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfust_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_2005_06848_amd import _build
+    if not os.path.exists(_build.LIB_PATH):
+        _build.build()
+    return _build.LIB_PATH
+
+
+def test_every_declared_symbol_is_exported(libpath):
+    names = _declared()
+    assert "cfust_estep" in names and "cfust_em_fit" in names and "cfust_mstep" in names
+    assert "cfust_loglik" in names
+    L = ctypes.CDLL(libpath)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_host_only_entry_points(libpath):
+    L = ctypes.CDLL(libpath)
+    L.cfust_stats_size.restype = ctypes.c_int
+    for p, q in [(2, 2), (4, 4), (6, 6), (5, 5), (3, 1)]:
+        assert L.cfust_stats_size(p, q) == 3 + p + q + p * q + p * (p + 1) // 2 + q * (q + 1) // 2
+    L.cfust_aitken_linf.restype = ctypes.c_double
+    L.cfust_aitken_linf.argtypes = [ctypes.c_double] * 3
+    for lstar, C, r in [(-100.0, 5.0, 0.5), (-2211.3, 40.0, 0.9)]:
+        l = [lstar - C * r ** k for k in range(3)]
+        assert abs(L.cfust_aitken_linf(*l) - lstar) < 1e-9 * abs(lstar)
+    L.cfust_strerror.restype = ctypes.c_char_p
+    assert L.cfust_strerror(2) == b"matrix not positive definite"
+
+
+def test_workspace_size_and_limits(libpath):
+    from paper_2005_06848_amd import native
+    assert native.workspace_size(20000, 4, 4, 3, 4096) > 20000 * 3 * 8 * 17
+    with pytest.raises(native.CfustError):
+        native.workspace_size(10, 2, 9, 2, 64)  # q above the kernels' limit
+    with pytest.raises(native.CfustError):
+        native.workspace_size(10, 33, 2, 2, 64)  # p above the limit
+    with pytest.raises(native.CfustError):
+        native.workspace_size(10, 2, 2, 2, 0)  # no QMC points
+
+
+def test_product_path_does_not_import_oracle():
+    """The binding fails loudly without the library and never reaches the oracle."""
+    src = open(os.path.join(ROOT, "paper_2005_06848_amd", "native.py")).read()
+    assert "oracle" not in src
+    for name in os.listdir(os.path.join(ROOT, "paper_2005_06848_amd")):
+        if name.endswith(".py"):
+            text = open(os.path.join(ROOT, "paper_2005_06848_amd", name)).read()
+            assert "import oracle" not in text and "from oracle" not in text, name

@@ -1,0 +1,272 @@
+"""GPU path (HIP kernels through the C ABI) against the FP64 oracle.
+
+Bar (FP64): 1e-10 per quantity, measured as in tests/parity.py."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def gpu_params(par, dev):
+    return {k: T(v, dev) for k, v in par.items() if k in ("pi", "mu", "Sigma", "Delta", "nu")}
+
+
+def to_np(d):
+    out = {}
+    for k, v in d.items():
+        if hasattr(v, "detach"):
+            v = v.detach().cpu().numpy()
+            if k == "loglik":
+                v = float(v[0])
+        out[k] = v
+    return out
+
+
+def run_pair(dev, y, par, u, precision="fp64"):
+    from paper_2005_06848_amd import native
+    print(f"[gpu] estep n={y.shape[0]} p={y.shape[1]} q={par['Delta'].shape[2]} g={len(par['pi'])} "
+          f"N={u.shape[0]} {precision}", flush=True)
+    g = native.cfust_estep(T(y, dev), gpu_params(par, dev), T(u, dev), precision=precision)
+    return to_np(g)
+
+
+def check(err, tol=TOL):
+    bad = {k: v for k, v in err.items() if not (v <= tol)}
+    assert not bad, err
+
+
+def test_special_functions(dev):
+    from scipy import special as sp
+    from paper_2005_06848_amd import native
+    import torch
+    x = np.concatenate([np.linspace(-35, 8, 300), [-36.5, -40.0, -60.0]])
+    phi = native.cfust_eval_special(0, T(x, dev)).cpu().numpy()
+    lphi = native.cfust_eval_special(1, T(x, dev)).cpu().numpy()
+    ok = x > -37
+    rel = np.abs(phi[ok] / sp.ndtr(x[ok]) - 1)
+    assert np.all(rel <= 5e-16 * (4 + x[ok] ** 2)), rel.max()
+    np.testing.assert_allclose(lphi, sp.log_ndtr(x), rtol=1e-14)
+    p = np.concatenate([np.logspace(-300, -1, 80), np.linspace(0.02, 0.98, 49)])
+    w = native.cfust_eval_special(2, T(p, dev)).cpu().numpy()
+    np.testing.assert_allclose(w, sp.ndtri(p), rtol=2e-14, atol=2e-15)
+    lp = np.array([-800.0, -2000.0, -1e5])
+    wl = native.cfust_eval_special(3, T(lp, dev)).cpu().numpy()
+    np.testing.assert_allclose(sp.log_ndtr(wl), lp, rtol=1e-13)
+    uu = np.array([0.5 / 2 ** 30, 1e-6, 0.3, 0.5, 0.77, 1 - 0.5 / 2 ** 30])
+    for dof in [5.0, 9.3, 14.0, 30.0]:
+        q = native.cfust_eval_special(4, T(uu, dev), T(np.full(uu.size, dof), dev)).cpu().numpy()
+        ref = np.where(uu <= 0.5, 2 * sp.gammaincinv(dof / 2, uu), 2 * sp.gammainccinv(dof / 2, 1 - uu))
+        np.testing.assert_allclose(q, ref, rtol=1e-13)
+    xs = np.array([0.3, 1.0, 2.5, 7.9, 8.0, 30.0, 101.0])
+    np.testing.assert_allclose(native.cfust_eval_special(5, T(xs, dev)).cpu().numpy(), sp.digamma(xs), rtol=1e-14)
+    np.testing.assert_allclose(native.cfust_eval_special(6, T(xs, dev)).cpu().numpy(), sp.polygamma(1, xs), rtol=1e-11)
+
+
+def test_estep_config1(dev, orc):
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(1)
+    ref = orc.estep(c["y"], c["init"], c["u"])
+    gpu = run_pair(dev, c["y"], c["init"], c["u"])
+    err = __import__("parity").estep_errors(gpu, ref, c["p"], c["q"])
+    print(err)
+    check(err)
+
+
+SHAPES = [  # n, p, q, g, N : tiles, ragged tails, N below and above one wave
+    (1, 1, 1, 1, 64), (63, 2, 1, 2, 100), (64, 3, 3, 1, 63), (65, 2, 2, 3, 1),
+    (130, 5, 4, 2, 200), (37, 6, 6, 3, 129), (20, 4, 5, 4, 256), (17, 3, 2, 6, 77),
+    (9, 7, 7, 2, 65), (5, 8, 8, 2, 70), (40, 1, 3, 2, 128),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_estep_shapes(dev, orc, shape):
+    from paper_2005_06848_amd import inputs
+    n, p, q, g, N = shape
+    c = inputs.random_case(100 + sum(shape), n, p, q, g, N)
+    ref = orc.estep(c["y"], c["params"], c["u"])
+    gpu = run_pair(dev, c["y"], c["params"], c["u"])
+    err = __import__("parity").estep_errors(gpu, ref, p, q)
+    check(err)
+
+
+def test_estep_config2_reduced(dev, orc):
+    """The config-2 recipe (p=q=4, g=3, N=4096) on its first 160 observations."""
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(2)
+    y = c["y"][:160]
+    ref = orc.estep(y, c["init"], c["u"])
+    gpu = run_pair(dev, y, c["init"], c["u"])
+    err = __import__("parity").estep_errors(gpu, ref, 4, 4)
+    print(err)
+    check(err)
+
+
+def test_estep_config2_full_sampled(dev, orc):
+    """Full config 2 (n=20000) in the benchmark's launch configuration: sampled
+    pairs against the oracle; the statistics and log-likelihood against the
+    tau-weighted sums of the GPU's own per-pair outputs."""
+    from paper_2005_06848_amd import inputs
+    import parity
+    c = inputs.config(2)
+    gpu = run_pair(dev, c["y"], c["init"], c["u"])
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(c["n"], size=24, replace=False))
+    ref = orc.estep(c["y"][idx], c["init"], c["u"])
+    sub = {k: gpu[k][idx] for k in ("tau", "logf", "e1", "e2", "e3", "e4")}
+    # tau of a sampled observation depends only on its own pairs
+    sub["stats"] = ref["stats"]
+    sub["loglik"] = ref["loglik"]
+    err = parity.estep_errors(sub, ref, 4, 4)
+    check(err)
+    # property at full size: stats = tau-weighted sums of the pair outputs
+    y, mu = c["y"], c["init"]["mu"]
+    tau, e2 = gpu["tau"], gpu["e2"]
+    for i in range(3):
+        r = y - mu[i]
+        t = tau[:, i]
+        assert gpu["stats"][i, 0] == pytest.approx(t.sum(), rel=1e-12)
+        assert gpu["stats"][i, 1] == pytest.approx((t * e2[:, i]).sum(), rel=1e-12)
+        np.testing.assert_allclose(gpu["stats"][i, 2:6], (t * e2[:, i]) @ r, rtol=1e-11, atol=1e-9)
+        np.testing.assert_allclose(gpu["stats"][i, 6:10], t @ gpu["e3"][:, i], rtol=1e-11)
+    lse = np.logaddexp.reduce(gpu["logf"], axis=1)
+    assert gpu["loglik"] == pytest.approx(lse.sum(), rel=1e-12)
+    np.testing.assert_allclose(gpu["tau"].sum(1), 1.0, rtol=1e-13)
+
+
+def test_loglik_and_mstep(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.random_case(7, 300, 3, 3, 3, 512)
+    ll_gpu, lf_gpu = native.cfust_loglik(T(c["y"], dev), gpu_params(c["params"], dev), T(c["u"], dev),
+                                         want_logf=True)
+    ll_ref, lf_ref = orc.loglik(c["y"], c["params"], c["u"], want_logf=True)
+    assert float(ll_gpu.cpu()[0]) == pytest.approx(ll_ref, rel=TOL)
+    assert np.max(np.abs(lf_gpu.cpu().numpy() - lf_ref)) < TOL
+    ref = orc.estep(c["y"], c["params"], c["u"])
+    new_ref = orc.mstep(ref["stats"], 300, c["params"])
+    new_gpu = native.cfust_mstep(T(ref["stats"], dev), 300, gpu_params(c["params"], dev))
+    err = parity.params_rel_err({k: v.cpu().numpy() for k, v in new_gpu.items()}, new_ref)
+    assert max(err.values()) < 1e-12, err
+    for mode, kw in [("fixed", dict(nu_mode=orc.NU_FIXED)), ("d0", dict(fix_delta_zero=True))]:
+        r = orc.mstep(ref["stats"], 300, c["params"], **kw)
+        gkw = dict(nu_mode="fixed") if mode == "fixed" else dict(fix_delta_zero=True)
+        gg = native.cfust_mstep(T(ref["stats"], dev), 300, gpu_params(c["params"], dev), **gkw)
+        err = parity.params_rel_err({k: v.cpu().numpy() for k, v in gg.items()}, r)
+        assert max(err.values()) < 1e-12, (mode, err)
+
+
+def test_em_fit_config1(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.config(1)
+    ref = orc.em_fit(c["y"], c["init"], c["u"], max_iter=10, tol=0.0)
+    print("[gpu] em_fit config 1", flush=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), gpu_params(c["init"], dev), T(c["u"], dev),
+                              max_iter=10, tol=0.0)
+    assert fit["n_iter"] == ref["n_iter"] == 10
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=TOL)
+    err = parity.params_rel_err({k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")}, ref)
+    assert max(err.values()) < 1e-9, err
+    # same MAP labels (the paper's "same final clustering")
+    fr = {k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    a = orc.estep(c["y"], fr, c["u"])["tau"].argmax(1)
+    b = orc.estep(c["y"], ref, c["u"])["tau"].argmax(1)
+    assert np.array_equal(a, b)
+
+
+def test_em_fit_stops_like_oracle(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.random_case(21, 400, 2, 2, 2, 256)
+    ref = orc.em_fit(c["y"], c["params"], c["u"], max_iter=60, tol=1e-3)
+    fit = native.cfust_em_fit(T(c["y"], dev), gpu_params(c["params"], dev), T(c["u"], dev),
+                              max_iter=60, tol=1e-3)
+    assert fit["n_iter"] == ref["n_iter"]
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-9)
+
+
+def test_delta_zero_fit(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.random_case(22, 300, 3, 2, 2, 256)
+    par = {k: np.array(v) for k, v in c["params"].items()}
+    par["Delta"][:] = 0.0
+    ref = orc.em_fit(c["y"], par, c["u"], max_iter=5, tol=0.0, fix_delta_zero=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), gpu_params(par, dev), T(c["u"], dev), max_iter=5,
+                              tol=0.0, fix_delta_zero=True)
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-12)
+    np.testing.assert_allclose(fit["nu"].cpu().numpy(), ref["nu"], rtol=1e-10)
+
+
+def test_edge_cases(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import torch
+    # empty input
+    c = inputs.random_case(31, 0, 2, 2, 2, 64)
+    g = native.cfust_estep(torch.empty((0, 2), dtype=torch.float64, device=dev),
+                           gpu_params(c["params"], dev), T(c["u"], dev))
+    assert float(g["loglik"].cpu()[0]) == 0.0
+    assert torch.all(g["stats"] == 0)
+    # deep tail observation: finite and equal to the oracle
+    c = inputs.random_case(15, 5, 2, 2, 2, 256)
+    y = c["y"].copy()
+    y[0] = c["params"]["mu"][0] - 4000.0 * c["params"]["Delta"][0].sum(1)
+    ref = orc.estep(y, c["params"], c["u"])
+    gpu = run_pair(dev, y, c["params"], c["u"])
+    assert np.all(np.isfinite(gpu["logf"])) and np.all(np.isfinite(gpu["tau"]))
+    err = __import__("parity").estep_errors(gpu, ref, 2, 2)
+    assert err["logf"] < 1e-9 and err["tau"] < 1e-10, err
+    # error paths
+    c = inputs.random_case(17, 10, 2, 2, 2, 64)
+    bad = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    bad["nu"][1] = -1.0
+    with pytest.raises(native.CfustError) as e:
+        native.cfust_estep(T(c["y"], dev), gpu_params(bad, dev), T(c["u"], dev))
+    assert e.value.code == native.EINVAL
+    bad = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    bad["Sigma"][1] = -np.eye(2) * 5
+    with pytest.raises(native.CfustError) as e:
+        native.cfust_estep(T(c["y"], dev), gpu_params(bad, dev), T(c["u"], dev))
+    assert e.value.code == native.ENOTPD and e.value.bad == 1
+    y = c["y"].copy()
+    y[3, 1] = np.nan
+    with pytest.raises(native.CfustError) as e:
+        native.cfust_estep(T(y, dev), gpu_params(c["params"], dev), T(c["u"], dev))
+    assert e.value.code == native.ENONFINITE
+    u = c["u"].copy()
+    u[5, 0] = 1.0
+    with pytest.raises(native.CfustError) as e:
+        native.cfust_estep(T(c["y"], dev), gpu_params(c["params"], dev), T(u, dev))
+    assert e.value.code == native.EINVAL
+    # a good call after the failures still works
+    gpu = run_pair(dev, c["y"], c["params"], c["u"])
+    assert np.all(np.isfinite(gpu["tau"]))
+
+
+def test_deterministic(dev):
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.random_case(41, 2000, 4, 4, 3, 512)
+    a = run_pair(dev, c["y"], c["params"], c["u"])
+    b = run_pair(dev, c["y"], c["params"], c["u"])
+    for k in ("tau", "e4", "stats"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["loglik"] == b["loglik"]
