@@ -28,11 +28,25 @@ WORKLOAD = "cfust-em n=20000 p=4 q=4 g=3 N=4096 fp64"
 PEAK_FP64_VALU_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic FP64 flops per (observation, component) pair of the pair kernel
-# at p=q=4, N=4096: executed FP64 VALU flops per pair counted once with
-# rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes, FMA = 2) on the
-# first correct version of the kernel, then frozen (see profiles/).
-FLOPS_PER_PAIR = None
+# Algorithmic flop model of one (observation, component) pair (both GHK
+# integrals over N points plus the pair set-up), with fixed nominal costs per
+# special-function call: Phi (erfc) 40, Phi^-1 50, scaled accumulation 20.
+#   F_A = q^2 + q + q*40 + (q-1)*50 + 20
+#   F_B = q^2 + q + q*40 + q*50 + q(q+1) + 4q + 20
+#   F_pair = N (F_A + F_B) + 2p^2 + 2pq + 40
+C_PHI, C_PHIINV, C_ACC = 40, 50, 20
+
+
+# HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
+# (KiB per dispatch, scaled by the same counters on a plain copy kernel); None
+# when the kernel has changed since the counters were taken.
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+
+def flops_per_pair(p, q, N):
+    fa = q * q + q + q * C_PHI + (q - 1) * C_PHIINV + C_ACC
+    fb = q * q + q + q * C_PHI + q * C_PHIINV + q * (q + 1) + 4 * q + C_ACC
+    return N * (fa + fb) + 2 * p * p + 2 * p * q + 40
 
 
 def parse():
@@ -112,26 +126,22 @@ def main():
           f"mstep {prof[3] / args.steps:.3f} ms", file=sys.stderr, flush=True)
 
     if args.copy_probe_mib > 0:
+        # one elementwise kernel that reads and writes exactly this many bytes
         nb = args.copy_probe_mib * (1 << 20)
         a = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         print(f"[bench] copy probe {args.copy_probe_mib} MiB done", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (pair kernel): ALU-bound (FP64 VALU)
-    roof = None
-    if FLOPS_PER_PAIR is not None:
-        ach = FLOPS_PER_PAIR * pairs / (pair_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VALU_TFLOPS, 4),
-                "traffic": None, "kernel": "pair_kernel<double,4,true>",
-                "kernel_ms": round(pair_ms, 4), "flops_per_pair": FLOPS_PER_PAIR}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": None, "traffic": None, "kernel": "pair_kernel<double,4,true>",
-                "kernel_ms": round(pair_ms, 4)}
+    fpp = flops_per_pair(p, q, N)
+    ach = fpp * pairs / (pair_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VALU_TFLOPS, 4),
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH, "kernel": f"pair_kernel<double,{q},true>",
+            "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -147,7 +147,7 @@ double cfust_aitken_linf(double l0, double l1, double l2);
 /* Diagnostic: evaluates a device special function elementwise on x[n]
  * (device), writing out[n] (device).  fn: 0 Phi, 1 log Phi, 2 Phi^-1,
  * 3 Phi^-1 from log p, 4 chi-square quantile at (x, x2 = dof), 5 digamma,
- * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32.  x2 may be NULL unless
+ * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32, 9 log, 10 sqrt.  x2 may be NULL unless
  * fn is 4. */
 int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
                        void* stream);

@@ -376,64 +376,59 @@ __global__ __launch_bounds__(256) void pair_kernel(
   const T* rsBi = rsB + (size_t)i * N;
   Acc<T> accA;
   accA.zero();
-  int refA = -(1 << 29);
+  double refA = -1.0e30;
   Acc<T> b0, b1[Q], b2[NT];
   b0.zero();
 #pragma unroll
   for (int m = 0; m < Q; ++m) b1[m].zero();
 #pragma unroll
   for (int m = 0; m < NT; ++m) b2[m].zero();
-  int refB = -(1 << 29);
+  double refB = -1.0e30;
 
+  // integral A: dof nu+p, draws for coordinates 1..Q-1
 #pragma unroll 1
   for (int k = lane; k < N; k += 64) {
-    T uu[Q], ub_[Q];
+    const T s = sAi[k];
+    T eps[Q];
+    T prod = T(1);
+    double ex = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-      uu[m] = uT[(size_t)(m + 1) * N + k];
-      ub_[m] = ubT[(size_t)(m + 1) * N + k];
-    }
-    // integral A: dof nu+p, draws for coordinates 1..Q-1
-    {
-      const T s = sAi[k];
-      T eps[Q];
-      T prod = T(1);
-      int ex = 0;
+      T bnd = s * htA[m];
 #pragma unroll
-      for (int m = 0; m < Q; ++m) {
-        T bnd = s * htA[m];
-#pragma unroll
-        for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
-        Coord<T> cc = norm_coord<T>(bnd);
-        prod *= cc.mant;
-        ex += cc.ex;
-        if (m < Q - 1) eps[m] = norm_draw<T>(uu[m], ub_[m], cc);
-      }
-      if (ex > refA + Prec<T>::kRescale) {
-        accA.scale(Prec<T>::ldexp_(T(1), max(refA - ex, -1000)));
-        refA = ex;
-      }
-      accA.add(Prec<T>::ldexp_(prod, ex - refA));
+      for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
+      PhiVal<T> cc = phi_eval(bnd);
+      prod *= cc.m;
+      ex += cc.n;
+      if (m < Q - 1) eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
     }
-    if (MOM) {
-      // integral B: dof nu+p+2, draws for all Q coordinates, moments of eps/s
+    if (ex > refA + Prec<T>::kRescale) {
+      accA.scale(Prec<T>::ldexp_(T(1), (int)fmax(refA - ex, -1000.0)));
+      refA = ex;
+    }
+    accA.add(Prec<T>::ldexp_(prod, (int)fmax(ex - refA, -1000.0)));
+  }
+  // integral B: dof nu+p+2, draws for all Q coordinates, moments of eps/s
+  if (MOM) {
+#pragma unroll 1
+    for (int k = lane; k < N; k += 64) {
       const T s = sBi[k];
       const T rs = rsBi[k];
       T eps[Q];
       T prod = T(1);
-      int ex = 0;
+      double ex = 0.0;
 #pragma unroll
       for (int m = 0; m < Q; ++m) {
         T bnd = s * htB[m];
 #pragma unroll
         for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
-        Coord<T> cc = norm_coord<T>(bnd);
-        prod *= cc.mant;
-        ex += cc.ex;
-        eps[m] = norm_draw<T>(uu[m], ub_[m], cc);
+        PhiVal<T> cc = phi_eval(bnd);
+        prod *= cc.m;
+        ex += cc.n;
+        eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
       }
       if (ex > refB + Prec<T>::kRescale) {
-        T f = Prec<T>::ldexp_(T(1), max(refB - ex, -1000));
+        T f = Prec<T>::ldexp_(T(1), (int)fmax(refB - ex, -1000.0));
         b0.scale(f);
 #pragma unroll
         for (int m = 0; m < Q; ++m) b1[m].scale(f);
@@ -441,7 +436,7 @@ __global__ __launch_bounds__(256) void pair_kernel(
         for (int m = 0; m < NT; ++m) b2[m].scale(f);
         refB = ex;
       }
-      T wgt = Prec<T>::ldexp_(prod, ex - refB);
+      T wgt = Prec<T>::ldexp_(prod, (int)fmax(ex - refB, -1000.0));
       T eh[Q];
 #pragma unroll
       for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
@@ -462,14 +457,14 @@ __global__ __launch_bounds__(256) void pair_kernel(
   double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
   {
-    int R = wave_max(refA);
-    double sc = ldexp(1.0, max(refA - R, -1100));
+    double R = wave_max(refA);
+    double sc = ldexp(1.0, (int)fmax(refA - R, -1100.0));
     double S = wave_sum(accA.value() * sc);
     logTA = log(S) + R * kLn2 - log((double)N);
   }
   if (MOM) {
-    int R = wave_max(refB);
-    double sc = ldexp(1.0, max(refB - R, -1100));
+    double R = wave_max(refB);
+    double sc = ldexp(1.0, (int)fmax(refB - R, -1100.0));
     double S0 = wave_sum(b0.value() * sc);
     double S1[Q], S2[Q][Q];
 #pragma unroll
@@ -870,22 +865,24 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
   double r = 0.0;
   switch (fn) {
     case 0: {  // Phi
-      Coord<double> c = norm_coord<double>(a);
-      r = c.deep ? exp(c.lphi) : c.e;
+      PhiVal<double> c = phi_eval(a);
+      r = ldexp(c.m, (int)fmax(c.n, -1100.0));
       break;
     }
     case 1: {  // log Phi
-      Coord<double> c = norm_coord<double>(a);
-      r = c.deep ? c.lphi : (a > 0.0 ? log1p(-c.ebar) : log(c.e));
+      PhiVal<double> c = phi_eval(a);
+      r = c.neg ? log(c.m) + c.n * kLn2 : log1p(-c.ebar);
       break;
     }
-    case 2: {  // Phi^{-1}(p) via the draw routine with u = p, Phi(ub) = 1
-      Coord<double> c;
-      c.e = 1.0;
+    case 2: {  // Phi^{-1}(p) through the draw routine with Phi(ub) = 1
+      PhiVal<double> c;
+      c.e = 0.0;
+      c.m = 1.0;
+      c.n = 0.0;
       c.ebar = 0.0;
-      c.deep = false;
+      c.neg = false;
       c.lphi = 0.0;
-      r = norm_draw<double>(a, 1.0 - a, c);
+      r = draw_eval(a, 1.0 - a, c);
       break;
     }
     case 3: r = ninv_from_log(a); break;
@@ -893,19 +890,23 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
     case 5: r = digamma_(a); break;
     case 6: r = trigamma_(a); break;
     case 7: {  // Phi in FP32
-      Coord<float> c = norm_coord<float>((float)a);
-      r = c.deep ? exp(c.lphi) : (double)c.e;
+      PhiVal<float> c = phi_eval((float)a);
+      r = c.lphi != 0.0 ? exp(c.lphi) : (double)c.e;
       break;
     }
     case 8: {  // Phi^{-1} in FP32
-      Coord<float> c;
+      PhiVal<float> c;
       c.e = 1.0f;
+      c.m = 1.0f;
+      c.n = 0.0;
       c.ebar = 0.0f;
-      c.deep = false;
+      c.neg = false;
       c.lphi = 0.0;
-      r = (double)norm_draw<float>((float)a, (float)(1.0 - a), c);
+      r = (double)draw_eval((float)a, (float)(1.0 - a), c);
       break;
     }
+    case 9: r = log_(a); break;
+    case 10: r = sqrt_(a); break;
     default: r = NAN;
   }
   out[t] = r;

@@ -9,6 +9,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "cfust_coeffs.hpp"
+
 namespace cfust {
 
 constexpr double kLn2 = 0.69314718055994530942;
@@ -52,9 +54,154 @@ __device__ __forceinline__ double log_phi_lower_tail(double x) {
   return log(0.5 * erfcx(z)) - z * z;
 }
 
-// Lower-tail normal quantile from log p for p below the double range.
-// Newton on log Phi(w) - lp; the slope phi(w)/Phi(w) equals
-// 1 / (sqrt(2 pi) erfcx(-w/sqrt 2) / 2), so no exp is needed.
+// ---------------------------------------------------------------------------
+// One GHK coordinate.  PhiVal holds Phi(ub) = m * 2^n with the exponent n
+// carried separately (a double holding an integer), so that no truncation
+// probability ever underflows, and the complement ebar = 1 - Phi(ub) with full
+// relative accuracy where it can be close to 0 (ub > 0).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PhiVal {
+  T e;        // FP32: Phi(ub) as a plain value
+  T m;        // Phi(ub) = m * 2^n
+  double n;
+  T ebar;     // 1 - Phi(ub)
+  bool neg;   // ub < 0
+  double lphi;  // FP32 deep tail only: log Phi(ub)
+};
+
+// FP64 building blocks --------------------------------------------------------
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2Hi = 0.69314718055994528623;   // double(ln 2)
+constexpr double kLn2Lo = 2.3190468138462996154e-17; // ln 2 - kLn2Hi
+
+// A zero the compiler cannot see through (one s_mov_b32, no memory access).
+// Offsetting table reads by it keeps the scalar loads of polynomial tables
+// next to their use: hoisted out of the point loop, the ~75 FP64 coefficients
+// would not fit the SGPR file and would spill into VGPR lanes.
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
+
+// sum_j c[j] x^j as four interleaved power sums over y = x^4,
+//   acc_m = sum_k c[4k+m] y^k,  result = acc_0 + x (acc_1 + x (acc_2 + x acc_3)).
+// Each coefficient enters as the multiplicand of an fma (acc += c * y^k), so it
+// is read straight from an SGPR; in Horner form it would be the tied addend of
+// v_fmac and cost two extra moves per step.  Rounding stays at a few ulp for
+// the tables used here (|x| <= 1 with decaying coefficients, or all terms of
+// one sign).
+template <int K>
+__device__ __forceinline__ double poly(const double (&c)[K], double x) {
+  static_assert(K >= 8, "poly: at least 8 coefficients");
+  const double* cp = c + opaque_zero();
+  double x2 = x * x;
+  double y = x2 * x2;
+  double acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = cp[4 + m] * y;  // c[4+m] y^1
+  double yk = y * y;
+#pragma unroll
+  for (int j = 8; j < K; j += 4) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (j + m < K) acc[m] = fma(cp[j + m], yk, acc[m]);
+    if (j + 4 < K) yk *= y;
+  }
+  // the constant terms c[0..3] enter through one add each (SGPR operand)
+  double r0 = acc[0] + cp[0], r1 = acc[1] + cp[1], r2 = acc[2] + cp[2], r3 = acc[3] + cp[3];
+  return fma(x2, fma(x, r3, r2), fma(x, r1, r0));
+}
+
+// 1/x for x > 0 normal: hardware reciprocal plus two Newton steps.
+__device__ __forceinline__ double rcp_(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// exp(x) = r * 2^n with n = rint(x / ln 2), |x| <= 2^50.  The reduction uses
+// fma so that n * ln2 is subtracted exactly even for large n; exp of the
+// reduced argument (|r| <= ln2/2 plus a rounding residual) by its Taylor
+// polynomial of degree 13 (truncation below 1e-17).
+__constant__ double kExpTaylor[14] = {
+    1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320,
+    1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0};
+
+__device__ __forceinline__ double exp_split(double x, double* n) {
+  double k = rint(x * kLog2e);
+  double r = fma(k, -kLn2Hi, x);
+  r = fma(k, -kLn2Lo, r);
+  *n = k;
+  return poly(kExpTaylor, r);
+}
+
+// 1/3, 1/5, ..., 1/21: the odd series of atanh after its leading term
+__constant__ double kAtanhOdd[10] = {1.0 / 3,  1.0 / 5,  1.0 / 7,  1.0 / 9,  1.0 / 11,
+                                     1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21};
+
+// Natural log of a positive normal double: x = m 2^k, m in [sqrt(1/2), sqrt(2)),
+// log m = 2 atanh(s), s = (m - 1) / (m + 1), by its odd series in s up to s^21.
+__device__ __forceinline__ double log_(double x) {
+  int k;
+  double m = frexp(x, &k);
+  bool lo = m < kSqrtHalf;
+  m = lo ? m + m : m;
+  double kd = (double)(lo ? k - 1 : k);
+  double f = m - 1.0;
+  double s = f * rcp_(2.0 + f);
+  double s2 = s * s;
+  double p = poly(kAtanhOdd, s2);
+  // log m = 2 s + 2 s s2 p = f - s f + 2 s s2 p  (f - s f = 2s exactly in real arithmetic)
+  double two_s = s + s;
+  double lm = fma(two_s * s2, p, two_s);
+  return fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
+}
+
+// sqrt of x > 0: hardware reciprocal square root plus two Newton steps.
+__device__ __forceinline__ double sqrt_(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double g = x * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  // final correction on the residual
+  double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+// Phi(ub) for FP64, branch-free: with z = |ub| / sqrt 2 and t = 2 / (2 + z),
+// erfc(z) = erfcx(z) exp(-z^2) = t Q(2t - 1) exp(-z^2); the exponent of
+// exp(-z^2) is kept apart.  z^2 is split into its rounded value and the exact
+// residual (fma) so that exp(-z^2) keeps full relative accuracy.
+__device__ __forceinline__ PhiVal<double> phi_eval(double ub) {
+  double z = fmin(fabs(ub) * kSqrtHalf, 1.0e7);
+  double t = 2.0 * rcp_(2.0 + z);
+  double ex = t * poly(kErfcxQ, fma(2.0, t, -1.0));
+  double zz = z * z;
+  double res = fma(z, z, -zz);
+  double n;
+  double er = exp_split(-zz, &n);
+  double mh = 0.5 * ex * er * (1.0 - res);  // erfc(z)/2 = mh 2^n
+  double small = ldexp(mh, (int)fmax(n, -1100.0));
+  PhiVal<double> v;
+  v.neg = ub < 0.0;
+  v.e = 0.0;
+  v.m = v.neg ? mh : 1.0 - small;
+  v.n = v.neg ? n : 0.0;
+  v.ebar = v.neg ? 1.0 - small : small;
+  v.lphi = 0.0;
+  return v;
+}
+
+// Lower-tail quantile from log p where p is below the rational's range
+// (t > kNinvTMax, p < 1e-313): Newton on log Phi(w) - lp with erfcx.
 __device__ __noinline__ double ninv_from_log(double lp) {
   double t = -2.0 * lp;
   double w = -sqrt(t - log(t) - 2.0 * kLogSqrt2Pi);
@@ -70,61 +217,67 @@ __device__ __noinline__ double ninv_from_log(double lp) {
   return w;
 }
 
-// One GHK coordinate: the truncation probability e = Phi(ub) as
-// mant * 2^ex (mant in [1/2, 1)), its complement ebar = 1 - Phi(ub), and,
-// in the deep lower tail, log Phi(ub) in FP64.
-template <typename T>
-struct Coord {
-  T e, ebar, mant;
-  int ex;
-  bool deep;
-  double lphi;
-};
+// eps = Phi^{-1}(u Phi(ub)) for FP64, branch-free outside the deep tail:
+// with the lower-half probability a = u Phi(ub) (or its complement
+// (1 - u) + u (1 - Phi(ub)) when u Phi(ub) > 1/2) and t = sqrt(-2 log a),
+// Phi^{-1}(a) = -t + P(t)/R(t).
+__device__ __forceinline__ double draw_eval(double u, double ubar, const PhiVal<double>& v) {
+  double um = u * v.m;
+  bool lower = v.neg || um <= 0.5;
+  double a = lower ? um : fma(u, v.ebar, ubar);
+  double nl = lower ? v.n : 0.0;
+  double L = fma(nl, kLn2Hi, fma(nl, kLn2Lo, log_(a)));
+  double t2 = -2.0 * L;
+  double w;
+  if (t2 <= kNinvTMax * kNinvTMax) {
+    double t = sqrt_(t2);
+    w = fma(poly(kNinvP, t), rcp_(poly(kNinvR, t)), -t);
+  } else {
+    w = ninv_from_log(L);
+  }
+  return lower ? w : -w;
+}
 
-// Deep lower tail of norm_coord, kept out of line: it is rare and its
-// log/exp/erfcx would otherwise inflate the register budget of the hot loop.
-__device__ __noinline__ void deep_coord(double ub, double* mant, int* ex, double* lphi) {
+// FP32 building blocks (ocml float functions; the deep lower tail in FP64) ----
+__device__ __noinline__ void deep_coord(double ub, double* mant, double* ex, double* lphi) {
   double lp = log_phi_lower_tail(ub);
   double k = floor(lp / kLn2);
-  double m = exp(lp - k * kLn2);  // in [1, 2)
-  *ex = (int)k + 1;
-  *mant = 0.5 * m;
+  *mant = exp(lp - k * kLn2);  // in [1, 2)
+  *ex = k;
   *lphi = lp;
 }
 
-template <typename T>
-__device__ __forceinline__ Coord<T> norm_coord(T ub) {
-  Coord<T> c;
-  if (ub >= Prec<T>::deep()) {
-    T t = T(0.5) * Prec<T>::erfc_(fabs(ub) * T(kSqrtHalf));
-    bool neg = ub < T(0);
-    c.e = neg ? t : T(1) - t;
-    c.ebar = neg ? T(1) - t : t;
-    c.mant = Prec<T>::frexp_(c.e, &c.ex);
-    c.deep = false;
+__device__ __forceinline__ PhiVal<float> phi_eval(float ub) {
+  PhiVal<float> c;
+  if (ub >= Prec<float>::deep()) {
+    float t = 0.5f * erfcf(fabsf(ub) * (float)kSqrtHalf);
+    c.neg = ub < 0.0f;
+    c.e = c.neg ? t : 1.0f - t;
+    c.ebar = c.neg ? 1.0f - t : t;
+    int ex;
+    c.m = frexpf(c.e, &ex);
+    c.n = (double)ex;
     c.lphi = 0.0;
   } else {
     double m;
-    deep_coord((double)ub, &m, &c.ex, &c.lphi);
-    c.mant = (T)m;
-    c.e = T(0);
-    c.ebar = T(1);
-    c.deep = true;
+    deep_coord((double)ub, &m, &c.n, &c.lphi);
+    c.m = (float)m;
+    c.e = 0.0f;
+    c.ebar = 1.0f;
+    c.neg = true;
   }
   return c;
 }
 
 __device__ __noinline__ double deep_draw(double u, double lphi) { return ninv_from_log(log(u) + lphi); }
 
-// Draw eps = Phi^{-1}(u Phi(ub)) by inversion.  Above 1/2 the quantile is
-// taken from the complement (1 - u) + u (1 - Phi(ub)), which keeps full
-// relative accuracy near 1.
-template <typename T>
-__device__ __forceinline__ T norm_draw(T u, T ubar, const Coord<T>& c) {
-  if (c.deep) return (T)deep_draw((double)u, c.lphi);
-  T pr = u * c.e;
-  if (pr <= T(0.5)) return Prec<T>::ninv(pr);
-  return -Prec<T>::ninv(ubar + u * c.ebar);
+__device__ __forceinline__ float draw_eval(float u, float ubar, const PhiVal<float>& c) {
+  if (c.lphi != 0.0) return (float)deep_draw((double)u, c.lphi);
+  float pr = u * c.e;
+  bool lower = pr <= 0.5f;
+  float a = lower ? pr : ubar + u * c.ebar;
+  float w = normcdfinvf(a);
+  return lower ? w : -w;
 }
 
 // ---------------------------------------------------------------------------
@@ -250,9 +403,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ int wave_max(int v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
 
