@@ -186,11 +186,13 @@ double orc_chi2_quantile(double u, double dof) {
       hi = x;
     double dens = exp((a - 1.0) * log(x) - x - lga);
     double xn = x - f / dens;
-    if (!(xn > lo && xn < hi)) xn = isinf(hi) ? 2.0 * x : 0.5 * (lo + hi);
-    if (fabs(xn - x) <= 1e-15 * xn) {
-      x = xn;
+    /* stop when the Newton step is at rounding level or the bracket has
+     * closed to a few ulp (P, Q carry about 1e-15 absolute rounding) */
+    if (fabs(xn - x) <= 1e-15 * x || hi - lo <= 4e-16 * x) {
+      if (xn > lo && xn < hi) x = xn;
       break;
     }
+    if (!(xn > lo && xn < hi)) xn = isinf(hi) ? 2.0 * x : 0.5 * (lo + hi);
     x = xn;
   }
   return 2.0 * x;
