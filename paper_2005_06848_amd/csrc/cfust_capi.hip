@@ -231,8 +231,7 @@ void launch_stats(const Ws& ws, const Plan& pl, const double* y, const double* m
       out ? out->tau : nullptr, out ? out->logf : logf_only, out ? out->e1 : nullptr,
       out ? out->e2 : nullptr, out ? out->e3 : nullptr, out ? out->e4 : nullptr,
       ws.at<int>(pl.o_status));
-  int threads = pl.GS + 1;
-  reduce_kernel<<<(threads + 255) / 256, 256, 0, ws.st>>>(
+  reduce_kernel<<<pl.GS + 1, 64, 0, ws.st>>>(
       ws.at<double>(pl.o_part), ws.at<double>(pl.o_pll), pl.nb, pl.GS,
       with_stats ? stats : nullptr, loglik, ws.at<int>(pl.o_status));
 }

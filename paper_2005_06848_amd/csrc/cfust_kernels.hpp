@@ -675,21 +675,31 @@ __global__ __launch_bounds__(256) void stats_kernel(
   if (tid == 0 && writer) partial_ll[blockIdx.x] = ll_acc;
 }
 
-// fixed-order reduction of the block partials: thread per entry
-__global__ void reduce_kernel(const double* __restrict__ partial, const double* __restrict__ partial_ll,
-                              int nb, int GS, double* __restrict__ stats, double* __restrict__ loglik,
-                              const int* __restrict__ status) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = status[0] == kOk;
-  if (e < GS && stats) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * GS + e];
-    stats[e] = ok ? s : NAN;
+// fixed-order reduction of the block partials: one 64-lane wave per entry
+// (block e < GS: statistic e; block GS: the log-likelihood); lane l sums
+// partials l, l+64, ... in order, then a butterfly combines the lanes, so the
+// result does not depend on timing.
+__global__ __launch_bounds__(64) void reduce_kernel(const double* __restrict__ partial,
+                                                   const double* __restrict__ partial_ll, int nb,
+                                                   int GS, double* __restrict__ stats,
+                                                   double* __restrict__ loglik,
+                                                   const int* __restrict__ status) {
+  const int e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const bool ok = status[0] == kOk;
+  double s = 0.0;
+  if (e < GS) {
+    if (!stats) return;
+    for (int b = lane; b < nb; b += 64) s += partial[(size_t)b * GS + e];
+  } else {
+    for (int b = lane; b < nb; b += 64) s += partial_ll[b];
   }
-  if (e == GS) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial_ll[b];
-    loglik[0] = ok ? s : NAN;
+  s = wave_sum(s);
+  if (lane == 0) {
+    if (e < GS)
+      stats[e] = ok ? s : NAN;
+    else
+      loglik[0] = ok ? s : NAN;
   }
 }
 

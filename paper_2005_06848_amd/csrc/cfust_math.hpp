@@ -320,7 +320,7 @@ __device__ void inc_gamma(double a, double x, double lga, double* P, double* Q) 
       dd = 1.0 / dd;
       double delta = dd * cc;
       f *= delta;
-      if (fabs(delta - 1.0) < 1e-17) break;
+      if (fabs(delta - 1.0) <= 2.3e-16) break;
     }
     *Q = lead * f;
     *P = 1.0 - *Q;
@@ -342,7 +342,7 @@ __device__ double chi2_quantile(double u, double dof) {
   double lo = 0.0, hi = 1e308;
   bool upper = u > 0.5;
   double target = upper ? (1.0 - u) : u;
-  for (int it = 0; it < 400; ++it) {
+  for (int it = 0; it < 100; ++it) {
     double P, Q;
     inc_gamma(a, x, lga, &P, &Q);
     double r = upper ? (target - Q) : (P - target);  // increasing in x
@@ -351,11 +351,16 @@ __device__ double chi2_quantile(double u, double dof) {
     else
       hi = x;
     double dens = exp((a - 1.0) * log(x) - x - lga);
-    double xn = x - r / dens;
+    double step = r / dens;
+    double xn = x - step;
+    // converged: the Newton step is at rounding level, or the bracket has
+    // shrunk to a few ulp (P and Q carry ~1e-15 absolute rounding)
+    if (fabs(step) <= 1e-15 * x || hi - lo <= 4e-16 * x) {
+      x = xn > lo && xn < hi ? xn : x;
+      break;
+    }
     if (!(xn > lo && xn < hi)) xn = (hi < 1e308) ? 0.5 * (lo + hi) : 4.0 * x;
-    double dx = fabs(xn - x);
     x = xn;
-    if (dx <= 1e-15 * x) break;
   }
   return 2.0 * x;
 }
