@@ -49,6 +49,53 @@ def flops_per_pair(p, q, N):
     return N * (fa + fb) + 2 * p * p + 2 * p * q + 40
 
 
+def precision_form(args, native, L, torch, np, inputs, dev):
+    """FP32 integrand vs FP64 on the precision-form workload: one E-step each
+    (precompute, chi tables, pair kernel, partial sums), same inputs."""
+    c = inputs.config(3)
+    n, p, q, g, N = c["n"], c["p"], c["q"], c["g"], c["n_qmc"]
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y, u = T(c["y"]), T(c["u"])
+    par = {k: T(v) for k, v in c["init"].items()}
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    S = native.stats_size(p, q)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        stats = torch.empty((g, S), dtype=torch.float64, device=dev)
+        ll = torch.empty(1, dtype=torch.float64, device=dev)
+        ws = native.alloc_workspace(n, p, q, g, N, prec)
+        prof = native.prof_buffer()
+        opts = native.make_opts(precision=prec, workspace=ws, prof=prof)
+        out = native.EstepOut(None, None, None, None, None, None, P(stats), P(ll), -1)
+        pp = [P(par[k]) for k in ("pi", "mu", "Sigma", "Delta", "nu")]
+
+        def estep():
+            rc = L.cfust_estep(P(y), n, p, q, g, pp[0], pp[1], pp[2], pp[3], pp[4], P(u), N,
+                               ctypes.byref(opts), ctypes.byref(out))
+            if rc:
+                raise native.CfustError(rc, "cfust_estep", out.bad_component)
+
+        print(f"[bench] form {prec}: n={n} p={p} q={q} g={g} N={N}", file=sys.stderr, flush=True)
+        estep()
+        torch.cuda.synchronize()
+        for s_ in range(4):
+            prof[s_] = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.form_reps):
+            estep()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.form_reps
+        res[prec] = {"ms_per_estep": round(ms, 3), "pairs_per_s": round(n * g / (ms * 1e-3), 1),
+                     "pair_kernel_ms": round(prof[1] / args.form_reps, 3),
+                     "loglik": float(ll.cpu()[0])}
+        del ws
+    res["fp32_speedup_vs_fp64"] = round(res["fp64"]["ms_per_estep"] / res["fp32"]["ms_per_estep"], 3)
+    res["loglik_rel_diff"] = abs(res["fp32"]["loglik"] / res["fp64"]["loglik"] - 1)
+    res["workload"] = "cfust E-step n=200000 p=6 q=6 g=4 N=8192"
+    res["tolerance"] = "fp32 vs fp64 oracle: moments 1e-4, log-likelihood 1e-7 (tests/test_gpu_fp32.py)"
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +105,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-obs", type=int, default=500,
                     help="observations of the workload timed on the CPU oracle")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32-form speedup leg (n=200000, p=q=6, g=4, N=8192)")
+    ap.add_argument("--form-reps", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (traffic calibration)")
     return ap.parse_args()
@@ -143,6 +193,10 @@ def main():
             "traffic": TRAFFIC_BYTES_PER_LAUNCH, "kernel": f"pair_kernel<double,{q},true>",
             "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp}
 
+    forms = None
+    if not args.no_forms:
+        forms = precision_form(args, native, L, torch, np, inputs, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -167,6 +221,7 @@ def main():
                    "step": "one EM iteration (E-step + M-step)", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
 

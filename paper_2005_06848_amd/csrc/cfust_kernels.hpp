@@ -304,6 +304,17 @@ struct Acc<float> {
   __device__ __forceinline__ double value() const { return (double)s + (double)c; }
 };
 
+// lowest reference exponent (no point seen yet) and the power-of-two shift of
+// a point relative to the reference, clamped below at -1100 (flushes to 0)
+template <typename E>
+__device__ __forceinline__ E exp_floor();
+template <>
+__device__ __forceinline__ double exp_floor<double>() { return -1.0e30; }
+template <>
+__device__ __forceinline__ int exp_floor<int>() { return -(1 << 29); }
+__device__ __forceinline__ int shift_of(double d) { return (int)fmax(d, -1100.0); }
+__device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
+
 // ---------------------------------------------------------------------------
 // pair kernel: one wave per (observation j, component i)
 // ---------------------------------------------------------------------------
@@ -374,16 +385,17 @@ __global__ __launch_bounds__(256) void pair_kernel(
   const T* sAi = sA + (size_t)i * N;
   const T* sBi = sB + (size_t)i * N;
   const T* rsBi = rsB + (size_t)i * N;
+  using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
   Acc<T> accA;
   accA.zero();
-  double refA = -1.0e30;
+  E refA = exp_floor<E>();
   Acc<T> b0, b1[Q], b2[NT];
   b0.zero();
 #pragma unroll
   for (int m = 0; m < Q; ++m) b1[m].zero();
 #pragma unroll
   for (int m = 0; m < NT; ++m) b2[m].zero();
-  double refB = -1.0e30;
+  E refB = exp_floor<E>();
 
   // integral A: dof nu+p, draws for coordinates 1..Q-1
 #pragma unroll 1
@@ -391,7 +403,7 @@ __global__ __launch_bounds__(256) void pair_kernel(
     const T s = sAi[k];
     T eps[Q];
     T prod = T(1);
-    double ex = 0.0;
+    E ex = 0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
       T bnd = s * htA[m];
@@ -403,10 +415,10 @@ __global__ __launch_bounds__(256) void pair_kernel(
       if (m < Q - 1) eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
     }
     if (ex > refA + Prec<T>::kRescale) {
-      accA.scale(Prec<T>::ldexp_(T(1), (int)fmax(refA - ex, -1000.0)));
+      accA.scale(Prec<T>::ldexp_(T(1), shift_of(refA - ex)));
       refA = ex;
     }
-    accA.add(Prec<T>::ldexp_(prod, (int)fmax(ex - refA, -1000.0)));
+    accA.add(Prec<T>::ldexp_(prod, shift_of(ex - refA)));
   }
   // integral B: dof nu+p+2, draws for all Q coordinates, moments of eps/s
   if (MOM) {
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(256) void pair_kernel(
       const T rs = rsBi[k];
       T eps[Q];
       T prod = T(1);
-      double ex = 0.0;
+      E ex = 0;
 #pragma unroll
       for (int m = 0; m < Q; ++m) {
         T bnd = s * htB[m];
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(256) void pair_kernel(
         eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
       }
       if (ex > refB + Prec<T>::kRescale) {
-        T f = Prec<T>::ldexp_(T(1), (int)fmax(refB - ex, -1000.0));
+        T f = Prec<T>::ldexp_(T(1), shift_of(refB - ex));
         b0.scale(f);
 #pragma unroll
         for (int m = 0; m < Q; ++m) b1[m].scale(f);
@@ -436,7 +448,7 @@ __global__ __launch_bounds__(256) void pair_kernel(
         for (int m = 0; m < NT; ++m) b2[m].scale(f);
         refB = ex;
       }
-      T wgt = Prec<T>::ldexp_(prod, (int)fmax(ex - refB, -1000.0));
+      T wgt = Prec<T>::ldexp_(prod, shift_of(ex - refB));
       T eh[Q];
 #pragma unroll
       for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
@@ -457,14 +469,14 @@ __global__ __launch_bounds__(256) void pair_kernel(
   double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
   {
-    double R = wave_max(refA);
-    double sc = ldexp(1.0, (int)fmax(refA - R, -1100.0));
+    E R = wave_max(refA);
+    double sc = ldexp(1.0, shift_of(refA - R));
     double S = wave_sum(accA.value() * sc);
     logTA = log(S) + R * kLn2 - log((double)N);
   }
   if (MOM) {
-    double R = wave_max(refB);
-    double sc = ldexp(1.0, (int)fmax(refB - R, -1100.0));
+    E R = wave_max(refB);
+    double sc = ldexp(1.0, shift_of(refB - R));
     double S0 = wave_sum(b0.value() * sc);
     double S1[Q], S2[Q][Q];
 #pragma unroll
@@ -901,14 +913,14 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
     case 6: r = trigamma_(a); break;
     case 7: {  // Phi in FP32
       PhiVal<float> c = phi_eval((float)a);
-      r = c.lphi != 0.0 ? exp(c.lphi) : (double)c.e;
+      r = ldexp((double)c.m, c.n);
       break;
     }
     case 8: {  // Phi^{-1} in FP32
       PhiVal<float> c;
       c.e = 1.0f;
       c.m = 1.0f;
-      c.n = 0.0;
+      c.n = 0;
       c.ebar = 0.0f;
       c.neg = false;
       c.lphi = 0.0;

@@ -9,6 +9,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "cfust_coeffs.hpp"
 
 namespace cfust {
@@ -20,39 +22,23 @@ constexpr double kSqrt2Pi = 2.50662827463100050242;
 constexpr double kLogPi = 1.14472988584940017414;
 
 // ---------------------------------------------------------------------------
-// precision traits: the integrand type T and its tail threshold.  Below
-// `deep` the lower-tail probability Phi(x) is treated in log space, chosen so
-// that u * Phi(x) stays a normal number of type T for every u >= 2^-31.
+// precision traits of the integrand type T: ldexp and how far the weight
+// accumulators may grow above their reference before it is moved.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Prec;
 
 template <>
 struct Prec<double> {
-  static __device__ __forceinline__ double deep() { return -36.0; }
-  static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
-  static __device__ __forceinline__ double ninv(double p) { return normcdfinv(p); }
-  static __device__ __forceinline__ double frexp_(double x, int* e) { return frexp(x, e); }
   static __device__ __forceinline__ double ldexp_(double x, int e) { return ldexp(x, e); }
   static constexpr int kRescale = 64;  // accumulators may grow to 2^64 before re-referencing
 };
 
 template <>
 struct Prec<float> {
-  static __device__ __forceinline__ float deep() { return -11.0f; }
-  static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
-  static __device__ __forceinline__ float ninv(float p) { return normcdfinvf(p); }
-  static __device__ __forceinline__ float frexp_(float x, int* e) { return frexpf(x, e); }
   static __device__ __forceinline__ float ldexp_(float x, int e) { return ldexpf(x, e); }
   static constexpr int kRescale = 32;
 };
-
-// log Phi(x) for x far in the lower tail (x < -10), in FP64:
-// Phi(x) = erfcx(z) exp(-z^2) / 2 with z = -x / sqrt(2).
-__device__ __forceinline__ double log_phi_lower_tail(double x) {
-  double z = -x * kSqrtHalf;
-  return log(0.5 * erfcx(z)) - z * z;
-}
 
 // ---------------------------------------------------------------------------
 // One GHK coordinate.  PhiVal holds Phi(ub) = m * 2^n with the exponent n
@@ -62,12 +48,12 @@ __device__ __forceinline__ double log_phi_lower_tail(double x) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PhiVal {
-  T e;        // FP32: Phi(ub) as a plain value
+  T e;        // FP32: Phi(ub) as a plain value (0 when below the float range)
   T m;        // Phi(ub) = m * 2^n
-  double n;
+  typename std::conditional<sizeof(T) == 8, double, int>::type n;
   T ebar;     // 1 - Phi(ub)
   bool neg;   // ub < 0
-  double lphi;  // FP32 deep tail only: log Phi(ub)
+  double lphi;  // unused (kept zero)
 };
 
 // FP64 building blocks --------------------------------------------------------
@@ -238,45 +224,61 @@ __device__ __forceinline__ double draw_eval(double u, double ubar, const PhiVal<
   return lower ? w : -w;
 }
 
-// FP32 building blocks (ocml float functions; the deep lower tail in FP64) ----
-__device__ __noinline__ void deep_coord(double ub, double* mant, double* ex, double* lphi) {
-  double lp = log_phi_lower_tail(ub);
-  double k = floor(lp / kLn2);
-  *mant = exp(lp - k * kLn2);  // in [1, 2)
-  *ex = k;
-  *lphi = lp;
+// FP32 building blocks --------------------------------------------------------
+// Same construction as FP64 with hardware v_exp_f32 / v_log_f32 / v_rcp_f32 /
+// v_sqrt_f32 and single-precision fits; the exponent of Phi is an int.
+constexpr float kSqrtHalfF = 0.70710678118654752f;
+constexpr float kLog2eF = 1.44269504088896341f;
+constexpr float kLog2eLoF = 1.925963033500011e-08f;  // log2(e) - float(log2(e))
+constexpr float kLn2F = 0.69314718055994531f;
+
+template <int K>
+__device__ __forceinline__ float poly_f(const float (&c)[K], float x) {
+  float r = c[K - 1];
+#pragma unroll
+  for (int j = K - 2; j >= 0; --j) r = fmaf(r, x, c[j]);
+  return r;
 }
 
 __device__ __forceinline__ PhiVal<float> phi_eval(float ub) {
-  PhiVal<float> c;
-  if (ub >= Prec<float>::deep()) {
-    float t = 0.5f * erfcf(fabsf(ub) * (float)kSqrtHalf);
-    c.neg = ub < 0.0f;
-    c.e = c.neg ? t : 1.0f - t;
-    c.ebar = c.neg ? 1.0f - t : t;
-    int ex;
-    c.m = frexpf(c.e, &ex);
-    c.n = (double)ex;
-    c.lphi = 0.0;
-  } else {
-    double m;
-    deep_coord((double)ub, &m, &c.n, &c.lphi);
-    c.m = (float)m;
-    c.e = 0.0f;
-    c.ebar = 1.0f;
-    c.neg = true;
-  }
-  return c;
+  float z = fminf(fabsf(ub) * kSqrtHalfF, 2000.0f);
+  float t = 2.0f * __builtin_amdgcn_rcpf(2.0f + z);
+  float ex = t * poly_f(kErfcxQf, fmaf(2.0f, t, -1.0f));
+  float zz = z * z;
+  float res = fmaf(z, z, -zz);
+  // exp(-zz - res) = 2^k * 2^r: k = rint(-zz log2 e), r with a two-part log2 e
+  float k = rintf(-zz * kLog2eF);
+  float r = fmaf(-zz, kLog2eF, -k);
+  r = fmaf(-zz, kLog2eLoF, r);
+  r = fmaf(-res, kLog2eF, r);
+  float mh = 0.5f * ex * __builtin_amdgcn_exp2f(r);  // erfc(z)/2 = mh 2^k
+  int n = (int)k;
+  float small = ldexpf(mh, max(n, -160));
+  PhiVal<float> v;
+  v.neg = ub < 0.0f;
+  v.m = v.neg ? mh : 1.0f - small;
+  v.n = v.neg ? n : 0;
+  v.ebar = v.neg ? 1.0f - small : small;
+  v.e = v.neg ? small : v.m;
+  v.lphi = 0.0;
+  return v;
 }
 
-__device__ __noinline__ double deep_draw(double u, double lphi) { return ninv_from_log(log(u) + lphi); }
+__device__ __noinline__ double deep_draw_f(double lp) { return ninv_from_log(lp); }
 
-__device__ __forceinline__ float draw_eval(float u, float ubar, const PhiVal<float>& c) {
-  if (c.lphi != 0.0) return (float)deep_draw((double)u, c.lphi);
-  float pr = u * c.e;
-  bool lower = pr <= 0.5f;
-  float a = lower ? pr : ubar + u * c.ebar;
-  float w = normcdfinvf(a);
+__device__ __forceinline__ float draw_eval(float u, float ubar, const PhiVal<float>& v) {
+  float um = u * v.m;
+  bool lower = v.neg || um <= 0.5f;
+  float a = lower ? um : fmaf(u, v.ebar, ubar);
+  float L2 = __builtin_amdgcn_logf(a) + (lower ? (float)v.n : 0.0f);  // log2 of the probability
+  float t2 = (-2.0f * kLn2F) * L2;
+  float w;
+  if (t2 <= kNinvTMaxF * kNinvTMaxF) {
+    float t = __builtin_amdgcn_sqrtf(t2);
+    w = fmaf(poly_f(kNinvPf, t), __builtin_amdgcn_rcpf(poly_f(kNinvRf, t)), -t);
+  } else {
+    w = (float)deep_draw_f((double)L2 * kLn2);
+  }
   return lower ? w : -w;
 }
 
@@ -405,6 +407,12 @@ __device__ double trigamma_(double x) {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
   return v;
 }
 
