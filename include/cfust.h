@@ -74,6 +74,11 @@ typedef struct cfust_opts {
                              [0] precompute + chi tables, [1] pair kernel (the two
                              GHK integrals), [2] responsibilities + partial sums,
                              [3] M-step */
+  int graph;              /* cfust_em_fit_batched: nonzero = capture one iteration in a
+                             hipGraph and replay it (default 1) */
+  int tile;               /* cfust_em_fit_batched: launch shape of the persistent pair
+                             kernel, 0 = autotune, else 1 + index into the candidate
+                             table (see cfust_batched_config) */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4
@@ -139,6 +144,34 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
                  double* Sigma, double* Delta, double* nu, const double* u, int n_qmc,
                  const cfust_opts* opts, double* loglik_trace, int* n_iter,
                  int* bad_component);
+
+/* Batched EM fit (section 3.1, Algorithm 1: many starts; sections 3.2-3.4
+ * for each): n_problems independent problems with shared p, q and QMC points.
+ * Problem k owns rows [off_k, off_k + n_obs[k]) of y (off_k = sum of the
+ * previous n_obs) and components [c_k, c_k + g[k]) of pi, mu, Sigma, Delta
+ * and nu (c_k = sum of the previous g); the parameter arrays hold Psi^(0) on
+ * entry and each problem's estimate on return.  Each problem stops on its own
+ * Aitken test, at opts->max_iter, or on an error (its status), while the
+ * others continue.  The integrand runs in opts->precision; partial sums, the
+ * M-step and the stopping rule in float64.  All iterations run on the device;
+ * with opts->graph one iteration is captured as a hipGraph and replayed.
+ * Host outputs: loglik_trace [n_problems][max_iter + 1] (NaN past n_iter),
+ * n_iter [n_problems], status [n_problems] (CFUST_* codes).
+ * Requires n_obs[k] >= 1, 1 <= g[k] <= 16, n_problems >= 1. */
+int cfust_em_fit_batched(const double* y, int p, int q, int n_problems, const int64_t* n_obs,
+                         const int* g, double* pi, double* mu, double* Sigma, double* Delta,
+                         double* nu, const double* u, int n_qmc, const cfust_opts* opts,
+                         double* loglik_trace, int* n_iter, int* status);
+
+/* Bytes of device workspace cfust_em_fit_batched needs. */
+int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_obs, const int* g,
+                                 int n_qmc, int precision, int max_iter, size_t* bytes);
+
+/* Launch shape chosen for the last cfust_em_fit_batched call (host outputs):
+ * waves per block, pairs per work-queue fetch, resident waves per SIMD, and
+ * the autotuner's timing of that shape in ms (0 if not tuned).  Returns the
+ * number of candidate shapes. */
+int cfust_batched_config(int* waves_per_block, int* chunk, int* waves_per_simd, double* tuned_ms);
 
 /* Aitken-accelerated limit l_inf from l^(t-2), l^(t-1), l^(t) (Algorithm 4,
  * read with the denominator 1 - a). Host scalars. */

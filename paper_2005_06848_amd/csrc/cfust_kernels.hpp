@@ -92,47 +92,19 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 // ---------------------------------------------------------------------------
 // per-component precompute (eq. (2)): one lane per component
 // ---------------------------------------------------------------------------
-__global__ void precompute_kernel(int p, int q, int g, const double* __restrict__ pi,
-                                  const double* __restrict__ Sigma,
-                                  const double* __restrict__ Delta, const double* __restrict__ mu,
-                                  const double* __restrict__ nu, double* __restrict__ comp,
-                                  int* status) {
-  const int i = threadIdx.x;
+// Component i's block: returns kOk or a status code (the block is then
+// incomplete).  w = pi_i, v = nu_i, mu_i, Sg = Sigma_i, Dl = Delta_i.
+__device__ int precompute_component(int p, int q, double w, double v, const double* mu_i,
+                                    const double* Sg, const double* Dl, double* out) {
   CompLayout cl(p, q);
-  if (i == 0) {
-    double s = 0.0;
-    for (int k = 0; k < g; ++k) s += pi[k];
-    if (!(fabs(s - 1.0) <= 1e-12)) set_status(status, kEInval, -1);
-  }
-  if (i >= g) return;
-  const double v = nu[i];
-  const double w = pi[i];
-  if (!isfinite(v) || !isfinite(w)) {
-    set_status(status, kENonFinite, i);
-    return;
-  }
-  if (!(v > 0.0) || !(w > 0.0)) {
-    set_status(status, kEInval, i);
-    return;
-  }
-  const double* Sg = Sigma + (size_t)i * p * p;
-  const double* Dl = Delta + (size_t)i * p * q;
+  if (!isfinite(v) || !isfinite(w)) return kENonFinite;
+  if (!(v > 0.0) || !(w > 0.0)) return kEInval;
   for (int a = 0; a < p; ++a)
-    if (!isfinite(mu[i * p + a])) {
-      set_status(status, kENonFinite, i);
-      return;
-    }
+    if (!isfinite(mu_i[a])) return kENonFinite;
   for (int a = 0; a < p * p; ++a)
-    if (!isfinite(Sg[a])) {
-      set_status(status, kENonFinite, i);
-      return;
-    }
+    if (!isfinite(Sg[a])) return kENonFinite;
   for (int a = 0; a < p * q; ++a)
-    if (!isfinite(Dl[a])) {
-      set_status(status, kENonFinite, i);
-      return;
-    }
-  double* out = comp + (size_t)i * cl.stride;
+    if (!isfinite(Dl[a])) return kENonFinite;
   double* L = out + cl.L;
   // Omega = Sigma + Delta Delta^T, Cholesky in place (lower, row-major)
   for (int a = 0; a < p; ++a)
@@ -144,10 +116,7 @@ __global__ void precompute_kernel(int p, int q, int g, const double* __restrict_
   for (int j = 0; j < p; ++j) {
     double s = L[j * p + j];
     for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
-    if (!(s > 0.0)) {
-      set_status(status, kENotPD, i);
-      return;
-    }
+    if (!(s > 0.0)) return kENotPD;
     double ljj = sqrt(s);
     L[j * p + j] = ljj;
     for (int r = j + 1; r < p; ++r) {
@@ -192,10 +161,7 @@ __global__ void precompute_kernel(int p, int q, int g, const double* __restrict_
   double* D = out + cl.D;
   double* Dinv = out + cl.Dinv;
   for (int k = 0; k < q; ++k) {
-    if (!(lam[k * q + k] > 0.0)) {
-      set_status(status, kENotPD, i);
-      return;
-    }
+    if (!(lam[k * q + k] > 0.0)) return kENotPD;
     D[k] = sqrt(lam[k * q + k]);
     Dinv[k] = 1.0 / D[k];
   }
@@ -205,10 +171,7 @@ __global__ void precompute_kernel(int p, int q, int g, const double* __restrict_
   for (int j = 0; j < q; ++j) {
     double s = C[j * q + j];
     for (int k = 0; k < j; ++k) s -= C[j * q + k] * C[j * q + k];
-    if (!(s > 0.0)) {
-      set_status(status, kENotPD, i);
-      return;
-    }
+    if (!(s > 0.0)) return kENotPD;
     double cjj = sqrt(s);
     C[j * q + j] = cjj;
     for (int r = j + 1; r < q; ++r) {
@@ -222,6 +185,27 @@ __global__ void precompute_kernel(int p, int q, int g, const double* __restrict_
                   0.5 * logdet;
   out[cl.nu] = v;
   out[cl.psi_a] = digamma_(a_);
+  return kOk;
+}
+
+__device__ bool pi_on_simplex(const double* pi, int g) {
+  double s = 0.0;
+  for (int k = 0; k < g; ++k) s += pi[k];
+  return fabs(s - 1.0) <= 1e-12;
+}
+
+__global__ void precompute_kernel(int p, int q, int g, const double* __restrict__ pi,
+                                  const double* __restrict__ Sigma,
+                                  const double* __restrict__ Delta, const double* __restrict__ mu,
+                                  const double* __restrict__ nu, double* __restrict__ comp,
+                                  int* status) {
+  const int i = threadIdx.x;
+  CompLayout cl(p, q);
+  if (i == 0 && !pi_on_simplex(pi, g)) set_status(status, kEInval, -1);
+  if (i >= g) return;
+  int rc = precompute_component(p, q, pi[i], nu[i], mu + (size_t)i * p, Sigma + (size_t)i * p * p,
+                                Delta + (size_t)i * p * q, comp + (size_t)i * cl.stride);
+  if (rc != kOk) set_status(status, rc, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -316,38 +300,33 @@ __device__ __forceinline__ int shift_of(double d) { return (int)fmax(d, -1100.0)
 __device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
 
 // ---------------------------------------------------------------------------
-// pair kernel: one wave per (observation j, component i)
+// one (observation, component) pair on one wave: lanes split the QMC points
+// of both GHK integrals; after the wave reductions every lane holds the same
+// record and lane t returns entry t of
+//   log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[Q] | e4 (upper triangle)
+// Returns false if y_j is not finite.
 // ---------------------------------------------------------------------------
 template <typename T, int Q, bool MOM>
-__global__ __launch_bounds__(256) void pair_kernel(
-    const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
-    const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
-    const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
-    double* __restrict__ pairbuf, int W, int* status) {
+__device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
+                                          const double* __restrict__ mui,
+                                          const double* __restrict__ cp,
+                                          const T* __restrict__ sAi, const T* __restrict__ sBi,
+                                          const T* __restrict__ rsBi, const T* __restrict__ uT,
+                                          const T* __restrict__ ubT, int N, int lane,
+                                          double* lane_out) {
   constexpr int NT = Q * (Q + 1) / 2;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
-  if (pair >= n * g) return;
-  if (status[0] != kOk) return;
-  const int64_t j = pair / g;
-  const int i = (int)(pair - j * g);
   const CompLayout cl(p, Q);
-  const double* cp = comp + (size_t)i * cl.stride;
   const double v = cp[cl.nu];
 
   // ---- a4: Mahalanobis distance and skew projection (eq. (2)) ----
   double r[kMaxP];
   bool finite_ok = true;
   for (int a = 0; a < p; ++a) {
-    double ya = y[j * p + a];
+    double ya = yj[a];
     finite_ok = finite_ok && isfinite(ya);
-    r[a] = ya - mu[i * p + a];
+    r[a] = ya - mui[a];
   }
-  if (!finite_ok) {
-    if (lane == 0) set_status(status, kENonFinite, -1);
-    return;
-  }
+  if (!finite_ok) return false;
   double d = 0.0;
   {
     double z[kMaxP];
@@ -382,9 +361,6 @@ __global__ __launch_bounds__(256) void pair_kernel(
   }
 
   // ---- a5 / a6: the two GHK integrals over this lane's points ----
-  const T* sAi = sA + (size_t)i * N;
-  const T* sBi = sB + (size_t)i * N;
-  const T* rsBi = rsB + (size_t)i * N;
   using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
   Acc<T> accA;
   accA.zero();
@@ -547,8 +523,40 @@ __global__ __launch_bounds__(256) void pair_kernel(
         ++t;
       }
   }
-  const int nw = MOM ? (3 + Q + NT) : 1;
-  if (lane < nw) pairbuf[pair * W + lane] = out;
+  *lane_out = out;
+  return true;
+}
+
+
+template <int Q, bool MOM>
+__host__ __device__ constexpr int record_width() {
+  return MOM ? (3 + Q + Q * (Q + 1) / 2) : 1;
+}
+
+// one wave per pair, four pairs per 256-thread block
+template <typename T, int Q, bool MOM>
+__global__ __launch_bounds__(256) void pair_kernel(
+    const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
+    const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
+    const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
+    double* __restrict__ pairbuf, int W, int* status) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
+  if (pair >= n * g) return;
+  if (status[0] != kOk) return;
+  const int64_t j = pair / g;
+  const int i = (int)(pair - j * g);
+  const CompLayout cl(p, Q);
+  double out;
+  bool ok = pair_eval<T, Q, MOM>(y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride,
+                                 sA + (size_t)i * N, sB + (size_t)i * N, rsB + (size_t)i * N, uT,
+                                 ubT, N, lane, &out);
+  if (!ok) {
+    if (lane == 0) set_status(status, kENonFinite, -1);
+    return;
+  }
+  if (lane < record_width<Q, MOM>()) pairbuf[pair * W + lane] = out;
 }
 
 // ---------------------------------------------------------------------------
@@ -558,25 +566,25 @@ __global__ __launch_bounds__(256) void pair_kernel(
 // ---------------------------------------------------------------------------
 constexpr int kStatsPerBlock = 2048;  // statistic entries per block (256 threads x 8)
 
-__global__ __launch_bounds__(256) void stats_kernel(
+// Body of one statistics block over observations [j0, j1) of one problem.
+// partial_row: this block's GS partial sums; ll_slot: its log-likelihood part.
+// ebase selects which 2048 statistic entries this block owns.
+__device__ __forceinline__ void stats_body(
     const double* __restrict__ y, int64_t n, int p, int q, int g, const double* __restrict__ mu,
-    const double* __restrict__ pairbuf, int W, int64_t per_block, int tile, int with_stats,
-    double* __restrict__ partial, double* __restrict__ partial_ll, double* __restrict__ tau_out,
-    double* __restrict__ logf_out, double* __restrict__ e1_out, double* __restrict__ e2_out,
-    double* __restrict__ e3_out, double* __restrict__ e4_out, const int* __restrict__ status) {
+    const double* __restrict__ pairbuf, int W, int64_t j0, int64_t j1, int tile, int with_stats,
+    int ebase, bool writer, bool ok, double* __restrict__ partial_row, double* __restrict__ ll_slot,
+    double* __restrict__ tau_out, double* __restrict__ logf_out, double* __restrict__ e1_out,
+    double* __restrict__ e2_out, double* __restrict__ e3_out, double* __restrict__ e4_out) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x;
   const StatLayout sl(p, q);
   const int GS = g * sl.S;
-  const int64_t j0 = (int64_t)blockIdx.x * per_block;
-  const int64_t j1 = min(n, j0 + per_block);
   // LDS: tile records [tile][g][W], taus [tile][g], y tile [tile][p], ll [tile]
   double* recs = sm;
   double* taus = recs + tile * g * W;
   double* ys = taus + tile * g;
   double* lls = ys + tile * p;
   constexpr int kPer = kStatsPerBlock / 256;
-  const int ebase = blockIdx.y * kStatsPerBlock;
   double acc[kPer];
   int kind[kPer], ia[kPer], xa[kPer], xb[kPer];
 #pragma unroll
@@ -616,8 +624,6 @@ __global__ __launch_bounds__(256) void stats_kernel(
     }
   }
   double ll_acc = 0.0;
-  const bool ok = status[0] == kOk;
-  const bool writer = blockIdx.y == 0;
   for (int64_t t0 = j0; t0 < j1 && ok; t0 += tile) {
     const int nt = (int)min((int64_t)tile, j1 - t0);
     for (int x = tid; x < nt * g * W; x += 256) recs[x] = pairbuf[t0 * g * W + x];
@@ -682,9 +688,23 @@ __global__ __launch_bounds__(256) void stats_kernel(
   if (with_stats) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e)
-      if (kind[e] >= 0) partial[(size_t)blockIdx.x * GS + ebase + tid + e * 256] = acc[e];
+      if (kind[e] >= 0) partial_row[ebase + tid + e * 256] = acc[e];
   }
-  if (tid == 0 && writer) partial_ll[blockIdx.x] = ll_acc;
+  if (tid == 0 && writer) *ll_slot = ll_acc;
+}
+
+__global__ __launch_bounds__(256) void stats_kernel(
+    const double* __restrict__ y, int64_t n, int p, int q, int g, const double* __restrict__ mu,
+    const double* __restrict__ pairbuf, int W, int64_t per_block, int tile, int with_stats,
+    double* __restrict__ partial, double* __restrict__ partial_ll, double* __restrict__ tau_out,
+    double* __restrict__ logf_out, double* __restrict__ e1_out, double* __restrict__ e2_out,
+    double* __restrict__ e3_out, double* __restrict__ e4_out, const int* __restrict__ status) {
+  const StatLayout sl(p, q);
+  const int64_t j0 = (int64_t)blockIdx.x * per_block;
+  const int64_t j1 = min(n, j0 + per_block);
+  stats_body(y, n, p, q, g, mu, pairbuf, W, j0, j1, tile, with_stats, blockIdx.y * kStatsPerBlock,
+             blockIdx.y == 0, status[0] == kOk, partial + (size_t)blockIdx.x * g * sl.S,
+             partial_ll + blockIdx.x, tau_out, logf_out, e1_out, e2_out, e3_out, e4_out);
 }
 
 // fixed-order reduction of the block partials: one 64-lane wave per entry
@@ -758,11 +778,16 @@ __device__ double nu_root(double cst, double lo, double hi, double v0) {
   return v;
 }
 
-__global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p, int q, int g,
-                             const double* mu_old, const double* Delta_old, const double* nu_old,
-                             int nu_fixed, int fix_delta_zero, double nu_lo, double nu_hi,
-                             double* pi, double* mu, double* Sigma, double* Delta, double* nu,
-                             double* __restrict__ pi_tmp, int* status) {
+// One problem's M-step on one block, lane i = component i.  Statuses go to
+// status[0..1].  Parameters may alias the old ones: every lane reads its old
+// values before any lane writes.
+__device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int64_t n, int p,
+                                           int q, int g, const double* mu_old,
+                                           const double* Delta_old, const double* nu_old,
+                                           int nu_fixed, int fix_delta_zero, double nu_lo,
+                                           double nu_hi, double* pi, double* mu, double* Sigma,
+                                           double* Delta, double* nu, double* __restrict__ pi_tmp,
+                                           int* status) {
   const int i = threadIdx.x;
   const StatLayout sl(p, q);
   __shared__ int fail;
@@ -874,6 +899,15 @@ __global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p,
     for (int k = 0; k < g; ++k) ps += pi_tmp[k];
     pi[i] = pi_tmp[i] / ps;
   }
+}
+
+__global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p, int q, int g,
+                             const double* mu_old, const double* Delta_old, const double* nu_old,
+                             int nu_fixed, int fix_delta_zero, double nu_lo, double nu_hi,
+                             double* pi, double* mu, double* Sigma, double* Delta, double* nu,
+                             double* __restrict__ pi_tmp, int* status) {
+  mstep_body(stats, n, p, q, g, mu_old, Delta_old, nu_old, nu_fixed, fix_delta_zero, nu_lo, nu_hi,
+             pi, mu, Sigma, Delta, nu, pi_tmp, status);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,8 @@ class Opts(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("prof_ms", ctypes.c_void_p),
+        ("graph", ctypes.c_int),
+        ("tile", ctypes.c_int),
     ]
 
 
@@ -89,6 +91,14 @@ def _lib():
         L.cfust_aitken_linf.restype = d
         L.cfust_eval_special.argtypes = [i, P, P, P, i64, P]
         L.cfust_eval_special.restype = i
+        L.cfust_em_fit_batched.argtypes = [P, i, i, i, P, P, P, P, P, P, P, P, i,
+                                           ctypes.POINTER(Opts), P, P, P]
+        L.cfust_em_fit_batched.restype = i
+        L.cfust_batched_workspace_size.argtypes = [i, i, i, P, P, i, i, i, ctypes.POINTER(sz)]
+        L.cfust_batched_workspace_size.restype = i
+        L.cfust_batched_config.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                           ctypes.POINTER(d)]
+        L.cfust_batched_config.restype = i
         L.cfust_strerror.argtypes = [i]
         L.cfust_strerror.restype = ctypes.c_char_p
         _LIB = L
@@ -112,7 +122,7 @@ def _ptr(t):
 
 
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
-              nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None):
+              nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -130,6 +140,8 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
         o.workspace_bytes = workspace.numel() * workspace.element_size()
     if prof is not None:
         o.prof_ms = ctypes.cast(prof, ctypes.c_void_p)
+    o.graph = int(bool(graph))
+    o.tile = int(tile)
     return o
 
 
@@ -252,3 +264,38 @@ def cfust_eval_special(fn, x, x2=None):
     if rc:
         raise CfustError(rc, "cfust_eval_special")
     return out
+
+
+def cfust_em_fit_batched(y, n_obs, g, params0, u, max_iter=50, tol=1e-6, **opt):
+    """Batched EM fit of independent problems (rows of y and components of the
+    parameter arrays concatenated problem by problem).  Returns the fitted
+    parameters (new tensors, concatenated), traces [P][max_iter+1] (NaN past
+    n_iter), n_iter [P] and status [P] (numpy arrays)."""
+    import numpy as np
+    y = _dev(y, "y")
+    u = _dev(u, "u")
+    par = {k: _dev(v, k).clone() for k, v in params0.items()}
+    P = len(n_obs)
+    p = y.shape[1]
+    q = par["Delta"].shape[2]
+    n_arr = (ctypes.c_int64 * P)(*[int(v) for v in n_obs])
+    g_arr = (ctypes.c_int * P)(*[int(v) for v in g])
+    trace = np.zeros((P, max_iter + 1))
+    n_iter = np.zeros(P, dtype=np.int32)
+    status = np.zeros(P, dtype=np.int32)
+    o = make_opts(max_iter=max_iter, tol=tol, **opt)
+    rc = _lib().cfust_em_fit_batched(_ptr(y), p, q, P, n_arr, g_arr, _ptr(par["pi"]), _ptr(par["mu"]),
+                                     _ptr(par["Sigma"]), _ptr(par["Delta"]), _ptr(par["nu"]), _ptr(u),
+                                     u.shape[0], ctypes.byref(o), trace.ctypes.data,
+                                     n_iter.ctypes.data, status.ctypes.data)
+    if rc:
+        raise CfustError(rc, "cfust_em_fit_batched")
+    return par, trace, n_iter, status
+
+
+def cfust_batched_config():
+    w, c, s = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    ms = ctypes.c_double(0)
+    n = _lib().cfust_batched_config(ctypes.byref(w), ctypes.byref(c), ctypes.byref(s), ctypes.byref(ms))
+    return dict(waves_per_block=w.value, chunk=c.value, waves_per_simd=s.value, tuned_ms=ms.value,
+                n_candidates=n)

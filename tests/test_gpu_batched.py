@@ -1,0 +1,139 @@
+"""Batched form: many independent EM problems in one device-driven loop,
+iterations captured in a hipGraph.  Checked against the oracle per problem,
+against the single-problem GPU fit, graph against eager launches, and with
+one poisoned problem."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def small_batch(n_problems, seed, p=3, q=2, n_lo=60, n_hi=160, N=256):
+    from paper_2005_06848_amd import inputs
+    rng = np.random.default_rng(seed)
+    probs = []
+    for k in range(n_problems):
+        g = int(rng.integers(2, 5))
+        n = int(rng.integers(n_lo, n_hi))
+        c = inputs.random_case(seed * 100 + k, n, p, q, g, N)
+        probs.append(c)
+    u = probs[0]["u"]
+    return probs, u
+
+
+def concat(probs):
+    y = np.concatenate([c["y"] for c in probs])
+    par = {k: np.concatenate([c["params"][k] for c in probs]) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    return y, par, [c["n"] for c in probs], [c["g"] for c in probs]
+
+
+def split(par, g):
+    out, c0 = [], 0
+    for gk in g:
+        out.append({k: np.asarray(v)[c0:c0 + gk] for k, v in par.items()})
+        c0 += gk
+    return out
+
+
+def test_batched_matches_oracle_fp64(dev, orc):
+    from paper_2005_06848_amd import native
+    probs, u = small_batch(5, 1)
+    y, par, n, g = concat(probs)
+    print("[gpu] batched fp64 5 problems", flush=True)
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(
+        T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()}, T(u, dev), max_iter=6, tol=0.0,
+        precision="fp64")
+    assert np.all(status == 0)
+    fitted = split({k: v.cpu().numpy() for k, v in fit.items() if k in par}, g)
+    for k, c in enumerate(probs):
+        ref = orc.em_fit(c["y"], c["params"], u, max_iter=6, tol=0.0)
+        assert n_iter[k] == ref["n_iter"] == 6
+        np.testing.assert_allclose(trace[k, :7], ref["trace"], rtol=1e-10)
+        for key in ("pi", "mu", "Sigma", "Delta", "nu"):
+            r = ref[key]
+            assert np.max(np.abs(fitted[k][key] - r)) <= 1e-8 * max(np.max(np.abs(r)), 1e-300), (k, key)
+
+
+def test_batched_graph_equals_eager_and_single(dev):
+    from paper_2005_06848_amd import native
+    probs, u = small_batch(7, 2, n_lo=200, n_hi=700, N=512)
+    y, par, n, g = concat(probs)
+    P = {k: T(v, dev) for k, v in par.items()}
+    print("[gpu] batched fp32 graph vs eager", flush=True)
+    fg, tg, ng, sg = native.cfust_em_fit_batched(T(y, dev), n, g, P, T(u, dev), max_iter=12,
+                                                  tol=1e-6, precision="fp32", graph=True)
+    fe, te, ne, se = native.cfust_em_fit_batched(T(y, dev), n, g, P, T(u, dev), max_iter=12,
+                                                  tol=1e-6, precision="fp32", graph=False)
+    assert np.all(sg == 0) and np.all(se == 0)
+    np.testing.assert_array_equal(ng, ne)
+    np.testing.assert_array_equal(np.nan_to_num(tg, nan=7.0), np.nan_to_num(te, nan=7.0))
+    for key in ("pi", "mu", "Sigma", "Delta", "nu"):
+        np.testing.assert_array_equal(fg[key].cpu().numpy(), fe[key].cpu().numpy())
+    # the same problems one by one through the single-problem entry point
+    for k, c in enumerate(probs):
+        single = native.cfust_em_fit(T(c["y"], dev), {kk: T(v, dev) for kk, v in c["params"].items()},
+                                     T(u, dev), max_iter=12, tol=1e-6, precision="fp32")
+        assert single["n_iter"] == ng[k]
+        np.testing.assert_allclose(tg[k, :ng[k] + 1], single["trace"], rtol=1e-12)
+    cfg = native.cfust_batched_config()
+    assert cfg["n_candidates"] >= 4 and cfg["waves_per_block"] in (1, 2, 4)
+
+
+def test_batched_poisoned_problem(dev):
+    from paper_2005_06848_amd import native
+    probs, u = small_batch(6, 3)
+    y, par, n, g = concat(probs)
+    bad = [dict(c) for c in probs]
+    yb = bad[2]["y"].copy()
+    yb[5, 0] = np.nan
+    bad[2] = dict(bad[2], y=yb)
+    y2, par2, _, _ = concat(bad)
+    P = {k: T(v, dev) for k, v in par.items()}
+    f_ok, t_ok, n_ok, s_ok = native.cfust_em_fit_batched(T(y, dev), n, g, P, T(u, dev), max_iter=5,
+                                                          tol=0.0, precision="fp64")
+    f_bad, t_bad, n_bad, s_bad = native.cfust_em_fit_batched(T(y2, dev), n, g, P, T(u, dev),
+                                                              max_iter=5, tol=0.0, precision="fp64")
+    assert s_bad[2] == native.ENONFINITE
+    keep = [k for k in range(6) if k != 2]
+    assert np.all(s_bad[keep] == 0)
+    np.testing.assert_array_equal(t_bad[keep], t_ok[keep])
+    fo = split({k: v.cpu().numpy() for k, v in f_ok.items() if k in par}, g)
+    fb = split({k: v.cpu().numpy() for k, v in f_bad.items() if k in par}, g)
+    for k in keep:
+        for key in ("pi", "mu", "Sigma", "Delta", "nu"):
+            np.testing.assert_array_equal(fb[k][key], fo[k][key])
+
+
+def test_batched_workload4_shape(dev):
+    """A reduced copy of the 64-start workload (n 500-2000, g 2-6, p=q=5,
+    N=1024) runs to completion with per-start stopping."""
+    from paper_2005_06848_amd import inputs, native
+    probs = inputs.batched_problems(16, 500, 2000)
+    u = inputs.qmc_points(1024, 5)
+    y = np.concatenate([c["y"] for c in probs])
+    par = {k: np.concatenate([c["init"][k] for c in probs]) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    n = [c["n"] for c in probs]
+    g = [c["g"] for c in probs]
+    f, tr, it, st = native.cfust_em_fit_batched(T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()},
+                                                T(u, dev), max_iter=20, tol=1e-6, precision="fp32")
+    assert np.all(st == 0), st
+    assert np.all(it >= 2)
+    for k in range(16):
+        tk = tr[k, :it[k] + 1]
+        assert np.all(np.isfinite(tk))
+        assert tk[-1] > tk[0]
