@@ -96,6 +96,49 @@ def precision_form(args, native, L, torch, np, inputs, dev):
     return res
 
 
+def batched_form(args, native, torch, np, inputs, dev):
+    """Batched form: 64 EM starts (n ~ U{5000..50000}, g ~ U{2..6}, p=q=5,
+    N=4096, FP32 integrand), one device-driven loop with hipGraph-captured
+    iterations and autotuned launch shape; compared with fitting the same
+    starts one after another through the single-problem entry point."""
+    print("[bench] batched: generating 64 starts", file=sys.stderr, flush=True)
+    probs = inputs.batched_problems(64)
+    u = inputs.qmc_points(4096, 5)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y = T(np.concatenate([c["y"] for c in probs]))
+    par = {k: T(np.concatenate([c["init"][k] for c in probs])) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    n = [c["n"] for c in probs]
+    g = [c["g"] for c in probs]
+    ut = T(u)
+    it = args.batched_iters
+    # warm-up (also runs the autotuner once for this shape)
+    native.cfust_em_fit_batched(y, n, g, par, ut, max_iter=1, tol=1e-6, precision="fp32")
+    torch.cuda.synchronize()
+    print(f"[bench] batched: fit of 64 starts, up to {it} iterations", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(y, n, g, par, ut, max_iter=it, tol=1e-6,
+                                                             precision="fp32")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    evals = int(sum((int(n_iter[k]) + 1) * n[k] * g[k] for k in range(len(n))))
+    res = {"workload": "64 starts, n~U{5000..50000}, g~U{2..6}, p=q=5, N=4096, fp32 integrand",
+           "iterations_cap": it, "seconds": round(tb, 3), "pair_evals_per_s": round(evals / tb, 1),
+           "n_iter_min": int(n_iter.min()), "n_iter_max": int(n_iter.max()),
+           "n_iter_mean": round(float(n_iter.mean()), 2), "failed": int((status != 0).sum()),
+           "launch_shape": native.cfust_batched_config()}
+    if not args.no_sequential:
+        print("[bench] batched: same starts one by one", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        for k, c in enumerate(probs):
+            native.cfust_em_fit(T(c["y"]), {kk: T(v) for kk, v in c["init"].items()}, ut,
+                                max_iter=it, tol=1e-6, precision="fp32")
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        res["sequential_seconds"] = round(ts, 3)
+        res["speedup_vs_sequential"] = round(ts / tb, 3)
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +151,11 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-form speedup leg (n=200000, p=q=6, g=4, N=8192)")
     ap.add_argument("--form-reps", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form leg (64 starts, p=q=5, N=4096, FP32)")
+    ap.add_argument("--batched-iters", type=int, default=50)
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched leg: skip fitting the starts one by one for comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (traffic calibration)")
     return ap.parse_args()
@@ -196,6 +244,9 @@ def main():
     forms = None
     if not args.no_forms:
         forms = precision_form(args, native, L, torch, np, inputs, dev)
+    if not args.no_batched:
+        forms = forms or {}
+        forms["batched"] = batched_form(args, native, torch, np, inputs, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

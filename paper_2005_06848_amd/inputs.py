@@ -258,7 +258,7 @@ def batched_problems(n_problems: int = 64, n_lo: int = 5000, n_hi: int = 50000,
         true = _true_params_basic(rng, p, q, g, rng.uniform(3, 15, size=g), 2.0,
                                   rng.dirichlet(np.full(g, 5.0)))
         y, z = sample_cfust(rng, n, **true)
-        lab = kmeans_pp(rng, y, g, n_lloyd=10)
+        lab = kmeans_pp(rng, y, g, n_lloyd=10, n_init=2)
         init = init_from_partition(y, lab, g, q)
         probs.append(dict(n=n, p=p, q=q, g=g, y=y, labels=z, true=true, init=init))
     return probs
