@@ -79,6 +79,10 @@ typedef struct cfust_opts {
   int tile;               /* cfust_em_fit_batched: launch shape of the persistent pair
                              kernel, 0 = autotune, else 1 + index into the candidate
                              table (see cfust_batched_config) */
+  struct cfust_surrogate* surrogate; /* optional trained surrogate network: when set,
+                             cfust_estep / cfust_loglik / cfust_em_fit evaluate the two
+                             GHK integrals of every in-range pair with it and the
+                             GHK kernel only for the others (q must match) */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4
@@ -172,6 +176,94 @@ int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_
  * the autotuner's timing of that shape in ms (0 if not tuned).  Returns the
  * number of candidate shapes. */
 int cfust_batched_config(int* waves_per_block, int* chunk, int* waves_per_simd, double* tuned_ms);
+
+/* GHK estimates for M standardised problems (the integrals behind eq. (2) and
+ * the truncated moments of section 2): for sample s, V ~ t_q(0, R_s, dof_s)
+ * with R: device [M][q][q] correlation matrices (symmetric positive definite,
+ * unit diagonal; only the lower triangle is read), bound h: device [M][q],
+ * dof: device [M] (at most 4096 distinct values).  out: device
+ * [M][1 + q + q(q+1)/2] = log P(V <= h) | E[V | V <= h] | E[V V^T | V <= h]
+ * (upper triangle, row by row).  opts->precision selects the integrand type.
+ * CFUST_ENOTPD if some R_s is not positive definite.  These are the labels
+ * the surrogate network learns. */
+int cfust_ghk_batch(int q, int64_t M, const double* h, const double* R, const double* dof,
+                    const double* u, int n_qmc, const cfust_opts* opts, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate network for the two GHK integrals of a pair.
+ *
+ * For pair (j, i) the integrals of eq. (2) and the truncated moments of
+ * section 2 reduce to standardised problems P(V <= h), V ~ t_q(0, R_i, dof)
+ * with R_i the correlation matrix of Lambda_i = I - Delta_i^T Omega_i^-1
+ * Delta_i: integral A at dof nu_i + p, integral B at dof nu_i + p + 2.  A
+ * feature row is  h[q] | r[q(q-1)/2] | dof  (r: entries of R above the
+ * diagonal, row by row), F = q + q(q-1)/2 + 1 doubles; a target row is the
+ * cfust_ghk_batch output, T = 1 + q + q(q+1)/2 doubles.  The network is a
+ * perceptron F -> 256 -> 256 -> 256 -> T with SiLU activations, bf16 weights
+ * and activations on the matrix cores, fp32 accumulation, fp32 master
+ * weights, trained with Adam on a mean squared error of standardised outputs.
+ * A handle owns its device memory; calls that share a handle must not
+ * overlap.  Limits: 1 <= q <= 8.
+ * ------------------------------------------------------------------------- */
+typedef struct cfust_surrogate cfust_surrogate;
+
+#define CFUST_SURR_PARAMS 164672  /* fp32 parameters incl. zero padding */
+#define CFUST_SURR_STD 256        /* standardisation: mean_x[64] | sd_x[64] | mean_y[64] | sd_y[64] */
+
+/* Creates an untrained network for q with the training range
+ * range[6] (host) = h_lo, h_hi (box for every h_m), dof_lo, dof_hi,
+ * r_max (bound on |r|), eig_min (bound on the smallest eigenvalue of R):
+ * the E-step uses the network only for pairs inside it.  Weights are drawn
+ * from a seeded normal of variance 2 / fan_in, biases zero. */
+int cfust_surrogate_create(int q, const double* range, unsigned long long seed,
+                           cfust_surrogate** out);
+void cfust_surrogate_destroy(cfust_surrogate* s);
+
+/* Trains for `epochs` passes over M samples (feat: device [M][F], targ:
+ * device [M][T]) in shuffled minibatches of `batch` rows (a multiple of 64,
+ * at most 65536), learning rate cosine-annealed from lr0 to lr1, per-output
+ * loss weights wo (host [T] or NULL for ones).  The first call sets the
+ * standardisation from this data.  loss_trace: host [epochs] mean training
+ * loss per epoch (or NULL). */
+int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* targ, int64_t M,
+                          int epochs, int batch, double lr0, double lr1, unsigned long long seed,
+                          const float* wo, const cfust_opts* opts, double* loss_trace);
+
+/* One forward and backward pass over M <= 65536 samples without an update:
+ * grad (host [CFUST_SURR_PARAMS]) = gradient of the loss, *loss (host).
+ * Needs the standardisation (set by cfust_surrogate_train or _set_state). */
+int cfust_surrogate_grad(cfust_surrogate* s, const double* feat, const double* targ, int64_t M,
+                         const float* wo, const cfust_opts* opts, float* grad, double* loss);
+
+/* Network outputs for M feature rows: out device [M][T] (de-standardised). */
+int cfust_surrogate_eval(cfust_surrogate* s, const double* feat, int64_t M,
+                         const cfust_opts* opts, double* out);
+
+/* Host copies of the parameters ([CFUST_SURR_PARAMS] fp32) and of the
+ * standardisation ([CFUST_SURR_STD] fp32); either pointer may be NULL. */
+int cfust_surrogate_get_state(const cfust_surrogate* s, float* params, float* stdv);
+int cfust_surrogate_set_state(cfust_surrogate* s, const float* params, const float* stdv);
+
+/* File I/O of a handle (range, standardisation, parameters). */
+int cfust_surrogate_save(const cfust_surrogate* s, const char* path);
+int cfust_surrogate_load(const char* path, cfust_surrogate** out);
+
+/* Pairs the last E-step with this handle sent to the GHK kernel (outside the
+ * training range). */
+int64_t cfust_surrogate_fallback_count(const cfust_surrogate* s);
+
+/* Raw feature rows of every pair at Psi: out device [n*g*2][F], row 2(j g + i)
+ * for integral A and 2(j g + i) + 1 for integral B. */
+int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                        const double* mu, const double* Sigma, const double* Delta,
+                        const double* nu, const cfust_opts* opts, double* out);
+
+/* Test hook of the network's matrix-core product: C[M][N] (device fp32) =
+ * op(A) op(B) with bf16 operands A, B (device, raw 16-bit patterns),
+ * op(A)[m][k] = ta ? A[k][m] : A[m][k], op(B)[k][n] = tb ? B[n][k] : B[k][n]
+ * (leading dimensions M or K and K or N).  M, N multiples of 64, K of 32. */
+int cfust_mlp_gemm(int ta, int tb, int M, int N, int K, const unsigned short* A,
+                   const unsigned short* B, float* C, void* stream);
 
 /* Aitken-accelerated limit l_inf from l^(t-2), l^(t-1), l^(t) (Algorithm 4,
  * read with the denominator 1 - a). Host scalars. */

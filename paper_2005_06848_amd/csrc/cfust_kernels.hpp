@@ -300,6 +300,127 @@ __device__ __forceinline__ int shift_of(double d) { return (int)fmax(d, -1100.0)
 __device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
 
 // ---------------------------------------------------------------------------
+// One GHK integral on one wave (section 2: the q-variate t CDF of eq. (2) and,
+// with MOM, the moments of the truncated t).  V ~ t_Q(0, R, dof), R = C C^T,
+// bound h: ht[m] = h_m / C_mm and Ct[m][l] = C_ml / C_mm (l < m) scale the
+// sequential bounds; s[k] = sqrt(chi2^-1(u_k0; dof)/dof) and rs = 1/s.  Lane
+// t handles points t, t+64, ...; MOM draws all Q coordinates and returns
+// E[V | V <= h] and E[V V^T | V <= h], otherwise the last draw is skipped.
+// Every lane returns log P(V <= h) and the moments.
+// ---------------------------------------------------------------------------
+template <typename T, int Q, bool MOM>
+__device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][Q],
+                                             const double* __restrict__ C,
+                                             const T* __restrict__ s_tab,
+                                             const T* __restrict__ rs_tab,
+                                             const T* __restrict__ uT, const T* __restrict__ ubT,
+                                             int N, int lane, double* logT, double (&m1)[Q],
+                                             double (&m2)[Q][Q]) {
+  constexpr int NT = Q * (Q + 1) / 2;
+  using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
+  Acc<T> b0, b1[MOM ? Q : 1], b2[MOM ? NT : 1];
+  b0.zero();
+  if (MOM) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) b1[m].zero();
+#pragma unroll
+    for (int m = 0; m < NT; ++m) b2[m].zero();
+  }
+  E ref = exp_floor<E>();
+#pragma unroll 1
+  for (int k = lane; k < N; k += 64) {
+    const T s = s_tab[k];
+    T eps[Q];
+    T prod = T(1);
+    E ex = 0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      T bnd = s * ht[m];
+#pragma unroll
+      for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
+      PhiVal<T> cc = phi_eval(bnd);
+      prod *= cc.m;
+      ex += cc.n;
+      if (MOM || m < Q - 1)
+        eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
+    }
+    if (ex > ref + Prec<T>::kRescale) {
+      T f = Prec<T>::ldexp_(T(1), shift_of(ref - ex));
+      b0.scale(f);
+      if (MOM) {
+#pragma unroll
+        for (int m = 0; m < Q; ++m) b1[m].scale(f);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) b2[m].scale(f);
+      }
+      ref = ex;
+    }
+    T wgt = Prec<T>::ldexp_(prod, shift_of(ex - ref));
+    b0.add(wgt);
+    if (MOM) {
+      const T rs = rs_tab[k];
+      T eh[Q];
+#pragma unroll
+      for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) b1[m].add(wgt * eh[m]);
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        T wa = wgt * eh[a];
+#pragma unroll
+        for (int b = a; b < Q; ++b) b2[t++].add(wa * eh[b]);
+      }
+    }
+  }
+  // wave reduction with exponent alignment
+  E R = wave_max(ref);
+  double sc = ldexp(1.0, shift_of(ref - R));
+  double S0 = wave_sum(b0.value() * sc);
+  *logT = log(S0) + R * kLn2 - log((double)N);
+  if (MOM) {
+    double S1[Q], S2[Q][Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) S1[m] = wave_sum(b1[m].value() * sc);
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+#pragma unroll
+      for (int b = a; b < Q; ++b) {
+        double s2 = wave_sum(b2[t++].value() * sc);
+        S2[a][b] = s2;
+        S2[b][a] = s2;
+      }
+    // E[V] = C S1/S0, E[V V^T] = C (S2/S0) C^T
+    const double inv0 = 1.0 / S0;
+    double tmp[Q][Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      double t1 = 0.0;
+#pragma unroll
+      for (int l = 0; l <= a; ++l) t1 += C[a * Q + l] * S1[l];
+      m1[a] = t1 * inv0;
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int l = 0; l <= a; ++l) t2 += C[a * Q + l] * S2[l][b];
+        tmp[a][b] = t2 * inv0;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+#pragma unroll
+      for (int b = 0; b < Q; ++b) {
+        double t2 = 0.0;
+#pragma unroll
+        for (int l = 0; l <= b; ++l) t2 += tmp[a][l] * C[b * Q + l];
+        m2[a][b] = t2;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // one (observation, component) pair on one wave: lanes split the QMC points
 // of both GHK integrals; after the wave reductions every lane holds the same
 // record and lane t returns entry t of
@@ -361,139 +482,10 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
   }
 
   // ---- a5 / a6: the two GHK integrals over this lane's points ----
-  using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
-  Acc<T> accA;
-  accA.zero();
-  E refA = exp_floor<E>();
-  Acc<T> b0, b1[Q], b2[NT];
-  b0.zero();
-#pragma unroll
-  for (int m = 0; m < Q; ++m) b1[m].zero();
-#pragma unroll
-  for (int m = 0; m < NT; ++m) b2[m].zero();
-  E refB = exp_floor<E>();
-
-  // integral A: dof nu+p, draws for coordinates 1..Q-1
-#pragma unroll 1
-  for (int k = lane; k < N; k += 64) {
-    const T s = sAi[k];
-    T eps[Q];
-    T prod = T(1);
-    E ex = 0;
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      T bnd = s * htA[m];
-#pragma unroll
-      for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
-      PhiVal<T> cc = phi_eval(bnd);
-      prod *= cc.m;
-      ex += cc.n;
-      if (m < Q - 1) eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
-    }
-    if (ex > refA + Prec<T>::kRescale) {
-      accA.scale(Prec<T>::ldexp_(T(1), shift_of(refA - ex)));
-      refA = ex;
-    }
-    accA.add(Prec<T>::ldexp_(prod, shift_of(ex - refA)));
-  }
-  // integral B: dof nu+p+2, draws for all Q coordinates, moments of eps/s
-  if (MOM) {
-#pragma unroll 1
-    for (int k = lane; k < N; k += 64) {
-      const T s = sBi[k];
-      const T rs = rsBi[k];
-      T eps[Q];
-      T prod = T(1);
-      E ex = 0;
-#pragma unroll
-      for (int m = 0; m < Q; ++m) {
-        T bnd = s * htB[m];
-#pragma unroll
-        for (int l = 0; l < m; ++l) bnd -= Ct[m][l] * eps[l];
-        PhiVal<T> cc = phi_eval(bnd);
-        prod *= cc.m;
-        ex += cc.n;
-        eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
-      }
-      if (ex > refB + Prec<T>::kRescale) {
-        T f = Prec<T>::ldexp_(T(1), shift_of(refB - ex));
-        b0.scale(f);
-#pragma unroll
-        for (int m = 0; m < Q; ++m) b1[m].scale(f);
-#pragma unroll
-        for (int m = 0; m < NT; ++m) b2[m].scale(f);
-        refB = ex;
-      }
-      T wgt = Prec<T>::ldexp_(prod, shift_of(ex - refB));
-      T eh[Q];
-#pragma unroll
-      for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
-      b0.add(wgt);
-#pragma unroll
-      for (int m = 0; m < Q; ++m) b1[m].add(wgt * eh[m]);
-      int t = 0;
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        T wa = wgt * eh[a];
-#pragma unroll
-        for (int b = a; b < Q; ++b) b2[t++].add(wa * eh[b]);
-      }
-    }
-  }
-
-  // ---- wave reductions with exponent alignment ----
   double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
-  {
-    E R = wave_max(refA);
-    double sc = ldexp(1.0, shift_of(refA - R));
-    double S = wave_sum(accA.value() * sc);
-    logTA = log(S) + R * kLn2 - log((double)N);
-  }
-  if (MOM) {
-    E R = wave_max(refB);
-    double sc = ldexp(1.0, shift_of(refB - R));
-    double S0 = wave_sum(b0.value() * sc);
-    double S1[Q], S2[Q][Q];
-#pragma unroll
-    for (int m = 0; m < Q; ++m) S1[m] = wave_sum(b1[m].value() * sc);
-    int t = 0;
-#pragma unroll
-    for (int a = 0; a < Q; ++a)
-#pragma unroll
-      for (int b = a; b < Q; ++b) {
-        double s2 = wave_sum(b2[t++].value() * sc);
-        S2[a][b] = s2;
-        S2[b][a] = s2;
-      }
-    logTB = log(S0) + R * kLn2 - log((double)N);
-    // E[V] = C S1/S0, E[V V^T] = C (S2/S0) C^T (V standardised, V <= h_B)
-    const double inv0 = 1.0 / S0;
-    double tmp[Q][Q];
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      double t1 = 0.0;
-#pragma unroll
-      for (int l = 0; l <= a; ++l) t1 += cp[cl.C + a * Q + l] * S1[l];
-      m1[a] = t1 * inv0;
-#pragma unroll
-      for (int b = 0; b < Q; ++b) {
-        double t2 = 0.0;
-#pragma unroll
-        for (int l = 0; l <= a; ++l) t2 += cp[cl.C + a * Q + l] * S2[l][b];
-        tmp[a][b] = t2 * inv0;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < Q; ++a)
-#pragma unroll
-      for (int b = 0; b < Q; ++b) {
-        double t2 = 0.0;
-#pragma unroll
-        for (int l = 0; l <= b; ++l) t2 += tmp[a][l] * cp[cl.C + b * Q + l];
-        m2[a][b] = t2;
-      }
-  }
+  ghk_integral<T, Q, false>(htA, Ct, cp + cl.C, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
+  if (MOM) ghk_integral<T, Q, true>(htB, Ct, cp + cl.C, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
 
   // ---- a7: pair assembly (wave-uniform values; lane t stores entry t) ----
   const double aa = 0.5 * (v + p);
@@ -557,6 +549,97 @@ __global__ __launch_bounds__(256) void pair_kernel(
     return;
   }
   if (lane < record_width<Q, MOM>()) pairbuf[pair * W + lane] = out;
+}
+
+// ---------------------------------------------------------------------------
+// GHK integrals for a batch of standardised problems (one wave per sample):
+// V ~ t_Q(0, R_s, dof_s) for a correlation matrix R_s (factored here,
+// R_s = C C^T), bound h_s; output per sample
+// log P(V <= h) | E[V | V <= h] (Q) | E[V V^T | V <= h] (upper triangle).
+// tab[s] selects the chi scale tables of the sample's dof.
+// ---------------------------------------------------------------------------
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void ghk_batch_kernel(
+    int64_t M, const double* __restrict__ h, const double* __restrict__ R,
+    const int* __restrict__ tab, const T* __restrict__ sB, const T* __restrict__ rsB,
+    const T* __restrict__ uT, const T* __restrict__ ubT, int N, double* __restrict__ out,
+    int* __restrict__ status) {
+  constexpr int NT = Q * (Q + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t smp = (int64_t)blockIdx.x * 4 + wv;
+  if (smp >= M || status[0] != kOk) return;
+  const double* hs = h + smp * Q;
+  const double* Rs = R + smp * Q * Q;
+  double Cs[Q * Q];
+  bool pd = true;
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int b = 0; b < Q; ++b) Cs[a * Q + b] = (b <= a) ? Rs[a * Q + b] : 0.0;
+#pragma unroll
+  for (int jc = 0; jc < Q; ++jc) {
+    double s = Cs[jc * Q + jc];
+#pragma unroll
+    for (int k = 0; k < jc; ++k) s -= Cs[jc * Q + k] * Cs[jc * Q + k];
+    pd = pd && s > 0.0;
+    const double cjj = sqrt(fmax(s, 1e-300));
+    Cs[jc * Q + jc] = cjj;
+#pragma unroll
+    for (int r = jc + 1; r < Q; ++r) {
+      double t = Cs[r * Q + jc];
+#pragma unroll
+      for (int k = 0; k < jc; ++k) t -= Cs[r * Q + k] * Cs[jc * Q + k];
+      Cs[r * Q + jc] = t / cjj;
+    }
+  }
+  if (!pd) {
+    if (lane == 0) set_status(status, kENotPD, -1);
+    return;
+  }
+  T ht[Q], Ct[Q][Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    double cmm = Cs[m * Q + m];
+    ht[m] = (T)(hs[m] / cmm);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(Cs[m * Q + l] / cmm) : T(0);
+  }
+  const int ti = tab[smp];
+  double logT, m1[Q], m2[Q][Q];
+  ghk_integral<T, Q, true>(ht, Ct, Cs, sB + (size_t)ti * N, rsB + (size_t)ti * N, uT, ubT, N, lane,
+                           &logT, m1, m2);
+  double o = logT;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) o = (lane == 1 + a) ? m1[a] : o;
+  int t = 1 + Q;
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int b = a; b < Q; ++b) {
+      o = (lane == t) ? m2[a][b] : o;
+      ++t;
+    }
+  if (lane < 1 + Q + NT) out[smp * (1 + Q + NT) + lane] = o;
+}
+
+// chi scale tables for a list of degrees of freedom: s[i][k], 1/s[i][k]
+template <typename T>
+__global__ void chi_list_kernel(const double* __restrict__ dofs, int nd,
+                                const double* __restrict__ u, int N, int q1, T* __restrict__ s,
+                                T* __restrict__ rs, int* status) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nd * N) return;
+  int i = (int)(t / N);
+  int k = (int)(t - (int64_t)i * N);
+  double dof = dofs[i];
+  if (!(dof > 0.0) || !isfinite(dof)) {
+    set_status(status, kEInval, -1);
+    return;
+  }
+  double v = sqrt(chi2_quantile(u[(size_t)k * q1], dof) / dof);
+  s[t] = (T)v;
+  rs[t] = (T)(1.0 / v);
 }
 
 // ---------------------------------------------------------------------------

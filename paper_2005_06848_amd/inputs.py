@@ -87,6 +87,54 @@ def kappa_nu(nu: float) -> float:
     return math.sqrt(nu / math.pi) * math.exp(_gammaln((nu - 1) / 2.0) - _gammaln(nu / 2.0))
 
 
+def lkj_corr_batch(rng: np.random.Generator, m: int, d: int, eta: float) -> np.ndarray:
+    """m random correlation matrices from LKJ(eta) by the onion method
+    (Lewandowski, Kurowicka & Joe 2009): grow each matrix one row at a time,
+    the new row's squared length drawn from a Beta and its direction uniform,
+    mapped through the current Cholesky factor.  Returns [m][d][d]."""
+    R = np.zeros((m, d, d))
+    idx = np.arange(d)
+    R[:, idx, idx] = 1.0
+    if d == 1:
+        return R
+    beta = eta + (d - 2) / 2.0
+    r = 2.0 * rng.beta(beta, beta, size=m) - 1.0
+    R[:, 0, 1] = r
+    R[:, 1, 0] = r
+    for k in range(2, d):
+        beta -= 0.5
+        yk = rng.beta(k / 2.0, beta, size=m)
+        z = rng.standard_normal((m, k))
+        w = np.sqrt(yk)[:, None] * z / np.linalg.norm(z, axis=1, keepdims=True)
+        L = np.linalg.cholesky(R[:, :k, :k])
+        qv = np.einsum("mab,mb->ma", L, w)
+        R[:, :k, k] = qv
+        R[:, k, :k] = qv
+    return R
+
+
+def lkj_corr(rng: np.random.Generator, d: int, eta: float) -> np.ndarray:
+    """One random correlation matrix from LKJ(eta) (see lkj_corr_batch)."""
+    return lkj_corr_batch(rng, 1, d, eta)[0]
+
+
+def surrogate_samples(rng: np.random.Generator, m: int, q: int, h_lo: float = -4.0,
+                      h_hi: float = 6.0, dof_lo: float = 5.0, dof_hi: float = 20.0,
+                      dof_step: float = 0.25, eta: float = 2.0, h_extra=None):
+    """Inputs of the surrogate's training set: correlation matrices R ~ LKJ(eta),
+    degrees of freedom uniform on a grid of step dof_step in [dof_lo, dof_hi],
+    truncation points h uniform on [h_lo, h_hi]^q (or, for the first rows,
+    the points given in h_extra).  Returns h [m][q], R [m][q][q], dof [m]."""
+    R = lkj_corr_batch(rng, m, q, eta)
+    grid = np.arange(dof_lo, dof_hi + 1e-9, dof_step)
+    dof = rng.choice(grid, size=m)
+    h = rng.uniform(h_lo, h_hi, size=(m, q))
+    if h_extra is not None:
+        k = min(len(h_extra), m)
+        h[:k] = h_extra[:k]
+    return np.ascontiguousarray(h), np.ascontiguousarray(R), np.ascontiguousarray(dof)
+
+
 # ----------------------------------------------------------------------------
 # starting values
 # ----------------------------------------------------------------------------

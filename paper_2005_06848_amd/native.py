@@ -42,6 +42,7 @@ class Opts(ctypes.Structure):
         ("prof_ms", ctypes.c_void_p),
         ("graph", ctypes.c_int),
         ("tile", ctypes.c_int),
+        ("surrogate", ctypes.c_void_p),
     ]
 
 
@@ -99,6 +100,36 @@ def _lib():
         L.cfust_batched_config.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                            ctypes.POINTER(d)]
         L.cfust_batched_config.restype = i
+        L.cfust_ghk_batch.argtypes = [i, i64, P, P, P, P, i, ctypes.POINTER(Opts), P]
+        L.cfust_ghk_batch.restype = i
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.cfust_surrogate_create.argtypes = [i, ctypes.POINTER(d), ctypes.c_ulonglong,
+                                             ctypes.POINTER(P)]
+        L.cfust_surrogate_create.restype = i
+        L.cfust_surrogate_destroy.argtypes = [P]
+        L.cfust_surrogate_destroy.restype = None
+        L.cfust_surrogate_train.argtypes = [P, P, P, i64, i, i, d, d, ctypes.c_ulonglong, f32p,
+                                            ctypes.POINTER(Opts), ctypes.POINTER(d)]
+        L.cfust_surrogate_train.restype = i
+        L.cfust_surrogate_grad.argtypes = [P, P, P, i64, f32p, ctypes.POINTER(Opts), f32p,
+                                           ctypes.POINTER(d)]
+        L.cfust_surrogate_grad.restype = i
+        L.cfust_surrogate_eval.argtypes = [P, P, i64, ctypes.POINTER(Opts), P]
+        L.cfust_surrogate_eval.restype = i
+        L.cfust_surrogate_get_state.argtypes = [P, f32p, f32p]
+        L.cfust_surrogate_get_state.restype = i
+        L.cfust_surrogate_set_state.argtypes = [P, f32p, f32p]
+        L.cfust_surrogate_set_state.restype = i
+        L.cfust_surrogate_save.argtypes = [P, ctypes.c_char_p]
+        L.cfust_surrogate_save.restype = i
+        L.cfust_surrogate_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(P)]
+        L.cfust_surrogate_load.restype = i
+        L.cfust_surrogate_fallback_count.argtypes = [P]
+        L.cfust_surrogate_fallback_count.restype = i64
+        L.cfust_pair_features.argtypes = [P, i64, i, i, i, P, P, P, P, P, ctypes.POINTER(Opts), P]
+        L.cfust_pair_features.restype = i
+        L.cfust_mlp_gemm.argtypes = [i, i, i, i, i, P, P, P, P]
+        L.cfust_mlp_gemm.restype = i
         L.cfust_strerror.argtypes = [i]
         L.cfust_strerror.restype = ctypes.c_char_p
         _LIB = L
@@ -122,7 +153,8 @@ def _ptr(t):
 
 
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
-              nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0):
+              nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0,
+              surrogate=None):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -142,6 +174,8 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
         o.prof_ms = ctypes.cast(prof, ctypes.c_void_p)
     o.graph = int(bool(graph))
     o.tile = int(tile)
+    if surrogate is not None:
+        o.surrogate = surrogate.handle
     return o
 
 
@@ -299,3 +333,177 @@ def cfust_batched_config():
     n = _lib().cfust_batched_config(ctypes.byref(w), ctypes.byref(c), ctypes.byref(s), ctypes.byref(ms))
     return dict(waves_per_block=w.value, chunk=c.value, waves_per_simd=s.value, tuned_ms=ms.value,
                 n_candidates=n)
+
+
+def cfust_ghk_batch(h, R, dof, u, **opt):
+    """GHK estimates for standardised problems V ~ t_q(0, R, dof) truncated to
+    V <= h: returns [M][1+q+q(q+1)/2] (log P(V<=h), E[V|V<=h], upper triangle
+    of E[VV^T|V<=h]); R: correlation matrices [M][q][q]."""
+    h = _dev(h, "h")
+    R = _dev(R, "R")
+    dof = _dev(dof, "dof")
+    u = _dev(u, "u")
+    M, q = h.shape
+    if R.shape != (M, q, q) or dof.shape != (M,):
+        raise ValueError("R must be [M][q][q] and dof [M]")
+    out = torch.empty((M, 1 + q + q * (q + 1) // 2), dtype=torch.float64, device=h.device)
+    o = make_opts(**opt)
+    rc = _lib().cfust_ghk_batch(q, M, _ptr(h), _ptr(R), _ptr(dof), _ptr(u), u.shape[0],
+                                ctypes.byref(o), _ptr(out))
+    if rc:
+        raise CfustError(rc, "cfust_ghk_batch")
+    return out
+
+
+SURR_PARAMS = 164672
+SURR_STD = 256
+
+
+def feat_width(q):
+    return q + q * (q - 1) // 2 + 1
+
+
+def targ_width(q):
+    return 1 + q + q * (q + 1) // 2
+
+
+def _f32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Surrogate:
+    """Handle of the surrogate network (cfust_surrogate_*)."""
+
+    def __init__(self, handle, q):
+        self.handle = handle
+        self.q = q
+
+    @classmethod
+    def create(cls, q, range_, seed=0):
+        import numpy as np
+        r = np.ascontiguousarray(range_, dtype=np.float64)
+        if r.shape != (6,):
+            raise ValueError("range is h_lo, h_hi, dof_lo, dof_hi, r_max, eig_min")
+        h = ctypes.c_void_p()
+        rc = _lib().cfust_surrogate_create(q, r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           int(seed), ctypes.byref(h))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_create")
+        return cls(h, q)
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        rc = _lib().cfust_surrogate_load(os.fsencode(path), ctypes.byref(h))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_load")
+        with open(path, "rb") as fh:
+            q = int.from_bytes(fh.read(16)[12:16], "little", signed=True)
+        return cls(h, q)
+
+    def save(self, path):
+        rc = _lib().cfust_surrogate_save(self.handle, os.fsencode(path))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_save")
+
+    def close(self):
+        if self.handle is not None and _LIB is not None:
+            _LIB.cfust_surrogate_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, feat, targ, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=0, wo=None, **opt):
+        import numpy as np
+        feat = _dev(feat, "feat")
+        targ = _dev(targ, "targ")
+        trace = (ctypes.c_double * max(epochs, 1))()
+        w = None if wo is None else np.ascontiguousarray(wo, dtype=np.float32)
+        o = make_opts(**opt)
+        rc = _lib().cfust_surrogate_train(self.handle, _ptr(feat), _ptr(targ), feat.shape[0],
+                                          int(epochs), int(batch), float(lr0), float(lr1),
+                                          int(seed), None if w is None else _f32p(w),
+                                          ctypes.byref(o), trace)
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_train")
+        return list(trace)[:epochs]
+
+    def grad(self, feat, targ, wo=None, **opt):
+        import numpy as np
+        feat = _dev(feat, "feat")
+        targ = _dev(targ, "targ")
+        g = np.empty(SURR_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double(0)
+        w = None if wo is None else np.ascontiguousarray(wo, dtype=np.float32)
+        o = make_opts(**opt)
+        rc = _lib().cfust_surrogate_grad(self.handle, _ptr(feat), _ptr(targ), feat.shape[0],
+                                         None if w is None else _f32p(w), ctypes.byref(o),
+                                         _f32p(g), ctypes.byref(loss))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_grad")
+        return g, loss.value
+
+    def eval(self, feat, **opt):
+        feat = _dev(feat, "feat")
+        M, F = feat.shape
+        q = {feat_width(k): k for k in range(1, 9)}[F]
+        out = torch.empty((M, targ_width(q)), dtype=torch.float64, device=feat.device)
+        o = make_opts(**opt)
+        rc = _lib().cfust_surrogate_eval(self.handle, _ptr(feat), M, ctypes.byref(o), _ptr(out))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_eval")
+        return out
+
+    def get_state(self):
+        import numpy as np
+        p = np.empty(SURR_PARAMS, dtype=np.float32)
+        s = np.empty(SURR_STD, dtype=np.float32)
+        rc = _lib().cfust_surrogate_get_state(self.handle, _f32p(p), _f32p(s))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_get_state")
+        return p, s
+
+    def set_state(self, params=None, stdv=None):
+        import numpy as np
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        s = None if stdv is None else np.ascontiguousarray(stdv, dtype=np.float32)
+        rc = _lib().cfust_surrogate_set_state(self.handle, None if p is None else _f32p(p),
+                                              None if s is None else _f32p(s))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_set_state")
+
+    def fallback_count(self):
+        return int(_lib().cfust_surrogate_fallback_count(self.handle))
+
+
+def cfust_pair_features(y, params, **opt):
+    """Raw feature rows (h | correlations | dof) of both integrals of every
+    pair: [n*g*2][q + q(q-1)/2 + 1]."""
+    y = _dev(y, "y")
+    (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
+    n = y.shape[0]
+    out = torch.empty((2 * n * g, feat_width(q)), dtype=torch.float64, device=y.device)
+    o = make_opts(**opt)
+    rc = _lib().cfust_pair_features(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma),
+                                    _ptr(Delta), _ptr(nu), ctypes.byref(o), _ptr(out))
+    if rc:
+        raise CfustError(rc, "cfust_pair_features")
+    return out
+
+
+def cfust_mlp_gemm(ta, tb, A, B, M, N, K):
+    """Matrix-core product of bf16 operands (int16 tensors holding the bit
+    patterns): C[M][N] fp32 = op(A) op(B)."""
+    for t, nm in ((A, "A"), (B, "B")):
+        if not t.is_cuda or t.dtype != torch.int16 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous int16 CUDA tensor")
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    rc = _lib().cfust_mlp_gemm(int(ta), int(tb), M, N, K, _ptr(A), _ptr(B), _ptr(C),
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc:
+        raise CfustError(rc, "cfust_mlp_gemm")
+    return C

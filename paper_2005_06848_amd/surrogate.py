@@ -1,0 +1,149 @@
+"""Training set and training of the surrogate network for the GHK integrals.
+
+Training set (q = 6): correlation matrices R ~ LKJ(2) (onion method),
+degrees of freedom uniform on a 0.25 grid in [5, 20], truncation points h
+half uniform on [-4, 6]^6 and half taken from the h values of the pairs of
+an EM run on data shaped like the surrogate workload (n obs, p = q = 6,
+g = 4), logged at the starting values and at later iterates.  Labels are
+GHK estimates by the library's own kernel (cfust_ghk_batch) with 2^14
+points.  Training runs the library's BF16 matrix-core forward/backward and
+Adam kernels (cfust_surrogate_train).
+
+Run:  python -m paper_2005_06848_amd.surrogate --out <file>
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import inputs
+from . import native as nat
+
+Q = 6
+H_LO, H_HI = -4.0, 6.0
+DOF_LO, DOF_HI = 5.0, 20.0
+R_MAX = 0.95
+EIG_PERCENTILE = 1.0
+N_LABEL = 1 << 14
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "surrogate_q6.bin")
+
+
+def log(msg):
+    print(f"[surrogate] {msg}", flush=True)
+
+
+def feature_rows(h, R, dof):
+    """(h | entries of R above the diagonal, row by row | dof) per sample."""
+    q = h.shape[1]
+    iu = np.triu_indices(q, 1)
+    return np.ascontiguousarray(np.concatenate([h, R[:, iu[0], iu[1]], dof[:, None]], axis=1))
+
+
+def eig_threshold(R):
+    """The EIG_PERCENTILE-th percentile of the smallest eigenvalue of R."""
+    return float(np.percentile(np.linalg.eigvalsh(R)[:, 0], EIG_PERCENTILE))
+
+
+def proposal_h(n_obs=100_000, iterates=(0, 3, 10, 30), seed=0, device="cuda"):
+    """h rows of integrals A and B of every pair, logged along an FP32 EM run
+    on data shaped like the surrogate workload; rows inside the h box only."""
+    c = inputs.config(5, n=n_obs)
+    y = torch.tensor(c["y"], device=device)
+    u = torch.tensor(c["u"], device=device)
+    par = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=device)
+           for k, v in c["init"].items()}
+    rows = []
+    done = 0
+    for it in iterates:
+        if it > done:
+            res = nat.cfust_em_fit(y, par, u, max_iter=it - done, tol=0.0, precision="fp32")
+            par = {k: res[k] for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+            done = it
+        f = nat.cfust_pair_features(y, par)[:, :Q].cpu().numpy()
+        keep = np.all((f >= H_LO) & (f <= H_HI), axis=1)
+        rows.append(f[keep])
+        log(f"proposal: iterate {it}: {keep.sum()} of {len(keep)} h rows in the box")
+    out = np.concatenate(rows)
+    rng = np.random.default_rng(seed)
+    return out[rng.permutation(len(out))]
+
+
+def label(h, R, dof, u, chunk=1 << 18, device="cuda"):
+    """GHK labels (log T | E[V] | E[V V^T] upper) by the library kernel."""
+    out = []
+    for s in range(0, len(h), chunk):
+        e = min(len(h), s + chunk)
+        out.append(nat.cfust_ghk_batch(torch.tensor(h[s:e], device=device),
+                                       torch.tensor(R[s:e], device=device),
+                                       torch.tensor(dof[s:e], device=device), u))
+    return torch.cat(out)
+
+
+def training_set(m, seed=1, proposal=None, n_label=N_LABEL, device="cuda"):
+    """Feature rows (device [m][22]), labels (device [m][28]) and the raw R."""
+    rng = np.random.default_rng(seed)
+    h_extra = None
+    if proposal is not None and len(proposal):
+        k = m // 2
+        h_extra = proposal[rng.integers(0, len(proposal), size=k)]
+    h, R, dof = inputs.surrogate_samples(rng, m, Q, H_LO, H_HI, DOF_LO, DOF_HI, 0.25, 2.0, h_extra)
+    u = torch.tensor(inputs.qmc_points(n_label, Q, seed=0x51), device=device)
+    targ = label(h, R, dof, u, device=device)
+    feat = torch.tensor(feature_rows(h, R, dof), device=device)
+    return feat, targ, R
+
+
+def output_weights(q=Q):
+    """Loss weight per output: log T counts as much as all moments together."""
+    T = 1 + q + q * (q + 1) // 2
+    w = np.ones(T, dtype=np.float32)
+    w[0] = T - 1
+    return w
+
+
+def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, n_obs=100_000,
+          device="cuda"):
+    t0 = time.time()
+    prop = proposal_h(n_obs=n_obs, device=device)
+    log(f"proposal rows {len(prop)} ({time.time() - t0:.1f} s)")
+    feat, targ, R = training_set(m, seed=seed, proposal=prop, device=device)
+    torch.cuda.synchronize()
+    log(f"training set {m} samples labelled ({time.time() - t0:.1f} s)")
+    rng_ = [H_LO, H_HI, DOF_LO, DOF_HI, R_MAX, eig_threshold(R)]
+    net = nat.Surrogate.create(Q, rng_, seed=seed)
+    trace = []
+    step = 10
+    for e0 in range(0, epochs, step):
+        ne = min(step, epochs - e0)
+        # one cosine schedule over all epochs, split into calls of `step` epochs
+        a = 0.5 * (1 + np.cos(np.pi * e0 / epochs))
+        b = 0.5 * (1 + np.cos(np.pi * (e0 + ne) / epochs))
+        lra = lr1 + (lr0 - lr1) * a
+        lrb = lr1 + (lr0 - lr1) * b
+        trace += net.train(feat, targ, ne, batch=batch, lr0=lra, lr1=lrb, seed=seed + e0,
+                           wo=output_weights())
+        log(f"epoch {e0 + ne}: loss {trace[-1]:.3e} ({time.time() - t0:.1f} s)")
+    return net, trace, rng_
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--samples", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr0", type=float, default=2e-3)
+    ap.add_argument("--lr1", type=float, default=2e-6)
+    ap.add_argument("--seed", type=int, default=7)
+    a = ap.parse_args()
+    net, trace, rng_ = train(a.samples, a.epochs, a.batch, a.lr0, a.lr1, a.seed)
+    net.save(a.out)
+    log(f"saved {a.out}; range {rng_}; final loss {trace[-1]:.3e}")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+"""Surrogate form: the BF16 matrix-core network kernels and their use in the
+E-step.
+
+* the matrix-core product against numpy on bf16-exact operands (all four
+  operand layouts), which also pins the MFMA lane layout;
+* the GHK label kernel (cfust_ghk_batch) against the FP64 oracle;
+* the network gradient against the FP64 CPU reference with bf16-rounded
+  weights, inputs and activations (1e-4 relative per parameter block);
+* training lowers the loss;
+* pair features against their definition;
+* pairs outside the training range go through the GHK kernel unchanged.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def bf16_bits(x):
+    """float array -> (int16 bit patterns, the bf16 values as float64)."""
+    from oracle import mlp_oracle as mo
+    v = mo.to_bf16(x)
+    bits = (v.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return np.ascontiguousarray(bits), v
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_mlp_gemm_layouts(dev, ta, tb):
+    import torch
+    from paper_2005_06848_amd import native
+    M, N, K = 128, 192, 96
+    rng = np.random.default_rng(10 + 2 * ta + tb)
+    a_bits, a = bf16_bits(rng.standard_normal((K, M) if ta else (M, K)))
+    b_bits, b = bf16_bits(rng.standard_normal((N, K) if tb else (K, N)))
+    print(f"[gpu] gemm ta={ta} tb={tb} M={M} N={N} K={K}", flush=True)
+    C = native.cfust_mlp_gemm(ta, tb, torch.tensor(a_bits, device=dev),
+                              torch.tensor(b_bits, device=dev), M, N, K).cpu().numpy()
+    opa = a.T if ta else a
+    opb = b.T if tb else b
+    ref = opa @ opb
+    scale = np.abs(opa) @ np.abs(opb)
+    assert np.max(np.abs(C - ref) / scale) < 1e-5
+
+
+def test_ghk_batch_matches_oracle(dev):
+    import oracle as orc
+    from paper_2005_06848_amd import inputs, native
+    rng = np.random.default_rng(3)
+    q, m = 6, 24
+    h, R, dof = inputs.surrogate_samples(rng, m, q)
+    u = inputs.qmc_points(1024, q)
+    print(f"[gpu] ghk_batch q={q} M={m} N=1024", flush=True)
+    out = native.cfust_ghk_batch(T(h, dev), T(R, dev), T(dof, dev), T(u, dev)).cpu().numpy()
+    iu = np.triu_indices(q)
+    for s in range(m):
+        lt, ev, evv = orc.ghk(h[s], np.linalg.cholesky(R[s]), dof[s], u)
+        ref = np.concatenate([[lt], ev, evv[iu]])
+        np.testing.assert_allclose(out[s], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def test_ghk_batch_rejects_indefinite(dev):
+    from paper_2005_06848_amd import inputs, native
+    q = 3
+    R = np.eye(q)[None].repeat(2, 0)
+    R[1, 0, 1] = R[1, 1, 0] = 1.2
+    with pytest.raises(native.CfustError) as ei:
+        native.cfust_ghk_batch(T(np.zeros((2, q)), dev), T(R, dev), T(np.array([5.0, 5.0]), dev),
+                               T(inputs.qmc_points(64, q), dev))
+    assert ei.value.code == native.ENOTPD
+
+
+def _net_and_batch(dev, seed, m):
+    from paper_2005_06848_amd import inputs, native
+    rng = np.random.default_rng(seed)
+    q = 6
+    F, Tw = native.feat_width(q), native.targ_width(q)
+    net = native.Surrogate.create(q, [-4, 6, 5, 20, 0.95, 0.01], seed=seed)
+    h, R, dof = inputs.surrogate_samples(rng, m, q)
+    from paper_2005_06848_amd.surrogate import feature_rows
+    feat = feature_rows(h, R, dof)
+    targ = rng.standard_normal((m, Tw)) * 2.0 + 0.5
+    stdv = np.zeros(native.SURR_STD, dtype=np.float32)
+    stdv[:F] = feat.mean(0)
+    stdv[64:64 + F] = np.maximum(feat.std(0), 1e-3)
+    stdv[64 + F:128] = 1.0
+    stdv[128:128 + Tw] = targ.mean(0)
+    stdv[192:192 + Tw] = targ.std(0)
+    stdv[192 + Tw:] = 1.0
+    net.set_state(None, stdv)
+    return net, feat, targ, stdv
+
+
+def test_surrogate_gradient_matches_cpu_reference(dev):
+    from oracle import mlp_oracle as mo
+    from paper_2005_06848_amd import native
+    m = 512
+    net, feat, targ, stdv = _net_and_batch(dev, 5, m)
+    wo = np.linspace(0.5, 2.0, targ.shape[1]).astype(np.float32)
+    print(f"[gpu] surrogate grad M={m}", flush=True)
+    g, loss = net.grad(T(feat, dev), T(targ, dev), wo=wo)
+    theta, _ = net.get_state()
+    F = feat.shape[1]
+    X = np.zeros((m, 64))
+    X[:, :F] = ((feat - stdv[:F].astype(np.float64)) / stdv[64:64 + F].astype(np.float64)
+                ).astype(np.float32)
+    Tw = targ.shape[1]
+    Ts = ((targ - stdv[128:128 + Tw].astype(np.float64)) / stdv[192:192 + Tw].astype(np.float64)
+          ).astype(np.float32).astype(np.float64)
+    ref_loss, ref = mo.loss_and_grad(theta.astype(np.float64), X, Ts, wo, bf16=True)
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    errs = {}
+    for l, ((n, k), (ow, ob)) in enumerate(zip(mo.SHAPES, mo.OFFSETS)):
+        for lo, hi, nm in ((ow, ow + n * k, "W"), (ob, ob + n, "b")):
+            errs[f"{nm}{l}"] = np.linalg.norm(g[lo:hi] - ref[lo:hi]) / np.linalg.norm(ref[lo:hi])
+    print("  relative gradient errors:", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-4, errs
+
+
+def test_surrogate_training_lowers_loss(dev):
+    from paper_2005_06848_amd import inputs, native
+    from paper_2005_06848_amd.surrogate import feature_rows
+    rng = np.random.default_rng(11)
+    q, m = 6, 16384
+    h, R, dof = inputs.surrogate_samples(rng, m, q)
+    u = T(inputs.qmc_points(1024, q), dev)
+    print(f"[gpu] surrogate training M={m}", flush=True)
+    targ = native.cfust_ghk_batch(T(h, dev), T(R, dev), T(dof, dev), u)
+    feat = T(feature_rows(h, R, dof), dev)
+    net = native.Surrogate.create(q, [-4, 6, 5, 20, 0.95, 0.01], seed=1)
+    t = targ.cpu().numpy()
+    trace = net.train(feat, targ, 1, batch=1024, lr0=1e-9, lr1=1e-9)  # sets the scaling only
+    before = np.mean((net.eval(feat).cpu().numpy() - t) ** 2, 0)
+    trace = net.train(feat, targ, 8, batch=1024, lr0=2e-3, lr1=2e-4)
+    print("  loss trace", ["%.3e" % x for x in trace])
+    assert all(np.isfinite(trace)) and all(b < a for a, b in zip(trace, trace[1:]))
+    after = np.mean((net.eval(feat).cpu().numpy() - t) ** 2, 0)
+    print("  eval MSE after / before:", np.round(after / before, 3).tolist())
+    assert np.all(after < 0.5 * before)
+
+
+def test_pair_features_definition(dev):
+    """h^A = D^-1 c sqrt((nu+p)/(nu+d)), h^B with nu+p+2, R the correlation of
+    Lambda = I - Delta^T Omega^-1 Delta, dofs nu+p and nu+p+2."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=300)
+    par = c["true"]
+    print("[gpu] pair features n=300", flush=True)
+    f = native.cfust_pair_features(T(c["y"], dev), {k: T(v, dev) for k, v in par.items()}
+                                   ).cpu().numpy()
+    p, q, g = c["p"], c["q"], c["g"]
+    iu = np.triu_indices(q, 1)
+    for i in range(g):
+        S, D, nu, mu = par["Sigma"][i], par["Delta"][i], par["nu"][i], par["mu"][i]
+        Om = S + D @ D.T
+        Lam = np.eye(q) - D.T @ np.linalg.solve(Om, D)
+        dd = np.sqrt(np.diag(Lam))
+        R = Lam / np.outer(dd, dd)
+        r = c["y"] - mu
+        d = np.einsum("na,na->n", r, np.linalg.solve(Om, r.T).T)
+        cc = np.linalg.solve(Om, r.T).T @ D
+        for row, dof in ((0, nu + p), (1, nu + p + 2)):
+            fr = f[2 * (np.arange(c["n"]) * g + i) + row]
+            h = cc / dd * np.sqrt(dof / (nu + d))[:, None]
+            np.testing.assert_allclose(fr[:, :q], h, rtol=1e-9, atol=1e-9)
+            np.testing.assert_allclose(fr[:, q:-1], np.broadcast_to(R[iu], (c["n"], len(iu[0]))),
+                                       rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(fr[:, -1], dof, rtol=1e-15)
+
+
+def test_out_of_range_pairs_fall_back_to_ghk(dev):
+    """With an h box no pair reaches, every pair goes through the GHK kernel
+    and the E-step equals the plain one bit for bit."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=500)
+    par = {k: T(v, dev) for k, v in c["true"].items()}
+    y, u = T(c["y"], dev), T(inputs.qmc_points(512, c["q"]), dev)
+    net = native.Surrogate.create(6, [50.0, 60.0, 5, 20, 0.95, 0.01], seed=2)
+    net.set_state(None, np.tile(np.repeat(np.array([0.0, 1.0], np.float32), 64), 2))
+    print("[gpu] estep fallback n=500", flush=True)
+    ref = native.cfust_estep(y, par, u)
+    got = native.cfust_estep(y, par, u, surrogate=net)
+    assert net.fallback_count() == c["n"] * c["g"]
+    for k in ("tau", "logf", "e2", "e3", "e4", "stats", "loglik"):
+        assert np.array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy()), k
