@@ -38,9 +38,13 @@ C_PHI, C_PHIINV, C_ACC = 40, 50, 20
 
 
 # HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
-# (KiB per dispatch, scaled by the same counters on a plain copy kernel); None
-# when the kernel has changed since the counters were taken.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# (KiB per dispatch, scaled by the same counters on a plain copy kernel:
+# fetch x 1.99979, write x 0.99998); None when the kernel has changed since
+# the counters were taken.
+TRAFFIC_BYTES_PER_LAUNCH = 15068030
+# executed FP64 flops per launch of the same kernel from the SQ_INSTS_VALU_*_F64
+# counters (64 lanes, FMA = 2)
+EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.594e11
 
 
 def flops_per_pair(p, q, N):
@@ -238,8 +242,13 @@ def main():
     ach = fpp * pairs / (pair_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VALU_TFLOPS, 4),
-            "traffic": TRAFFIC_BYTES_PER_LAUNCH, "kernel": f"pair_kernel<double,{q},true>",
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH if args.precision == "fp64" else None,
+            "kernel": f"pair_kernel<double,{q},true>",
             "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp}
+    if args.precision == "fp64":
+        ex = EXECUTED_FP64_FLOPS_PER_LAUNCH / (pair_ms * 1e-3) / 1e12
+        roof["executed_tflops"] = round(ex, 3)
+        roof["executed_frac"] = round(ex / PEAK_FP64_VALU_TFLOPS, 4)
 
     forms = None
     if not args.no_forms:

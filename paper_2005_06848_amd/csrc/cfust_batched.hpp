@@ -98,7 +98,7 @@ __global__ void bchi_kernel(BatchDev b, const double* __restrict__ comp, int com
 // Persistent pair kernel: waves take `chunk` consecutive pair indices at a
 // time from *counter until the index space is exhausted (every wave exits).
 template <typename T, int Q>
-__global__ void bpair_kernel(BatchDev b, const double* __restrict__ y,
+__global__ __launch_bounds__(256) void bpair_kernel(BatchDev b, const double* __restrict__ y,
                              const double* __restrict__ mu, const double* __restrict__ comp,
                              const T* __restrict__ sA, const T* __restrict__ sB,
                              const T* __restrict__ rsB, const T* __restrict__ uT,

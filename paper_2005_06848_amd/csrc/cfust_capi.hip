@@ -335,7 +335,7 @@ constexpr int64_t kSurrChunkPairs = int64_t(1) << 19;
 
 // E-step pairs through the network; pairs outside the training range through
 // the GHK kernel (on a compacted list per chunk)
-template <typename T, int Q>
+template <typename T, int Q, int PM>
 int launch_surrogate_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double* mu) {
   cfust_surrogate* s = ws.surr;
   const int64_t pairs = pl.n * pl.g;
@@ -352,11 +352,11 @@ int launch_surrogate_pairs_q(const Ws& ws, const Plan& pl, const double* y, cons
     const int64_t cn = std::min(chunk, pairs - c0);
     const unsigned nb = (unsigned)((cn + 255) / 256);
     fill_uint_kernel<<<1, 64, 0, ws.st>>>(s->count, 0u);
-    surr_feat_kernel<Q><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->rg, s->stdv,
+    surr_feat_kernel<Q, PM><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->rg, s->stdv,
                                                s->cf, s->cok, s->X, s->inr, s->list, s->count,
                                                status);
     mlp_forward(s, s->X, round64(2 * cn), H, nullptr, s->P, ws.st);
-    surr_assemble_kernel<Q><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->P,
+    surr_assemble_kernel<Q, PM><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->P,
                                                    s->stdv, s->inr, ws.at<double>(pl.o_pair),
                                                    pl.W);
     const unsigned lb = (unsigned)std::min<int64_t>((cn + 3) / 4, 8192);
@@ -369,19 +369,26 @@ int launch_surrogate_pairs_q(const Ws& ws, const Plan& pl, const double* y, cons
   return CFUST_OK;
 }
 
-template <typename T>
-int launch_surrogate_pairs(const Ws& ws, const Plan& pl, const double* y, const double* mu) {
+template <typename T, int PM>
+int launch_surrogate_pairs_p(const Ws& ws, const Plan& pl, const double* y, const double* mu) {
   switch (pl.q) {
-    case 1: return launch_surrogate_pairs_q<T, 1>(ws, pl, y, mu);
-    case 2: return launch_surrogate_pairs_q<T, 2>(ws, pl, y, mu);
-    case 3: return launch_surrogate_pairs_q<T, 3>(ws, pl, y, mu);
-    case 4: return launch_surrogate_pairs_q<T, 4>(ws, pl, y, mu);
-    case 5: return launch_surrogate_pairs_q<T, 5>(ws, pl, y, mu);
-    case 6: return launch_surrogate_pairs_q<T, 6>(ws, pl, y, mu);
-    case 7: return launch_surrogate_pairs_q<T, 7>(ws, pl, y, mu);
-    case 8: return launch_surrogate_pairs_q<T, 8>(ws, pl, y, mu);
+    case 1: return launch_surrogate_pairs_q<T, 1, PM>(ws, pl, y, mu);
+    case 2: return launch_surrogate_pairs_q<T, 2, PM>(ws, pl, y, mu);
+    case 3: return launch_surrogate_pairs_q<T, 3, PM>(ws, pl, y, mu);
+    case 4: return launch_surrogate_pairs_q<T, 4, PM>(ws, pl, y, mu);
+    case 5: return launch_surrogate_pairs_q<T, 5, PM>(ws, pl, y, mu);
+    case 6: return launch_surrogate_pairs_q<T, 6, PM>(ws, pl, y, mu);
+    case 7: return launch_surrogate_pairs_q<T, 7, PM>(ws, pl, y, mu);
+    case 8: return launch_surrogate_pairs_q<T, 8, PM>(ws, pl, y, mu);
   }
   return CFUST_EINVAL;
+}
+
+// thread-per-pair kernels keep p-vectors in registers for p <= 8
+template <typename T>
+int launch_surrogate_pairs(const Ws& ws, const Plan& pl, const double* y, const double* mu) {
+  if (pl.p <= 8) return launch_surrogate_pairs_p<T, 8>(ws, pl, y, mu);
+  return launch_surrogate_pairs_p<T, kMaxP>(ws, pl, y, mu);
 }
 
 void launch_stats(const Ws& ws, const Plan& pl, const double* y, const double* mu, bool with_stats,
@@ -1328,14 +1335,34 @@ float set_loss_weights(cfust_surrogate* s, const float* wo, hipStream_t st) {
 int set_std_from_data(cfust_surrogate* s, const double* feat, const double* targ, int64_t M,
                       hipStream_t st) {
   col_moments_kernel<<<s->F, 256, 0, st>>>(feat, M, s->F, s->stdv, s->stdv + kMlpPad);
-  col_moments_kernel<<<s->T, 256, 0, st>>>(targ, M, s->T, s->stdv + 2 * kMlpPad,
+  double* nt = nullptr;
+  if (hipMallocAsync((void**)&nt, (size_t)M * s->T * sizeof(double), st) != hipSuccess)
+    return CFUST_ENOMEM;
+  net_targets_kernel<<<(unsigned)((M * s->T + 255) / 256), 256, 0, st>>>(targ, M, s->q, s->T, nt);
+  col_moments_kernel<<<s->T, 256, 0, st>>>(nt, M, s->T, s->stdv + 2 * kMlpPad,
                                            s->stdv + 3 * kMlpPad);
+  (void)hipFreeAsync(nt, st);
   if (hipMemcpyAsync(s->h_std, s->stdv, sizeof(s->h_std), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return CFUST_EHIP;
   s->have_std = true;
   return CFUST_OK;
+}
+
+template <int PM>
+void launch_pair_features(int q, unsigned nb, hipStream_t st, const double* y, int64_t n, int p,
+                          int g, const double* mu, const double* comp, double* out, int* status) {
+  switch (q) {
+    case 1: pair_features_kernel<1, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 2: pair_features_kernel<2, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 3: pair_features_kernel<3, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 4: pair_features_kernel<4, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 5: pair_features_kernel<5, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 6: pair_features_kernel<6, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 7: pair_features_kernel<7, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+    case 8: pair_features_kernel<8, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+  }
 }
 
 struct SurrFileHeader {
@@ -1443,7 +1470,7 @@ int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* 
       const int64_t B = std::min<int64_t>(batch, M - b0);
       const int64_t Bp = round64(B);
       gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-          feat, targ, idx, b0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
+          feat, targ, idx, b0, B, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad,
           s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->tX, s->tT);
       forward_backward(s, B, Bp, wsum, lacc, ep, st);
       ++s->adam_t;
@@ -1488,7 +1515,7 @@ int cfust_surrogate_grad(cfust_surrogate* s, const double* feat, const double* t
   if (hipMallocAsync((void**)&lacc, sizeof(double), st) != hipSuccess) return CFUST_ENOMEM;
   (void)hipMemsetAsync(lacc, 0, sizeof(double), st);
   gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-      feat, targ, nullptr, 0, M, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad, s->stdv + 2 * kMlpPad,
+      feat, targ, nullptr, 0, M, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad, s->stdv + 2 * kMlpPad,
       s->stdv + 3 * kMlpPad, s->tX, s->tT);
   forward_backward(s, M, Bp, wsum, lacc, 0, st);
   rc = launch_check();
@@ -1514,11 +1541,11 @@ int cfust_surrogate_eval(cfust_surrogate* s, const double* feat, int64_t M, cons
     const int64_t B = std::min(chunk_rows, M - r0);
     const int64_t Bp = round64(B);
     gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-        feat, nullptr, nullptr, r0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
+        feat, nullptr, nullptr, r0, B, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad,
         s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->X, nullptr);
     mlp_forward(s, s->X, Bp, H, nullptr, s->P, st);
-    unstd_kernel<<<(unsigned)((B * s->T + 255) / 256), 256, 0, st>>>(
-        s->P, B, s->T, s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, out + r0 * s->T);
+    unstd_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(
+        s->P, B, s->T, s->q, s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, out + r0 * s->T);
   }
   rc = launch_check();
   if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = CFUST_EHIP;
@@ -1638,16 +1665,10 @@ int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const d
   const int64_t pairs = n * g;
   const unsigned nb = (unsigned)((pairs + 127) / 128);
   if (pairs > 0) {
-    switch (q) {
-      case 1: pair_features_kernel<1><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 2: pair_features_kernel<2><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 3: pair_features_kernel<3><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 4: pair_features_kernel<4><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 5: pair_features_kernel<5><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 6: pair_features_kernel<6><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 7: pair_features_kernel<7><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-      case 8: pair_features_kernel<8><<<nb, 128, 0, ws.st>>>(y, n, p, g, mu, comp, out, status); break;
-    }
+    if (p <= 8)
+      launch_pair_features<8>(q, nb, ws.st, y, n, p, g, mu, comp, out, status);
+    else
+      launch_pair_features<kMaxP>(q, nb, ws.st, y, n, p, g, mu, comp, out, status);
   }
   rc = launch_check();
   int stt = fetch_status(ws, pl, nullptr);

@@ -440,32 +440,31 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
   const double v = cp[cl.nu];
 
   // ---- a4: Mahalanobis distance and skew projection (eq. (2)) ----
-  double r[kMaxP];
-  bool finite_ok = true;
-  for (int a = 0; a < p; ++a) {
-    double ya = yj[a];
-    finite_ok = finite_ok && isfinite(ya);
-    r[a] = ya - mui[a];
+  // spread over the wave: lane a < p holds r_a = y_ja - mu_ia
+  double ra = 0.0;
+  bool bad = false;
+  if (lane < p) {
+    const double ya = yj[lane];
+    bad = !isfinite(ya);
+    ra = ya - mui[lane];
   }
-  if (!finite_ok) return false;
+  if (__ballot(bad) != 0) return false;
+  // forward substitution L z = r, column by column: z_b = t_b / L_bb is
+  // broadcast from lane b, then lanes a > b update t_a -= L_ab z_b
   double d = 0.0;
   {
-    double z[kMaxP];
     const double* L = cp + cl.L;
-    for (int a = 0; a < p; ++a) {
-      double t = r[a];
-      for (int b = 0; b < a; ++b) t -= L[a * p + b] * z[b];
-      z[a] = t / L[a * p + a];
-      d += z[a] * z[a];
+    double t = ra;
+    for (int b = 0; b < p; ++b) {
+      const double zb = wave_bcast(t, b) / L[b * p + b];
+      d += zb * zb;
+      if (lane > b && lane < p) t -= L[lane * p + b] * zb;
     }
   }
+  // c = Delta^T Omega^-1 r = B^T r by wave sums
   double c[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    double t = 0.0;
-    for (int a = 0; a < p; ++a) t += cp[cl.B + a * Q + k] * r[a];
-    c[k] = t;
-  }
+  for (int k = 0; k < Q; ++k) c[k] = wave_sum(lane < p ? cp[cl.B + lane * Q + k] * ra : 0.0);
   const double fa = sqrt((v + p) / (v + d));
   const double fb = sqrt((v + p + 2.0) / (v + d));
   // scaled bounds: ub_m = s * ht_m - sum_{l<m} Ct_ml eps_l, with

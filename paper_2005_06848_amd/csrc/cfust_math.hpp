@@ -410,6 +410,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// value of v in lane src (src wave-uniform)
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));

@@ -340,16 +340,42 @@ __global__ __launch_bounds__(256) void col_moments_kernel(const double* __restri
   }
 }
 
+// The network's outputs for a truncated-t problem of dimension q are
+//   log P(V <= h) | m1 = E[V | V <= h] (q) | Cov(V | V <= h) (upper triangle)
+// while the labels carry E[V V^T | V <= h] in place of the covariance: the
+// covariance stays within the untruncated t variance whereas E[V V^T] grows
+// like h h^T.  Column o of the label row in network form:
+__device__ __forceinline__ double net_target(const double* __restrict__ row, int q, int o) {
+  if (o < 1 + q) return row[o];
+  int t = o - 1 - q;
+  int a = 0;
+  while (t >= q - a) {
+    t -= q - a;
+    ++a;
+  }
+  const int b = a + t;
+  return row[o] - row[1 + a] * row[1 + b];
+}
+
+// targets of M label rows in network form (for the standardisation)
+__global__ void net_targets_kernel(const double* __restrict__ targ, int64_t M, int q, int OUT,
+                                   double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * OUT) return;
+  const int64_t r = t / OUT;
+  out[t] = net_target(targ + r * OUT, q, (int)(t % OUT));
+}
+
 // Standardised, padded rows: X[r] = (feat[idx[r]] - mx) / sx in bf16 (width
-// 64) and, when targ is given, T[r] = (targ[idx[r]] - my) / sy (fp32, width
-// OUT).  Rows r >= B (padding to a multiple of 64) are zero; idx NULL means
-// row base + r.
+// 64) and, when targ is given, T[r] = (net_target(targ[idx[r]]) - my) / sy
+// (fp32, width OUT).  Rows r >= B (padding to a multiple of 64) are zero;
+// idx NULL means row base + r.
 __global__ void gather_rows_kernel(const double* __restrict__ feat, const double* __restrict__ targ,
                                    const int64_t* __restrict__ idx, int64_t base, int64_t B,
-                                   int64_t Bp, int IN, int OUT, const float* __restrict__ mx,
-                                   const float* __restrict__ sx, const float* __restrict__ my,
-                                   const float* __restrict__ sy, bf16* __restrict__ X,
-                                   float* __restrict__ T) {
+                                   int64_t Bp, int IN, int OUT, int q,
+                                   const float* __restrict__ mx, const float* __restrict__ sx,
+                                   const float* __restrict__ my, const float* __restrict__ sy,
+                                   bf16* __restrict__ X, float* __restrict__ T) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Bp * kMlpPad) return;
   const int64_t r = t / kMlpPad;
@@ -360,20 +386,25 @@ __global__ void gather_rows_kernel(const double* __restrict__ feat, const double
   X[t] = f2bf(xv);
   if (targ && c < OUT) {
     float tv = 0.f;
-    if (r < B) tv = (float)((targ[s * OUT + c] - (double)my[c]) / (double)sy[c]);
+    if (r < B) tv = (float)((net_target(targ + s * OUT, q, c) - (double)my[c]) / (double)sy[c]);
     T[r * OUT + c] = tv;
   }
 }
 
-// out[r][o] = P[r][o] * sy[o] + my[o] for r < B, o < OUT (double)
-__global__ void unstd_kernel(const float* __restrict__ P, int64_t B, int OUT,
+// De-standardised network outputs in label form (E[V V^T] = Cov + m1 m1^T):
+// one thread per row r < B
+__global__ void unstd_kernel(const float* __restrict__ P, int64_t B, int OUT, int q,
                              const float* __restrict__ my, const float* __restrict__ sy,
                              double* __restrict__ out) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * OUT) return;
-  const int64_t r = t / OUT;
-  const int o = (int)(t % OUT);
-  out[t] = (double)P[r * kMlpPad + o] * (double)sy[o] + (double)my[o];
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= B) return;
+  const float* pr = P + r * kMlpPad;
+  double* o = out + r * OUT;
+  for (int c = 0; c < 1 + q; ++c) o[c] = (double)pr[c] * (double)sy[c] + (double)my[c];
+  int c = 1 + q;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++c)
+      o[c] = (double)pr[c] * (double)sy[c] + (double)my[c] + o[1 + a] * o[1 + b];
 }
 
 }  // namespace cfust

@@ -7,7 +7,7 @@
 // matrix of Lambda_i = I - Delta^T Omega^-1 Delta and D = sqrt(diag Lambda).
 // The network maps the feature row (h, the q(q-1)/2 correlations above the
 // diagonal of R row by row, dof) to (log P(V <= h), E[V | V <= h],
-// E[V V^T | V <= h] upper triangle).  A pair whose features leave the
+// Cov(V | V <= h) upper triangle).  A pair whose features leave the
 // training range is evaluated by the GHK kernel instead (QMC fallback).
 #pragma once
 #include "cfust_kernels.hpp"
@@ -96,32 +96,45 @@ __global__ void surr_comp_kernel(int p, int q, int g, const double* __restrict__
 }
 
 // r = y_j - mu_i, squared Mahalanobis distance d under Omega_i and
-// c = Delta^T Omega^-1 r (eq. (2)); false if y_j is not finite
-template <int Q>
+// c = Delta^T Omega^-1 r (eq. (2)) in one thread; false if y_j is not
+// finite.  PM >= p bounds the loops at compile time so that r and z stay in
+// registers.
+template <int Q, int PM>
 __device__ __forceinline__ bool pair_geometry(const double* __restrict__ yj, int p,
                                               const double* __restrict__ mui,
                                               const double* __restrict__ cp, double& d,
                                               double (&c)[Q]) {
   const CompLayout cl(p, Q);
-  double r[kMaxP], z[kMaxP];
+  double r[PM], z[PM];
   bool fin = true;
-  for (int a = 0; a < p; ++a) {
-    const double ya = yj[a];
-    fin = fin && isfinite(ya);
-    r[a] = ya - mui[a];
+#pragma unroll
+  for (int a = 0; a < PM; ++a) {
+    r[a] = 0.0;
+    z[a] = 0.0;
+    if (a < p) {
+      const double ya = yj[a];
+      fin = fin && isfinite(ya);
+      r[a] = ya - mui[a];
+    }
   }
   const double* L = cp + cl.L;
   d = 0.0;
-  for (int a = 0; a < p; ++a) {
-    double t = r[a];
-    for (int b = 0; b < a; ++b) t -= L[a * p + b] * z[b];
-    z[a] = t / L[a * p + a];
-    d += z[a] * z[a];
+#pragma unroll
+  for (int a = 0; a < PM; ++a) {
+    if (a < p) {
+      double t = r[a];
+#pragma unroll
+      for (int b = 0; b < a; ++b) t -= L[a * p + b] * z[b];
+      z[a] = t / L[a * p + a];
+      d += z[a] * z[a];
+    }
   }
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     double t = 0.0;
-    for (int a = 0; a < p; ++a) t += cp[cl.B + a * Q + k] * r[a];
+#pragma unroll
+    for (int a = 0; a < PM; ++a)
+      if (a < p) t += cp[cl.B + a * Q + k] * r[a];
     c[k] = t;
   }
   return fin;
@@ -177,7 +190,7 @@ __device__ __forceinline__ void write_feature_row(bf16* __restrict__ row, const 
 // One thread per pair of the chunk [c0, c0 + cn): rows 2t (integral A) and
 // 2t + 1 (integral B) of X; pairs outside the training range get zero rows,
 // inr[t] = 0 and an entry in list (order of the entries is arbitrary).
-template <int Q>
+template <int Q, int PM>
 __global__ __launch_bounds__(256) void surr_feat_kernel(
     const double* __restrict__ y, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, int64_t c0, int64_t cn, SurrRange rg,
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(256) void surr_feat_kernel(
   const CompLayout cl(p, Q);
   const double* cp = comp + (size_t)i * cl.stride;
   double d, c[Q], hA[Q], hB[Q];
-  const bool fin = pair_geometry<Q>(y + j * p, p, mu + (size_t)i * p, cp, d, c);
+  const bool fin = pair_geometry<Q, PM>(y + j * p, p, mu + (size_t)i * p, cp, d, c);
   if (!fin) set_status(status, kENonFinite, -1);
   pair_bounds<Q>(cp, p, d, c, hA, hB);
   bool in = fin && cok[i] != 0;
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(256) void surr_feat_kernel(
 //   log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[Q] | e4 (upper triangle)
 // from the network outputs P (rows 2t, 2t + 1; de-standardised with my, sy),
 // by the same assembly as the GHK path.
-template <int Q>
+template <int Q, int PM>
 __global__ __launch_bounds__(256) void surr_assemble_kernel(
     const double* __restrict__ y, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, int64_t c0, int64_t cn, const float* __restrict__ P,
@@ -230,7 +243,7 @@ __global__ __launch_bounds__(256) void surr_assemble_kernel(
   const CompLayout cl(p, Q);
   const double* cp = comp + (size_t)i * cl.stride;
   double d, c[Q];
-  pair_geometry<Q>(y + j * p, p, mu + (size_t)i * p, cp, d, c);
+  pair_geometry<Q, PM>(y + j * p, p, mu + (size_t)i * p, cp, d, c);
   const float* my = stdv + 2 * kMlpPad;
   const float* sy = stdv + 3 * kMlpPad;
   const float* PA = P + (size_t)(2 * t) * kMlpPad;
@@ -256,11 +269,12 @@ __global__ __launch_bounds__(256) void surr_assemble_kernel(
 #pragma unroll
   for (int k = 0; k < Q; ++k) rec[3 + k] = e2 * (c[k] - mx[k]);
   int u = 0;
+  // E[V V^T] = Cov + m1 m1^T (the network predicts the covariance)
 #pragma unroll
   for (int a = 0; a < Q; ++a)
 #pragma unroll
     for (int b = a; b < Q; ++b) {
-      const double m2 = un(PB, 1 + Q + u);
+      const double m2 = un(PB, 1 + Q + u) + un(PB, 1 + a) * un(PB, 1 + b);
       const double exx = c[a] * c[b] - c[a] * mx[b] - mx[a] * c[b] + Ds[a] * m2 * Ds[b];
       rec[3 + Q + u] = e2 * exx;
       ++u;
@@ -306,7 +320,7 @@ __global__ void add_count_kernel(const unsigned int* c, unsigned long long* tota
 
 // raw feature rows of every pair (2 per pair, A then B):
 // h (Q) | correlations (NR) | dof, doubles
-template <int Q>
+template <int Q, int PM>
 __global__ void pair_features_kernel(const double* __restrict__ y, int64_t n, int p, int g,
                                      const double* __restrict__ mu,
                                      const double* __restrict__ comp, double* __restrict__ out,
@@ -320,7 +334,7 @@ __global__ void pair_features_kernel(const double* __restrict__ y, int64_t n, in
   const CompLayout cl(p, Q);
   const double* cp = comp + (size_t)i * cl.stride;
   double d, c[Q], hA[Q], hB[Q];
-  if (!pair_geometry<Q>(y + j * p, p, mu + (size_t)i * p, cp, d, c))
+  if (!pair_geometry<Q, PM>(y + j * p, p, mu + (size_t)i * p, cp, d, c))
     set_status(status, kENonFinite, -1);
   pair_bounds<Q>(cp, p, d, c, hA, hB);
   const double* C = cp + cl.C;

@@ -256,14 +256,15 @@ def _true_params_separated(rng, p, q, g, nu, delta_half):
                 nu=np.asarray(nu, float))
 
 
-def config(k: int, n: int | None = None):
+def config(k: int, n: int | None = None, seed: int | None = None):
     """Return a dict with y, the true parameters, Psi^(0), u and sizes for workload k.
 
     ``n`` overrides the number of observations (the draws for the first
     observations do not depend on it for workloads 1-3 and 5 only through the
     label draw, so tests use it for reduced copies of the same recipe).
+    ``seed`` replaces the workload's own seed: another draw of the same recipe.
     """
-    rng = np.random.default_rng(SEED_BASE + k)
+    rng = np.random.default_rng(SEED_BASE + k if seed is None else seed)
     if k == 1:
         p, q, g, N = 2, 2, 2, 1024
         true = _true_params_basic(rng, p, q, g, [4.0, 8.0], 2.0, [0.4, 0.6])

@@ -1,12 +1,13 @@
 """Training set and training of the surrogate network for the GHK integrals.
 
-Training set (q = 6): correlation matrices R ~ LKJ(2) (onion method),
-degrees of freedom uniform on a 0.25 grid in [5, 20], truncation points h
-half uniform on [-4, 6]^6 and half taken from the h values of the pairs of
-an EM run on data shaped like the surrogate workload (n obs, p = q = 6,
-g = 4), logged at the starting values and at later iterates.  Labels are
-GHK estimates by the library's own kernel (cfust_ghk_batch) with 2^14
-points.  Training runs the library's BF16 matrix-core forward/backward and
+Training set (q = 6): half the samples with correlation matrices
+R ~ LKJ(2) (onion method), degrees of freedom uniform on a 0.25 grid in
+[5, 20] and truncation points h uniform on [-4, 6]^6; the other half are the
+(h, R, dof) of pairs logged along EM runs on other draws of the surrogate
+workload's recipe (p = q = 6, g = 4), at the starting values and at later
+iterates.  Labels are GHK estimates by the library's own kernel
+(cfust_ghk_batch) with 2^14 points; the network learns the covariance in
+place of E[V V^T].  Training runs the library's BF16 matrix-core forward/backward and
 Adam kernels (cfust_surrogate_train).
 
 Run:  python -m paper_2005_06848_amd.surrogate --out <file>
@@ -29,6 +30,9 @@ DOF_LO, DOF_HI = 5.0, 20.0
 R_MAX = 0.95
 EIG_PERCENTILE = 1.0
 N_LABEL = 1 << 14
+# other draws of the surrogate workload's recipe (the workload itself uses
+# its own seed, so the network never sees the benchmark's data)
+PROPOSAL_SEEDS = tuple(range(9001, 9009))
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "surrogate_q6.bin")
 
 
@@ -48,28 +52,45 @@ def eig_threshold(R):
     return float(np.percentile(np.linalg.eigvalsh(R)[:, 0], EIG_PERCENTILE))
 
 
-def proposal_h(n_obs=100_000, iterates=(0, 3, 10, 30), seed=0, device="cuda"):
-    """h rows of integrals A and B of every pair, logged along an FP32 EM run
-    on data shaped like the surrogate workload; rows inside the h box only."""
-    c = inputs.config(5, n=n_obs)
-    y = torch.tensor(c["y"], device=device)
-    u = torch.tensor(c["u"], device=device)
-    par = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=device)
-           for k, v in c["init"].items()}
+def proposal_rows(seeds=PROPOSAL_SEEDS, n_obs=50_000, iterates=(0, 3, 10, 30), per_iterate=100_000,
+                  device="cuda"):
+    """Feature rows (h | r | dof) of both integrals of the pairs of FP32 EM
+    runs on other draws of the surrogate workload's recipe (n_obs
+    observations, p = q = 6, g = 4), logged at the starting values and at
+    later iterates; rows inside the training box only, per_iterate of them
+    per logged iterate."""
+    rng = np.random.default_rng(12345)
     rows = []
-    done = 0
-    for it in iterates:
-        if it > done:
-            res = nat.cfust_em_fit(y, par, u, max_iter=it - done, tol=0.0, precision="fp32")
-            par = {k: res[k] for k in ("pi", "mu", "Sigma", "Delta", "nu")}
-            done = it
-        f = nat.cfust_pair_features(y, par)[:, :Q].cpu().numpy()
-        keep = np.all((f >= H_LO) & (f <= H_HI), axis=1)
-        rows.append(f[keep])
-        log(f"proposal: iterate {it}: {keep.sum()} of {len(keep)} h rows in the box")
-    out = np.concatenate(rows)
-    rng = np.random.default_rng(seed)
-    return out[rng.permutation(len(out))]
+    for sd in seeds:
+        c = inputs.config(5, n=n_obs, seed=sd)
+        y = torch.tensor(c["y"], device=device)
+        u = torch.tensor(c["u"], device=device)
+        par = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=device)
+               for k, v in c["init"].items()}
+        done = 0
+        for it in iterates:
+            if it > done:
+                res = nat.cfust_em_fit(y, par, u, max_iter=it - done, tol=0.0, precision="fp32")
+                par = {k: res[k] for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+                done = it
+            f = nat.cfust_pair_features(y, par).cpu().numpy()
+            keep = (np.all((f[:, :Q] >= H_LO) & (f[:, :Q] <= H_HI), axis=1)
+                    & np.all(np.abs(f[:, Q:-1]) <= R_MAX, axis=1)
+                    & (f[:, -1] >= DOF_LO) & (f[:, -1] <= DOF_HI))
+            f = f[keep]
+            rows.append(f[rng.permutation(len(f))[:per_iterate]])
+        log(f"proposal: draw {sd}: {sum(len(r) for r in rows)} rows so far")
+    return np.concatenate(rows)
+
+
+def corr_from_rows(r, q=Q):
+    """Correlation matrices from the entries above the diagonal, row by row."""
+    R = np.zeros((len(r), q, q))
+    iu = np.triu_indices(q, 1)
+    R[:, iu[0], iu[1]] = r
+    R[:, iu[1], iu[0]] = r
+    R[:, np.arange(q), np.arange(q)] = 1.0
+    return R
 
 
 def label(h, R, dof, u, chunk=1 << 18, device="cuda"):
@@ -84,17 +105,23 @@ def label(h, R, dof, u, chunk=1 << 18, device="cuda"):
 
 
 def training_set(m, seed=1, proposal=None, n_label=N_LABEL, device="cuda"):
-    """Feature rows (device [m][22]), labels (device [m][28]) and the raw R."""
+    """Feature rows (device [m][22]) and labels (device [m][28]): the first
+    half (all rows without a proposal) with R ~ LKJ(2), dof on the grid and h
+    uniform in the box, the second half drawn from the proposal rows.  Also
+    returns the smallest-eigenvalue threshold of the LKJ part."""
     rng = np.random.default_rng(seed)
-    h_extra = None
-    if proposal is not None and len(proposal):
-        k = m // 2
-        h_extra = proposal[rng.integers(0, len(proposal), size=k)]
-    h, R, dof = inputs.surrogate_samples(rng, m, Q, H_LO, H_HI, DOF_LO, DOF_HI, 0.25, 2.0, h_extra)
+    k = m if proposal is None or not len(proposal) else m - m // 2
+    h, R, dof = inputs.surrogate_samples(rng, k, Q, H_LO, H_HI, DOF_LO, DOF_HI, 0.25, 2.0)
+    thr = eig_threshold(R)
+    if k < m:
+        pr = proposal[rng.integers(0, len(proposal), size=m - k)]
+        h = np.concatenate([h, pr[:, :Q]])
+        R = np.concatenate([R, corr_from_rows(pr[:, Q:-1])])
+        dof = np.concatenate([dof, pr[:, -1]])
     u = torch.tensor(inputs.qmc_points(n_label, Q, seed=0x51), device=device)
     targ = label(h, R, dof, u, device=device)
     feat = torch.tensor(feature_rows(h, R, dof), device=device)
-    return feat, targ, R
+    return feat, targ, thr
 
 
 def output_weights(q=Q):
@@ -105,15 +132,14 @@ def output_weights(q=Q):
     return w
 
 
-def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, n_obs=100_000,
-          device="cuda"):
+def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, device="cuda"):
     t0 = time.time()
-    prop = proposal_h(n_obs=n_obs, device=device)
+    prop = proposal_rows(device=device)
     log(f"proposal rows {len(prop)} ({time.time() - t0:.1f} s)")
-    feat, targ, R = training_set(m, seed=seed, proposal=prop, device=device)
+    feat, targ, thr = training_set(m, seed=seed, proposal=prop, device=device)
     torch.cuda.synchronize()
     log(f"training set {m} samples labelled ({time.time() - t0:.1f} s)")
-    rng_ = [H_LO, H_HI, DOF_LO, DOF_HI, R_MAX, eig_threshold(R)]
+    rng_ = [H_LO, H_HI, DOF_LO, DOF_HI, R_MAX, thr]
     net = nat.Surrogate.create(Q, rng_, seed=seed)
     trace = []
     step = 10

@@ -84,6 +84,17 @@ def test_ghk_batch_rejects_indefinite(dev):
     assert ei.value.code == native.ENOTPD
 
 
+def net_form(t, q):
+    """Label rows (log T | m1 | E[VV^T]) in the network's form (log T | m1 | Cov)."""
+    out = np.array(t, dtype=np.float64, copy=True)
+    c = 1 + q
+    for a in range(q):
+        for b in range(a, q):
+            out[:, c] = t[:, c] - t[:, 1 + a] * t[:, 1 + b]
+            c += 1
+    return out
+
+
 def _net_and_batch(dev, seed, m):
     from paper_2005_06848_amd import inputs, native
     rng = np.random.default_rng(seed)
@@ -98,8 +109,9 @@ def _net_and_batch(dev, seed, m):
     stdv[:F] = feat.mean(0)
     stdv[64:64 + F] = np.maximum(feat.std(0), 1e-3)
     stdv[64 + F:128] = 1.0
-    stdv[128:128 + Tw] = targ.mean(0)
-    stdv[192:192 + Tw] = targ.std(0)
+    nt = net_form(targ, q)
+    stdv[128:128 + Tw] = nt.mean(0)
+    stdv[192:192 + Tw] = nt.std(0)
     stdv[192 + Tw:] = 1.0
     net.set_state(None, stdv)
     return net, feat, targ, stdv
@@ -119,8 +131,8 @@ def test_surrogate_gradient_matches_cpu_reference(dev):
     X[:, :F] = ((feat - stdv[:F].astype(np.float64)) / stdv[64:64 + F].astype(np.float64)
                 ).astype(np.float32)
     Tw = targ.shape[1]
-    Ts = ((targ - stdv[128:128 + Tw].astype(np.float64)) / stdv[192:192 + Tw].astype(np.float64)
-          ).astype(np.float32).astype(np.float64)
+    Ts = ((net_form(targ, 6) - stdv[128:128 + Tw].astype(np.float64))
+          / stdv[192:192 + Tw].astype(np.float64)).astype(np.float32).astype(np.float64)
     ref_loss, ref = mo.loss_and_grad(theta.astype(np.float64), X, Ts, wo, bf16=True)
     assert abs(loss - ref_loss) <= 1e-5 * ref_loss
     errs = {}
