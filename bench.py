@@ -100,6 +100,66 @@ def precision_form(args, native, L, torch, np, inputs, dev):
     return res
 
 
+def surrogate_form(args, native, torch, np, inputs, dev):
+    """Surrogate form on the n=1000000, p=q=6, g=4, N=8192 workload: E-step
+    time of the FP64 and FP32 GHK paths, of the shipped network, and of one
+    adaptation (GHK labels of 16384 sampled pairs, 20 epochs) followed by the
+    network E-step; accuracy of both against the FP64 GHK E-step on the first
+    20000 observations.  The k-means start uses one restart here."""
+    from paper_2005_06848_amd import surrogate as S
+    print("[bench] surrogate: generating n=1000000 p=q=6 g=4", file=sys.stderr, flush=True)
+    c = inputs.config(5, kmeans_restarts=1)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y, u = T(c["y"]), T(c["u"])
+    par = {k: T(v) for k, v in c["init"].items()}
+    ptrue = {k: T(v) for k, v in c["true"].items()}
+    net = native.Surrogate.load(S.DEFAULT_PATH)
+
+    def timed(f, reps=1):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    res = {"workload": "cfust E-step n=1000000 p=6 q=6 g=4 N=8192 (k-means start, 1 restart)"}
+    print("[bench] surrogate: GHK E-steps (fp64, fp32)", file=sys.stderr, flush=True)
+    res["fp64_ghk_ms"] = round(timed(lambda: native.cfust_estep(y, par, u, want=())), 2)
+    res["fp32_ghk_ms"] = round(timed(lambda: native.cfust_estep(y, par, u, want=(), precision="fp32")), 2)
+    print("[bench] surrogate: network E-steps", file=sys.stderr, flush=True)
+    res["network_ms"] = round(timed(lambda: native.cfust_estep(y, par, u, want=(), surrogate=net),
+                                    args.form_reps), 2)
+    res["network_fallback_pairs"] = net.fallback_count()
+    res["adapt_plus_network_ms"] = round(timed(
+        lambda: (net.adapt(y, par, u, samples=16384, epochs=20),
+                 native.cfust_estep(y, par, u, want=(), surrogate=net))), 2)
+    res["network_ms_at_true_params"] = round(timed(
+        lambda: native.cfust_estep(y, ptrue, u, want=(), surrogate=net)), 2)
+    res["fallback_pairs_at_true_params"] = net.fallback_count()
+    res["pairs"] = c["n"] * c["g"]
+    res["speedup_network_vs_fp64"] = round(res["fp64_ghk_ms"] / res["network_ms"], 2)
+    res["speedup_adapt_plus_network_vs_fp64"] = round(res["fp64_ghk_ms"] / res["adapt_plus_network_ms"], 2)
+    res["speedup_fp32_vs_fp64"] = round(res["fp64_ghk_ms"] / res["fp32_ghk_ms"], 2)
+    # accuracy on the first 20000 observations at the start
+    ys = y[:20000].contiguous()
+    ref = native.cfust_estep(ys, par, u)
+    acc = {}
+    for name, nt in (("shipped", native.Surrogate.load(S.DEFAULT_PATH)), ("adapted", None)):
+        if nt is None:
+            nt = native.Surrogate.load(S.DEFAULT_PATH)
+            nt.adapt(ys, par, u, samples=16384, epochs=50)
+        got = native.cfust_estep(ys, par, u, surrogate=nt)
+        g_, r_ = got["stats"].cpu().numpy(), ref["stats"].cpu().numpy()
+        acc[name] = {"stats_max_rel": float((np.abs(g_ - r_).max(1) / np.abs(r_).max(1)).max()),
+                     "loglik_rel": abs(got["loglik"].item() / ref["loglik"].item() - 1)}
+    res["accuracy_vs_fp64_ghk_n20000"] = acc
+    res["tolerance"] = ("target 1e-3 on moments, 1e-5 relative on the converged log-likelihood; "
+                        "measured values above (tests/test_gpu_surrogate.py)")
+    return res
+
+
 def batched_form(args, native, torch, np, inputs, dev):
     """Batched form: 64 EM starts (n ~ U{5000..50000}, g ~ U{2..6}, p=q=5,
     N=4096, FP32 integrand), one device-driven loop with hipGraph-captured
@@ -158,6 +218,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form leg (64 starts, p=q=5, N=4096, FP32)")
     ap.add_argument("--batched-iters", type=int, default=50)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-form leg (n=1000000, p=q=6, g=4, N=8192)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched leg: skip fitting the starts one by one for comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -253,6 +315,9 @@ def main():
     forms = None
     if not args.no_forms:
         forms = precision_form(args, native, L, torch, np, inputs, dev)
+    if not args.no_surrogate:
+        forms = forms or {}
+        forms["surrogate"] = surrogate_form(args, native, torch, np, inputs, dev)
     if not args.no_batched:
         forms = forms or {}
         forms["batched"] = batched_form(args, native, torch, np, inputs, dev)

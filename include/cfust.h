@@ -83,6 +83,10 @@ typedef struct cfust_opts {
                              cfust_estep / cfust_loglik / cfust_em_fit evaluate the two
                              GHK integrals of every in-range pair with it and the
                              GHK kernel only for the others (q must match) */
+  int adapt_samples;      /* cfust_em_fit with a surrogate: pairs sampled for
+                             cfust_surrogate_adapt before every surrogate E-step
+                             (0 = no adaptation) */
+  int adapt_epochs;       /* epochs of each of those adaptations */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4
@@ -143,7 +147,15 @@ int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* 
  * (l^(t) - l^(t-1)) / (1 - a), a = (l^(t) - l^(t-1)) / (l^(t-1) - l^(t-2)),
  * is within opts->tol of l^(t); otherwise the M-step gives Psi^(t+1).  At
  * most opts->max_iter M-steps.  loglik_trace: host [max_iter + 1], receives
- * l^(0..*n_iter).  n_iter, bad_component: host. */
+ * l^(0..*n_iter).  n_iter, bad_component: host.
+ * With opts->surrogate the fit runs in two phases: surrogate E-steps until
+ * the rule above stops, then one GHK E-step at the same parameters (the GHK
+ * log-likelihood at the surrogate's estimate; no M-step in between) and GHK
+ * EM from there until the rule stops again, the Aitken test using only
+ * values of the current phase (cfust_surrogate_em_switch gives the index of
+ * the first GHK E-step).  With opts->adapt_samples > 0, every surrogate
+ * E-step is preceded by cfust_surrogate_adapt at the current parameters
+ * (opts->adapt_samples pairs, opts->adapt_epochs epochs, seed = iteration). */
 int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, double* mu,
                  double* Sigma, double* Delta, double* nu, const double* u, int n_qmc,
                  const cfust_opts* opts, double* loglik_trace, int* n_iter,
@@ -202,6 +214,9 @@ int cfust_ghk_batch(int q, int64_t M, const double* h, const double* R, const do
  * perceptron F -> 256 -> 256 -> 256 -> T with SiLU activations, bf16 weights
  * and activations on the matrix cores, fp32 accumulation, fp32 master
  * weights, trained with Adam on a mean squared error of standardised outputs.
+ * Internally it predicts log P | E[V] | U with Cov(V | V <= h) = U^T U (U
+ * upper triangular, log diagonal), so every predicted covariance is
+ * positive definite; inputs and outputs of the entry points are label rows.
  * A handle owns its device memory; calls that share a handle must not
  * overlap.  Limits: 1 <= q <= 8.
  * ------------------------------------------------------------------------- */
@@ -248,9 +263,27 @@ int cfust_surrogate_set_state(cfust_surrogate* s, const float* params, const flo
 int cfust_surrogate_save(const cfust_surrogate* s, const char* path);
 int cfust_surrogate_load(const char* path, cfust_surrogate** out);
 
+/* Fine-tunes the network for the E-step at Psi = (pi, mu, Sigma, Delta, nu):
+ * `samples` pairs drawn uniformly (seeded) from the n*g pairs give their
+ * two feature rows; rows inside the training range get GHK labels over the
+ * points u (FP64, as cfust_ghk_batch) and the network trains `epochs`
+ * passes over them (minibatches of 1024, learning rate 5e-4 cosine-annealed
+ * to 1e-6, standardisation kept).  *loss (host, may be NULL) receives the
+ * last epoch's mean loss, *rows (host, may be NULL) the rows trained on. */
+int cfust_surrogate_adapt(cfust_surrogate* s, const double* y, int64_t n, int p, int q, int g,
+                          const double* pi, const double* mu, const double* Sigma,
+                          const double* Delta, const double* nu, const double* u, int n_qmc,
+                          int64_t samples, int epochs, unsigned long long seed,
+                          const cfust_opts* opts, double* loss, int64_t* rows);
+
 /* Pairs the last E-step with this handle sent to the GHK kernel (outside the
  * training range). */
 int64_t cfust_surrogate_fallback_count(const cfust_surrogate* s);
+
+/* Index of the first GHK E-step in the trace of the last cfust_em_fit with
+ * this handle (the switch from surrogate to GHK E-steps), -1 if the fit
+ * stopped before switching. */
+int cfust_surrogate_em_switch(const cfust_surrogate* s);
 
 /* Raw feature rows of every pair at Psi: out device [n*g*2][F], row 2(j g + i)
  * for integral A and 2(j g + i) + 1 for integral B. */

@@ -34,6 +34,7 @@ struct cfust_surrogate {
   float h_std[CFUST_SURR_STD];
   bool have_std = false;
   int64_t adam_t = 0;
+  int em_switch = -1;                      // first GHK E-step of the last cfust_em_fit
   unsigned long long* fb_total = nullptr;  // device: fallback pairs of the last E-step
   // inference buffers (pairs per chunk)
   int64_t cap_pairs = 0;
@@ -593,8 +594,20 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   clear_status(ws, pl);
   *n_iter = 0;
   int result = CFUST_OK;
+  // With a surrogate: phase 1 runs surrogate E-steps until Aitken's rule
+  // stops; the next E-step re-evaluates the same parameters with the GHK
+  // kernel and phase 2 continues with GHK E-steps until the rule stops again.
+  cfust_surrogate* surr = ws.surr;
+  if (surr) surr->em_switch = -1;
+  int phase_start = 0;
   for (int t = 0;; ++t) {
     const bool last = t == o->max_iter;
+    if (ws.surr && o->adapt_samples > 0) {
+      result = cfust_surrogate_adapt(ws.surr, y, n, p, q, g, pi, mu, Sigma, Delta, nu, u, n_qmc,
+                                     o->adapt_samples, o->adapt_epochs,
+                                     (unsigned long long)t + 1, o, nullptr, nullptr);
+      if (result) break;
+    }
     if (o->precision == CFUST_FP32)
       result = run_estep<float>(ws, pl, y, pi, mu, Sigma, Delta, nu, u, t == 0, !last, stats,
                                 ll_dev, nullptr, nullptr);
@@ -610,11 +623,18 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
     if ((result = fetch_status(ws, pl, bad_component))) break;
     loglik_trace[t] = ll;
     *n_iter = t;
-    if (t >= 2) {
+    bool conv = false;
+    if (t - phase_start >= 2) {
       double linf = cfust_aitken_linf(loglik_trace[t - 2], loglik_trace[t - 1], ll);
-      if (fabs(linf - ll) < o->tol) break;
+      conv = fabs(linf - ll) < o->tol;
     }
-    if (last) break;
+    if (conv && ws.surr && !last) {
+      ws.surr = nullptr;
+      surr->em_switch = t + 1;
+      phase_start = t + 1;
+      continue;
+    }
+    if (conv || last) break;
     run_mstep(ws, pl, n, stats, mu, Delta, nu, o, pi, mu, Sigma, Delta, nu);
   }
   if (result == CFUST_OK) {
@@ -1332,16 +1352,21 @@ float set_loss_weights(cfust_surrogate* s, const float* wo, hipStream_t st) {
   return sum;
 }
 
-int set_std_from_data(cfust_surrogate* s, const double* feat, const double* targ, int64_t M,
+// label rows -> network rows in a stream-ordered temporary (caller frees)
+int network_rows(cfust_surrogate* s, const double* targ, int64_t M, hipStream_t st, double** nt) {
+  *nt = nullptr;
+  if (hipMallocAsync((void**)nt, (size_t)M * s->T * sizeof(double), st) != hipSuccess)
+    return CFUST_ENOMEM;
+  net_targets_kernel<<<(unsigned)((M + 255) / 256), 256, 0, st>>>(targ, M, s->q, s->T, *nt);
+  return launch_check();
+}
+
+// standardisation from features and network rows
+int set_std_from_data(cfust_surrogate* s, const double* feat, const double* nt, int64_t M,
                       hipStream_t st) {
   col_moments_kernel<<<s->F, 256, 0, st>>>(feat, M, s->F, s->stdv, s->stdv + kMlpPad);
-  double* nt = nullptr;
-  if (hipMallocAsync((void**)&nt, (size_t)M * s->T * sizeof(double), st) != hipSuccess)
-    return CFUST_ENOMEM;
-  net_targets_kernel<<<(unsigned)((M * s->T + 255) / 256), 256, 0, st>>>(targ, M, s->q, s->T, nt);
   col_moments_kernel<<<s->T, 256, 0, st>>>(nt, M, s->T, s->stdv + 2 * kMlpPad,
                                            s->stdv + 3 * kMlpPad);
-  (void)hipFreeAsync(nt, st);
   if (hipMemcpyAsync(s->h_std, s->stdv, sizeof(s->h_std), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -1362,6 +1387,22 @@ void launch_pair_features(int q, unsigned nb, hipStream_t st, const double* y, i
     case 6: pair_features_kernel<6, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
     case 7: pair_features_kernel<7, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
     case 8: pair_features_kernel<8, PM><<<nb, 128, 0, st>>>(y, n, p, g, mu, comp, out, status); break;
+  }
+}
+
+template <int PM>
+void launch_features_list(int q, unsigned nb, hipStream_t st, const double* y, int p, int g,
+                          const double* mu, const double* comp, const int64_t* pick, int64_t m,
+                          double* out, int* status) {
+  switch (q) {
+    case 1: pair_features_list_kernel<1, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 2: pair_features_list_kernel<2, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 3: pair_features_list_kernel<3, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 4: pair_features_list_kernel<4, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 5: pair_features_list_kernel<5, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 6: pair_features_list_kernel<6, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 7: pair_features_list_kernel<7, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
+    case 8: pair_features_list_kernel<8, PM><<<nb, 128, 0, st>>>(y, p, g, mu, comp, pick, m, out, status); break;
   }
 }
 
@@ -1441,14 +1482,25 @@ int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* 
   hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
   int rc = ensure_train(s, batch);
   if (rc) return rc;
-  if (!s->have_std && (rc = set_std_from_data(s, feat, targ, M, st))) return rc;
+  double* nt = nullptr;
+  if ((rc = network_rows(s, targ, M, st, &nt))) {
+    if (nt) (void)hipFreeAsync(nt, st);
+    return rc;
+  }
+  if (!s->have_std && (rc = set_std_from_data(s, feat, nt, M, st))) {
+    (void)hipFreeAsync(nt, st);
+    return rc;
+  }
   const float wsum = set_loss_weights(s, wo, st);
-  if (!(wsum > 0.f)) return CFUST_EINVAL;
   int64_t* idx = nullptr;
   double* lacc = nullptr;
-  if (hipMallocAsync((void**)&idx, M * sizeof(int64_t), st) != hipSuccess) return CFUST_ENOMEM;
+  if (!(wsum > 0.f) || hipMallocAsync((void**)&idx, M * sizeof(int64_t), st) != hipSuccess) {
+    (void)hipFreeAsync(nt, st);
+    return wsum > 0.f ? CFUST_ENOMEM : CFUST_EINVAL;
+  }
   if (hipMallocAsync((void**)&lacc, (epochs + 1) * sizeof(double), st) != hipSuccess) {
     (void)hipFreeAsync(idx, st);
+    (void)hipFreeAsync(nt, st);
     return CFUST_ENOMEM;
   }
   (void)hipMemsetAsync(lacc, 0, (epochs + 1) * sizeof(double), st);
@@ -1470,7 +1522,7 @@ int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* 
       const int64_t B = std::min<int64_t>(batch, M - b0);
       const int64_t Bp = round64(B);
       gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-          feat, targ, idx, b0, B, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad,
+          feat, nt, idx, b0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
           s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->tX, s->tT);
       forward_backward(s, B, Bp, wsum, lacc, ep, st);
       ++s->adam_t;
@@ -1497,6 +1549,7 @@ int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* 
   }
   (void)hipFreeAsync(idx, st);
   (void)hipFreeAsync(lacc, st);
+  (void)hipFreeAsync(nt, st);
   if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = CFUST_EHIP;
   return rc;
 }
@@ -1511,11 +1564,19 @@ int cfust_surrogate_grad(cfust_surrogate* s, const double* feat, const double* t
   if (rc) return rc;
   const float wsum = set_loss_weights(s, wo, st);
   if (!(wsum > 0.f)) return CFUST_EINVAL;
+  double* nt = nullptr;
+  if ((rc = network_rows(s, targ, M, st, &nt))) {
+    if (nt) (void)hipFreeAsync(nt, st);
+    return rc;
+  }
   double* lacc = nullptr;
-  if (hipMallocAsync((void**)&lacc, sizeof(double), st) != hipSuccess) return CFUST_ENOMEM;
+  if (hipMallocAsync((void**)&lacc, sizeof(double), st) != hipSuccess) {
+    (void)hipFreeAsync(nt, st);
+    return CFUST_ENOMEM;
+  }
   (void)hipMemsetAsync(lacc, 0, sizeof(double), st);
   gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-      feat, targ, nullptr, 0, M, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad, s->stdv + 2 * kMlpPad,
+      feat, nt, nullptr, 0, M, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad, s->stdv + 2 * kMlpPad,
       s->stdv + 3 * kMlpPad, s->tX, s->tT);
   forward_backward(s, M, Bp, wsum, lacc, 0, st);
   rc = launch_check();
@@ -1524,6 +1585,7 @@ int cfust_surrogate_grad(cfust_surrogate* s, const double* feat, const double* t
               hipMemcpyAsync(loss, lacc, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess))
     rc = CFUST_EHIP;
   (void)hipFreeAsync(lacc, st);
+  (void)hipFreeAsync(nt, st);
   if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = CFUST_EHIP;
   return rc;
 }
@@ -1541,7 +1603,7 @@ int cfust_surrogate_eval(cfust_surrogate* s, const double* feat, int64_t M, cons
     const int64_t B = std::min(chunk_rows, M - r0);
     const int64_t Bp = round64(B);
     gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-        feat, nullptr, nullptr, r0, B, Bp, s->F, s->T, s->q, s->stdv, s->stdv + kMlpPad,
+        feat, nullptr, nullptr, r0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
         s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->X, nullptr);
     mlp_forward(s, s->X, Bp, H, nullptr, s->P, st);
     unstd_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(
@@ -1642,6 +1704,126 @@ int64_t cfust_surrogate_fallback_count(const cfust_surrogate* s) {
   unsigned long long v = 0;
   if (hipMemcpy(&v, s->fb_total, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
   return (int64_t)v;
+}
+
+int cfust_surrogate_em_switch(const cfust_surrogate* s) { return s ? s->em_switch : -1; }
+
+int cfust_surrogate_adapt(cfust_surrogate* s, const double* y, int64_t n, int p, int q, int g,
+                          const double* pi, const double* mu, const double* Sigma,
+                          const double* Delta, const double* nu, const double* u, int n_qmc,
+                          int64_t samples, int epochs, unsigned long long seed,
+                          const cfust_opts* o, double* loss, int64_t* rows) {
+  if (loss) *loss = 0.0;
+  if (rows) *rows = 0;
+  int rc = check_dims(n, p, q, g, n_qmc);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!s || !y || !pi || !mu || !Sigma || !Delta || !nu || !u || n < 1 || samples < 1 ||
+      epochs < 0 || s->q != q || !s->have_std)
+    return CFUST_EINVAL;
+  cfust_opts oo;
+  cfust_default_opts(&oo);
+  oo.stream = o ? o->stream : nullptr;
+  Plan pl = make_plan(0, p, q, g, 1, CFUST_FP64);
+  Ws ws;
+  if ((rc = acquire(pl, &oo, &ws))) return rc;
+  hipStream_t st = ws.st;
+  clear_status(ws, pl);
+  const double* comp = ws.at<double>(pl.o_comp);
+  int* status = ws.at<int>(pl.o_status);
+  precompute_kernel<<<1, 64, 0, st>>>(p, q, g, pi, Sigma, Delta, mu, nu,
+                                      ws.at<double>(pl.o_comp), status);
+  // uniform sample of pairs (with replacement)
+  const int64_t pairs = n * g;
+  const int F = s->F, T = s->T;
+  std::vector<int64_t> pick((size_t)samples);
+  Rng rng{seed * 0x9E3779B97F4A7C15ull + 0x5851F42D4C957F2Dull};
+  for (auto& k : pick) k = (int64_t)(rng.next() % (uint64_t)pairs);
+  int64_t* pick_d = nullptr;
+  double* feat_d = nullptr;
+  if (hipMallocAsync((void**)&pick_d, samples * sizeof(int64_t), st) != hipSuccess ||
+      hipMallocAsync((void**)&feat_d, (size_t)2 * samples * F * sizeof(double), st) !=
+          hipSuccess) {
+    if (pick_d) (void)hipFreeAsync(pick_d, st);
+    release(&ws);
+    return CFUST_ENOMEM;
+  }
+  (void)hipMemcpyAsync(pick_d, pick.data(), samples * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  const unsigned nb = (unsigned)((samples + 127) / 128);
+  if (p <= 8)
+    launch_features_list<8>(q, nb, st, y, p, g, mu, comp, pick_d, samples, feat_d, status);
+  else
+    launch_features_list<kMaxP>(q, nb, st, y, p, g, mu, comp, pick_d, samples, feat_d, status);
+  std::vector<double> fh((size_t)2 * samples * F);
+  rc = launch_check();
+  if (!rc && hipMemcpyAsync(fh.data(), feat_d, fh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            st) != hipSuccess)
+    rc = CFUST_EHIP;
+  if (!rc) rc = fetch_status(ws, pl, nullptr);
+  (void)hipFreeAsync(pick_d, st);
+  (void)hipFreeAsync(feat_d, st);
+  if (rc) {
+    release(&ws);
+    return rc;
+  }
+  // rows inside the training range
+  const SurrRange& r = s->rg;
+  std::vector<double> hs, Rs, dofs, fs;
+  for (int64_t k = 0; k < 2 * samples; ++k) {
+    const double* f = fh.data() + k * F;
+    bool in = f[F - 1] >= r.dof_lo && f[F - 1] <= r.dof_hi;
+    for (int a = 0; a < q && in; ++a) in = f[a] >= r.h_lo && f[a] <= r.h_hi;
+    for (int a = q; a < F - 1 && in; ++a) in = fabs(f[a]) <= r.r_max;
+    if (!in) continue;
+    fs.insert(fs.end(), f, f + F);
+    hs.insert(hs.end(), f, f + q);
+    dofs.push_back(f[F - 1]);
+    const size_t b = Rs.size();
+    Rs.resize(b + (size_t)q * q);
+    int t = q;
+    for (int a = 0; a < q; ++a) {
+      Rs[b + a * q + a] = 1.0;
+      for (int c = a + 1; c < q; ++c, ++t) {
+        Rs[b + a * q + c] = f[t];
+        Rs[b + c * q + a] = f[t];
+      }
+    }
+  }
+  const int64_t M = (int64_t)dofs.size();
+  if (rows) *rows = M;
+  if (M == 0 || epochs == 0) {
+    release(&ws);
+    return CFUST_OK;
+  }
+  double *h_d = nullptr, *R_d = nullptr, *dof_d = nullptr, *f_d = nullptr, *lab_d = nullptr;
+  bool ok = hipMallocAsync((void**)&h_d, hs.size() * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&R_d, Rs.size() * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&dof_d, dofs.size() * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&f_d, fs.size() * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&lab_d, (size_t)M * T * sizeof(double), st) == hipSuccess;
+  if (ok) {
+    (void)hipMemcpyAsync(h_d, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(R_d, Rs.data(), Rs.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(dof_d, dofs.data(), dofs.size() * sizeof(double), hipMemcpyHostToDevice,
+                         st);
+    (void)hipMemcpyAsync(f_d, fs.data(), fs.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    rc = run_ghk_batch<double>(q, M, h_d, R_d, dof_d, u, n_qmc, lab_d, st);
+    if (!rc) {
+      std::vector<float> wo((size_t)T, 1.0f);
+      wo[0] = (float)(T - 1);
+      std::vector<double> trace((size_t)epochs);
+      rc = cfust_surrogate_train(s, f_d, lab_d, M, epochs, 1024, 5e-4, 1e-6, seed, wo.data(), &oo,
+                                 trace.data());
+      if (!rc && loss) *loss = trace[epochs - 1];
+    }
+  } else {
+    rc = CFUST_ENOMEM;
+  }
+  for (double* ptr : {h_d, R_d, dof_d, f_d, lab_d})
+    if (ptr) (void)hipFreeAsync(ptr, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = CFUST_EHIP;
+  release(&ws);
+  return rc;
 }
 
 int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const double* pi,

@@ -341,41 +341,80 @@ __global__ __launch_bounds__(256) void col_moments_kernel(const double* __restri
 }
 
 // The network's outputs for a truncated-t problem of dimension q are
-//   log P(V <= h) | m1 = E[V | V <= h] (q) | Cov(V | V <= h) (upper triangle)
-// while the labels carry E[V V^T | V <= h] in place of the covariance: the
-// covariance stays within the untruncated t variance whereas E[V V^T] grows
-// like h h^T.  Column o of the label row in network form:
-__device__ __forceinline__ double net_target(const double* __restrict__ row, int q, int o) {
-  if (o < 1 + q) return row[o];
-  int t = o - 1 - q;
-  int a = 0;
-  while (t >= q - a) {
-    t -= q - a;
-    ++a;
+//   log P(V <= h) | m1 = E[V | V <= h] (q) | U (q(q+1)/2)
+// with Cov(V | V <= h) = U^T U, U upper triangular packed row by row and its
+// diagonal stored as logarithms: every prediction is a positive definite
+// covariance.  The labels carry E[V V^T | V <= h] (upper triangle) instead.
+constexpr int kNetMaxQ = 8;
+
+// label row -> network row (Cov = E[VV^T] - m1 m1^T factored by Cholesky).
+// Squared pivots are floored at kPivotFloor: a truncated t with unit-scale
+// margins and bounds in the training box has conditional variances far
+// above it, so only degenerate estimates (all weight on a few points) are
+// affected, and they stay finite.
+constexpr double kPivotFloor = 1e-6;
+__device__ inline void net_row(const double* __restrict__ lab, int q, double* __restrict__ out) {
+  double U[kNetMaxQ * kNetMaxQ];
+  out[0] = lab[0];
+  for (int a = 0; a < q; ++a) out[1 + a] = lab[1 + a];
+  int c = 1 + q;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++c) U[a * q + b] = lab[c] - lab[1 + a] * lab[1 + b];
+  // Cov = U^T U: row a of U from the rows above it
+  for (int a = 0; a < q; ++a) {
+    double d = U[a * q + a];
+    for (int k = 0; k < a; ++k) d -= U[k * q + a] * U[k * q + a];
+    d = sqrt(fmax(d, kPivotFloor));
+    U[a * q + a] = d;
+    for (int b = a + 1; b < q; ++b) {
+      double t = U[a * q + b];
+      for (int k = 0; k < a; ++k) t -= U[k * q + a] * U[k * q + b];
+      U[a * q + b] = t / d;
+    }
   }
-  const int b = a + t;
-  return row[o] - row[1 + a] * row[1 + b];
+  c = 1 + q;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++c) out[c] = (a == b) ? log(U[a * q + a]) : U[a * q + b];
 }
 
-// targets of M label rows in network form (for the standardisation)
+// de-standardised network row (fp32 outputs P, width >= T) -> label row
+__device__ inline void label_row(const float* __restrict__ P, const float* __restrict__ my,
+                                 const float* __restrict__ sy, int q, double* __restrict__ out) {
+  double U[kNetMaxQ * kNetMaxQ];
+  for (int c = 0; c < 1 + q; ++c) out[c] = (double)P[c] * (double)sy[c] + (double)my[c];
+  int c = 1 + q;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++c) {
+      const double v = (double)P[c] * (double)sy[c] + (double)my[c];
+      U[a * q + b] = (a == b) ? exp(v) : v;
+    }
+  c = 1 + q;
+  for (int a = 0; a < q; ++a)
+    for (int b = a; b < q; ++b, ++c) {
+      double cov = 0.0;
+      for (int k = 0; k <= a; ++k) cov += U[k * q + a] * U[k * q + b];
+      out[c] = cov + out[1 + a] * out[1 + b];
+    }
+}
+
+// label rows -> network rows, one thread per row
 __global__ void net_targets_kernel(const double* __restrict__ targ, int64_t M, int q, int OUT,
                                    double* __restrict__ out) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M * OUT) return;
-  const int64_t r = t / OUT;
-  out[t] = net_target(targ + r * OUT, q, (int)(t % OUT));
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M) return;
+  net_row(targ + r * OUT, q, out + r * OUT);
 }
 
 // Standardised, padded rows: X[r] = (feat[idx[r]] - mx) / sx in bf16 (width
-// 64) and, when targ is given, T[r] = (net_target(targ[idx[r]]) - my) / sy
+// 64) and, when targ (network rows) is given, T[r] = (targ[idx[r]] - my) / sy
 // (fp32, width OUT).  Rows r >= B (padding to a multiple of 64) are zero;
 // idx NULL means row base + r.
 __global__ void gather_rows_kernel(const double* __restrict__ feat, const double* __restrict__ targ,
                                    const int64_t* __restrict__ idx, int64_t base, int64_t B,
-                                   int64_t Bp, int IN, int OUT, int q,
-                                   const float* __restrict__ mx, const float* __restrict__ sx,
-                                   const float* __restrict__ my, const float* __restrict__ sy,
-                                   bf16* __restrict__ X, float* __restrict__ T) {
+                                   int64_t Bp, int IN, int OUT, const float* __restrict__ mx,
+                                   const float* __restrict__ sx, const float* __restrict__ my,
+                                   const float* __restrict__ sy, bf16* __restrict__ X,
+                                   float* __restrict__ T) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Bp * kMlpPad) return;
   const int64_t r = t / kMlpPad;
@@ -386,25 +425,18 @@ __global__ void gather_rows_kernel(const double* __restrict__ feat, const double
   X[t] = f2bf(xv);
   if (targ && c < OUT) {
     float tv = 0.f;
-    if (r < B) tv = (float)((net_target(targ + s * OUT, q, c) - (double)my[c]) / (double)sy[c]);
+    if (r < B) tv = (float)((targ[s * OUT + c] - (double)my[c]) / (double)sy[c]);
     T[r * OUT + c] = tv;
   }
 }
 
-// De-standardised network outputs in label form (E[V V^T] = Cov + m1 m1^T):
-// one thread per row r < B
+// network outputs of rows r < B back to label rows (double), one thread per row
 __global__ void unstd_kernel(const float* __restrict__ P, int64_t B, int OUT, int q,
                              const float* __restrict__ my, const float* __restrict__ sy,
                              double* __restrict__ out) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= B) return;
-  const float* pr = P + r * kMlpPad;
-  double* o = out + r * OUT;
-  for (int c = 0; c < 1 + q; ++c) o[c] = (double)pr[c] * (double)sy[c] + (double)my[c];
-  int c = 1 + q;
-  for (int a = 0; a < q; ++a)
-    for (int b = a; b < q; ++b, ++c)
-      o[c] = (double)pr[c] * (double)sy[c] + (double)my[c] + o[1 + a] * o[1 + b];
+  label_row(P + r * kMlpPad, my, sy, q, out + r * OUT);
 }
 
 }  // namespace cfust

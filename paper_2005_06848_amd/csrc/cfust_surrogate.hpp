@@ -7,7 +7,7 @@
 // matrix of Lambda_i = I - Delta^T Omega^-1 Delta and D = sqrt(diag Lambda).
 // The network maps the feature row (h, the q(q-1)/2 correlations above the
 // diagonal of R row by row, dof) to (log P(V <= h), E[V | V <= h],
-// Cov(V | V <= h) upper triangle).  A pair whose features leave the
+// Cov(V | V <= h) = U^T U with U upper triangular).  A pair whose features leave the
 // training range is evaluated by the GHK kernel instead (QMC fallback).
 #pragma once
 #include "cfust_kernels.hpp"
@@ -246,11 +246,12 @@ __global__ __launch_bounds__(256) void surr_assemble_kernel(
   pair_geometry<Q, PM>(y + j * p, p, mu + (size_t)i * p, cp, d, c);
   const float* my = stdv + 2 * kMlpPad;
   const float* sy = stdv + 3 * kMlpPad;
-  const float* PA = P + (size_t)(2 * t) * kMlpPad;
-  const float* PB = P + (size_t)(2 * t + 1) * kMlpPad;
-  auto un = [&](const float* row, int o) { return (double)row[o] * (double)sy[o] + (double)my[o]; };
-  const double logTA = un(PA, 0);
-  const double logTB = un(PB, 0);
+  // integral A: log T only; integral B: the whole label row
+  const double logTA =
+      (double)P[(size_t)(2 * t) * kMlpPad] * (double)sy[0] + (double)my[0];
+  double lb[1 + Q + NT];
+  label_row(P + (size_t)(2 * t + 1) * kMlpPad, my, sy, Q, lb);
+  const double logTB = lb[0];
   const double v = cp[cl.nu];
   const double aa = 0.5 * (v + p);
   const double bb = 0.5 * (v + d);
@@ -264,17 +265,16 @@ __global__ __launch_bounds__(256) void surr_assemble_kernel(
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     Ds[k] = sc * cp[cl.D + k];
-    mx[k] = Ds[k] * un(PB, 1 + k);
+    mx[k] = Ds[k] * lb[1 + k];
   }
 #pragma unroll
   for (int k = 0; k < Q; ++k) rec[3 + k] = e2 * (c[k] - mx[k]);
   int u = 0;
-  // E[V V^T] = Cov + m1 m1^T (the network predicts the covariance)
 #pragma unroll
   for (int a = 0; a < Q; ++a)
 #pragma unroll
     for (int b = a; b < Q; ++b) {
-      const double m2 = un(PB, 1 + Q + u) + un(PB, 1 + a) * un(PB, 1 + b);
+      const double m2 = lb[1 + Q + u];
       const double exx = c[a] * c[b] - c[a] * mx[b] - mx[a] * c[b] + Ds[a] * m2 * Ds[b];
       rec[3 + Q + u] = e2 * exx;
       ++u;
@@ -316,6 +316,49 @@ __global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v) {
 }
 __global__ void add_count_kernel(const unsigned int* c, unsigned long long* total) {
   if (threadIdx.x == 0 && blockIdx.x == 0) total[0] += c[0];
+}
+
+// raw feature rows of listed pairs (2 per listed pair, A then B), same
+// layout as pair_features_kernel
+template <int Q, int PM>
+__global__ void pair_features_list_kernel(const double* __restrict__ y, int p, int g,
+                                          const double* __restrict__ mu,
+                                          const double* __restrict__ comp,
+                                          const int64_t* __restrict__ pick, int64_t m,
+                                          double* __restrict__ out, int* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  constexpr int NR = Q * (Q - 1) / 2;
+  constexpr int F = Q + NR + 1;
+  const int64_t pair = pick[e];
+  const int64_t j = pair / g;
+  const int i = (int)(pair - j * g);
+  const CompLayout cl(p, Q);
+  const double* cp = comp + (size_t)i * cl.stride;
+  double d, c[Q], hA[Q], hB[Q];
+  if (!pair_geometry<Q, PM>(y + j * p, p, mu + (size_t)i * p, cp, d, c))
+    set_status(status, kENonFinite, -1);
+  pair_bounds<Q>(cp, p, d, c, hA, hB);
+  const double* C = cp + cl.C;
+  double* oa = out + (size_t)(2 * e) * F;
+  double* ob = oa + F;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    oa[k] = hA[k];
+    ob[k] = hB[k];
+  }
+  int t = Q;
+  for (int k = 0; k < Q; ++k)
+    for (int l = k + 1; l < Q; ++l) {
+      double sum = 0.0;
+      for (int mm = 0; mm <= k; ++mm) sum += C[k * Q + mm] * C[l * Q + mm];
+      oa[t] = sum;
+      ob[t] = sum;
+      ++t;
+    }
+  const double v = cp[cl.nu];
+  oa[F - 1] = v + p;
+  ob[F - 1] = v + p + 2.0;
 }
 
 // raw feature rows of every pair (2 per pair, A then B):

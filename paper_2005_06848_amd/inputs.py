@@ -256,13 +256,14 @@ def _true_params_separated(rng, p, q, g, nu, delta_half):
                 nu=np.asarray(nu, float))
 
 
-def config(k: int, n: int | None = None, seed: int | None = None):
+def config(k: int, n: int | None = None, seed: int | None = None, kmeans_restarts: int = 8):
     """Return a dict with y, the true parameters, Psi^(0), u and sizes for workload k.
 
     ``n`` overrides the number of observations (the draws for the first
     observations do not depend on it for workloads 1-3 and 5 only through the
     label draw, so tests use it for reduced copies of the same recipe).
     ``seed`` replaces the workload's own seed: another draw of the same recipe.
+    ``kmeans_restarts`` sets the restarts of the k-means++ start (Psi^(0)).
     """
     rng = np.random.default_rng(SEED_BASE + k if seed is None else seed)
     if k == 1:
@@ -288,7 +289,7 @@ def config(k: int, n: int | None = None, seed: int | None = None):
     else:
         raise ValueError("workload 4 is built by batched_problems()")
     y, z = sample_cfust(rng, n, **true)
-    lab = kmeans_pp(rng, y, g)
+    lab = kmeans_pp(rng, y, g, n_init=kmeans_restarts)
     init = init_from_partition(y, lab, g, q)
     u = qmc_points(N, q)
     return dict(k=k, n=n, p=p, q=q, g=g, n_qmc=N, iters=iters, y=y, labels=z,

@@ -43,6 +43,8 @@ class Opts(ctypes.Structure):
         ("graph", ctypes.c_int),
         ("tile", ctypes.c_int),
         ("surrogate", ctypes.c_void_p),
+        ("adapt_samples", ctypes.c_int),
+        ("adapt_epochs", ctypes.c_int),
     ]
 
 
@@ -126,6 +128,12 @@ def _lib():
         L.cfust_surrogate_load.restype = i
         L.cfust_surrogate_fallback_count.argtypes = [P]
         L.cfust_surrogate_fallback_count.restype = i64
+        L.cfust_surrogate_adapt.argtypes = [P, P, i64, i, i, i, P, P, P, P, P, P, i, i64, i,
+                                            ctypes.c_ulonglong, ctypes.POINTER(Opts),
+                                            ctypes.POINTER(d), ctypes.POINTER(i64)]
+        L.cfust_surrogate_adapt.restype = i
+        L.cfust_surrogate_em_switch.argtypes = [P]
+        L.cfust_surrogate_em_switch.restype = i
         L.cfust_pair_features.argtypes = [P, i64, i, i, i, P, P, P, P, P, ctypes.POINTER(Opts), P]
         L.cfust_pair_features.restype = i
         L.cfust_mlp_gemm.argtypes = [i, i, i, i, i, P, P, P, P]
@@ -154,7 +162,7 @@ def _ptr(t):
 
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
               nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0,
-              surrogate=None):
+              surrogate=None, adapt_samples=0, adapt_epochs=0):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -176,6 +184,8 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
     o.tile = int(tile)
     if surrogate is not None:
         o.surrogate = surrogate.handle
+    o.adapt_samples = int(adapt_samples)
+    o.adapt_epochs = int(adapt_epochs)
     return o
 
 
@@ -478,6 +488,27 @@ class Surrogate:
 
     def fallback_count(self):
         return int(_lib().cfust_surrogate_fallback_count(self.handle))
+
+    def adapt(self, y, params, u, samples=16384, epochs=100, seed=1, **opt):
+        """Fine-tune on GHK labels of `samples` random pairs at params; returns
+        (last-epoch loss, rows trained on)."""
+        y = _dev(y, "y")
+        u = _dev(u, "u")
+        (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
+        loss = ctypes.c_double(0)
+        rows = ctypes.c_int64(0)
+        o = make_opts(**opt)
+        rc = _lib().cfust_surrogate_adapt(self.handle, _ptr(y), y.shape[0], p, q, g, _ptr(pi),
+                                          _ptr(mu), _ptr(Sigma), _ptr(Delta), _ptr(nu), _ptr(u),
+                                          u.shape[0], int(samples), int(epochs), int(seed),
+                                          ctypes.byref(o), ctypes.byref(loss), ctypes.byref(rows))
+        if rc:
+            raise CfustError(rc, "cfust_surrogate_adapt")
+        return loss.value, rows.value
+
+    def em_switch(self):
+        """First GHK E-step of the last two-phase cfust_em_fit (-1: none)."""
+        return int(_lib().cfust_surrogate_em_switch(self.handle))
 
 
 def cfust_pair_features(y, params, **opt):

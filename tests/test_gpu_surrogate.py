@@ -85,14 +85,32 @@ def test_ghk_batch_rejects_indefinite(dev):
 
 
 def net_form(t, q):
-    """Label rows (log T | m1 | E[VV^T]) in the network's form (log T | m1 | Cov)."""
+    """Label rows (log T | m1 | E[VV^T] upper) in the network's form
+    (log T | m1 | U upper with log diagonal, Cov = m2 - m1 m1^T = U^T U)."""
     out = np.array(t, dtype=np.float64, copy=True)
-    c = 1 + q
-    for a in range(q):
-        for b in range(a, q):
-            out[:, c] = t[:, c] - t[:, 1 + a] * t[:, 1 + b]
-            c += 1
+    iu = np.triu_indices(q)
+    for r in range(len(t)):
+        m2 = np.zeros((q, q))
+        m2[iu] = t[r, 1 + q:]
+        m2 = m2 + np.triu(m2, 1).T
+        m1 = t[r, 1:1 + q]
+        U = np.linalg.cholesky(m2 - np.outer(m1, m1)).T
+        U[np.arange(q), np.arange(q)] = np.log(np.diag(U))
+        out[r, 1 + q:] = U[iu]
     return out
+
+
+def label_rows(rng, m, q):
+    """Random valid label rows: log T, m1, E[VV^T] = Cov + m1 m1^T."""
+    iu = np.triu_indices(q)
+    t = np.empty((m, 1 + q + len(iu[0])))
+    t[:, 0] = -rng.exponential(3.0, size=m)
+    for r in range(m):
+        m1 = rng.standard_normal(q)
+        A = rng.standard_normal((q, q)) * 0.5
+        t[r, 1:1 + q] = m1
+        t[r, 1 + q:] = (A @ A.T + 0.1 * np.eye(q) + np.outer(m1, m1))[iu]
+    return t
 
 
 def _net_and_batch(dev, seed, m):
@@ -104,7 +122,7 @@ def _net_and_batch(dev, seed, m):
     h, R, dof = inputs.surrogate_samples(rng, m, q)
     from paper_2005_06848_amd.surrogate import feature_rows
     feat = feature_rows(h, R, dof)
-    targ = rng.standard_normal((m, Tw)) * 2.0 + 0.5
+    targ = label_rows(rng, m, q)
     stdv = np.zeros(native.SURR_STD, dtype=np.float32)
     stdv[:F] = feat.mean(0)
     stdv[64:64 + F] = np.maximum(feat.std(0), 1e-3)
@@ -160,9 +178,17 @@ def test_surrogate_training_lowers_loss(dev):
     trace = net.train(feat, targ, 8, batch=1024, lr0=2e-3, lr1=2e-4)
     print("  loss trace", ["%.3e" % x for x in trace])
     assert all(np.isfinite(trace)) and all(b < a for a, b in zip(trace, trace[1:]))
-    after = np.mean((net.eval(feat).cpu().numpy() - t) ** 2, 0)
+    out = net.eval(feat).cpu().numpy()
+    after = np.mean((out - t) ** 2, 0)
     print("  eval MSE after / before:", np.round(after / before, 3).tolist())
     assert np.all(after < 0.5 * before)
+    # every predicted covariance E[VV^T] - m1 m1^T is positive definite
+    iu = np.triu_indices(q)
+    m2 = np.zeros((len(out), q, q))
+    m2[:, iu[0], iu[1]] = out[:, 1 + q:]
+    m2 = m2 + np.triu(m2, 1).transpose(0, 2, 1)
+    cov = m2 - out[:, 1:1 + q, None] * out[:, None, 1:1 + q]
+    assert np.linalg.eigvalsh(cov).min() > 0
 
 
 def test_pair_features_definition(dev):
@@ -209,3 +235,110 @@ def test_out_of_range_pairs_fall_back_to_ghk(dev):
     assert net.fallback_count() == c["n"] * c["g"]
     for k in ("tau", "logf", "e2", "e3", "e4", "stats", "loglik"):
         assert np.array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy()), k
+
+
+# ---------------------------------------------------------------------------
+# the trained network shipped with the package (trained on the GPU by
+# ``python -m paper_2005_06848_amd.surrogate``), judged by the GHK kernel
+# ---------------------------------------------------------------------------
+def _shipped():
+    from paper_2005_06848_amd import native, surrogate
+    return native.Surrogate.load(surrogate.DEFAULT_PATH)
+
+
+def _stats_err(got, ref):
+    g, r = got["stats"].cpu().numpy(), ref["stats"].cpu().numpy()
+    srel = np.abs(g - r).max(1) / np.abs(r).max(1)
+    ll = abs(got["loglik"].item() - ref["loglik"].item()) / abs(ref["loglik"].item())
+    return srel, ll
+
+
+def test_shipped_network_heldout_accuracy(dev):
+    """Held-out rows logged along EM runs on draws of the surrogate workload's
+    recipe that training never saw, labelled by the GHK kernel with 2^14
+    points (measured medians: log T 0.028, E[V] 0.027, E[VV^T] 0.045)."""
+    import torch
+    from paper_2005_06848_amd import inputs, surrogate as S
+    net = _shipped()
+    assert net.q == 6
+    print("[gpu] shipped network: held-out proposal rows", flush=True)
+    prop = S.proposal_rows(seeds=(9101,), n_obs=5000, per_iterate=5000)
+    u = T(inputs.qmc_points(S.N_LABEL, 6, seed=0x51), dev)
+    lab = S.label(prop[:, :6], S.corr_from_rows(prop[:, 6:-1]), prop[:, -1], u).cpu().numpy()
+    out = net.eval(T(prop, dev)).cpu().numpy()
+    d = np.abs(out - lab)
+    med = (np.median(d[:, 0]), np.median(d[:, 1:7]), np.median(d[:, 7:]))
+    print("  median |err| logT %.3e  E[V] %.3e  E[VV^T] %.3e" % med)
+    assert med[0] < 0.06 and med[1] < 0.06 and med[2] < 0.1
+
+
+def test_shipped_network_estep_and_adaptation(dev):
+    """E-step on the surrogate workload's own data (n=20000 subsample, at the
+    k-means start): the shipped network alone, then after one adaptation on
+    GHK labels of 16384 sampled pairs.  Bars: statistics within 5% / 1% of
+    the FP64 GHK E-step, log-likelihood within 1e-2 / 1e-4 relative."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=20000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    print("[gpu] surrogate E-step n=20000 q=6 N=8192", flush=True)
+    ref = native.cfust_estep(y, par, u)
+    net = _shipped()
+    s0, l0 = _stats_err(native.cfust_estep(y, par, u, surrogate=net), ref)
+    assert net.fallback_count() == 0
+    loss, rows = net.adapt(y, par, u, samples=16384, epochs=50)
+    s1, l1 = _stats_err(native.cfust_estep(y, par, u, surrogate=net), ref)
+    print(f"  shipped: stats {s0.max():.2e} loglik {l0:.2e}; adapted ({rows} rows, loss {loss:.2e}): "
+          f"stats {s1.max():.2e} loglik {l1:.2e}")
+    assert s0.max() < 5e-2 and l0 < 1e-2
+    assert s1.max() < 1e-2 and l1 < 1e-4
+
+
+def test_two_phase_em_tracks_ghk_em(dev):
+    """Adaptive two-phase EM against GHK EM from the same start (n=20000):
+    the log-likelihood traces agree within 1e-3 relative at every logged
+    iteration, and the fit switches to GHK E-steps before it ends."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=20000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    print("[gpu] two-phase EM n=20000, 60 iterations", flush=True)
+    rq = native.cfust_em_fit(y, par, u, max_iter=60, tol=0.5)
+    net = _shipped()
+    rs = native.cfust_em_fit(y, par, u, max_iter=60, tol=0.5, surrogate=net, adapt_samples=8192,
+                             adapt_epochs=10)
+    sw = net.em_switch()
+    tq, ts = np.array(rq["trace"]), np.array(rs["trace"])
+    k = min(len(tq), len(ts))
+    rel = np.abs(tq[:k] - ts[:k]) / np.abs(tq[:k])
+    print(f"  GHK {rq['n_iter']} its, two-phase {rs['n_iter']} its (switch at {sw}); "
+          f"max rel trace difference {rel.max():.2e}")
+    assert rel.max() < 1e-3
+
+
+def test_surrogate_estep_gain(dev):
+    """The gain: E-step time with the shipped network (and with one
+    adaptation first) against the FP64 GHK E-step, n=200000 p=q=6 g=4 N=8192."""
+    import time
+    import torch
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=200000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    net = _shipped()
+    print("[gpu] gain n=200000", flush=True)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+    t_ghk = timed(lambda: native.cfust_estep(y, par, u, want=()))
+    t_net = timed(lambda: native.cfust_estep(y, par, u, want=(), surrogate=net))
+    t_ad = timed(lambda: (net.adapt(y, par, u, samples=16384, epochs=20),
+                          native.cfust_estep(y, par, u, want=(), surrogate=net)))
+    print(f"  FP64 GHK {t_ghk * 1e3:.1f} ms, network {t_net * 1e3:.1f} ms "
+          f"({t_ghk / t_net:.0f}x), adaptation + network {t_ad * 1e3:.1f} ms ({t_ghk / t_ad:.1f}x)")
+    assert t_net * 20 < t_ghk and t_ad * 2 < t_ghk
