@@ -39,9 +39,9 @@ C_PHI, C_PHIINV, C_ACC = 40, 50, 20
 
 # HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (KiB per dispatch, scaled by the same counters on a plain copy kernel:
-# fetch x 1.99979, write x 0.99998); None when the kernel has changed since
+# fetch x 1.99980, write x 0.99998); None when the kernel has changed since
 # the counters were taken.
-TRAFFIC_BYTES_PER_LAUNCH = 15068030
+TRAFFIC_BYTES_PER_LAUNCH = 60822566
 # executed FP64 flops per launch of the same kernel from the SQ_INSTS_VALU_*_F64
 # counters (64 lanes, FMA = 2)
 EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.594e11
@@ -307,7 +307,7 @@ def main():
             "traffic": TRAFFIC_BYTES_PER_LAUNCH if args.precision == "fp64" else None,
             "kernel": f"pair_kernel<double,{q},true>",
             "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp}
-    if args.precision == "fp64":
+    if args.precision == "fp64" and EXECUTED_FP64_FLOPS_PER_LAUNCH:
         ex = EXECUTED_FP64_FLOPS_PER_LAUNCH / (pair_ms * 1e-3) / 1e12
         roof["executed_tflops"] = round(ex, 3)
         roof["executed_frac"] = round(ex / PEAK_FP64_VALU_TFLOPS, 4)

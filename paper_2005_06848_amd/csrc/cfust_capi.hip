@@ -245,7 +245,10 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   int64_t pairs = pl.n * pl.g;
   if (pairs == 0) return;
   unsigned blocks = (unsigned)((pairs + 3) / 4);
-  pair_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
+  // FP64 with q <= 4 fits four waves per SIMD with little spilling (2.5%
+  // faster at p=q=4); larger q spill heavily there and keep the default
+  constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4 : 0;
+  pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
       y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
       ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N, ws.at<double>(pl.o_pair),
       pl.W, ws.at<int>(pl.o_status));

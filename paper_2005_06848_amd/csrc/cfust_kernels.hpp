@@ -524,9 +524,11 @@ __host__ __device__ constexpr int record_width() {
   return MOM ? (3 + Q + Q * (Q + 1) / 2) : 1;
 }
 
-// one wave per pair, four pairs per 256-thread block
-template <typename T, int Q, bool MOM>
-__global__ __launch_bounds__(256) void pair_kernel(
+// one wave per pair, four pairs per 256-thread block; OCC > 0 asks for at
+// least OCC resident waves per SIMD (the register budget follows)
+template <typename T, int Q, bool MOM, int OCC = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+void pair_kernel(
     const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
     const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
