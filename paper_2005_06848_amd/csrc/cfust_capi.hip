@@ -38,7 +38,7 @@ struct cfust_surrogate {
   unsigned long long* fb_total = nullptr;  // device: fallback pairs of the last E-step
   // inference buffers (pairs per chunk)
   int64_t cap_pairs = 0;
-  bf16 *X = nullptr, *Ha = nullptr, *Hb = nullptr;
+  bf16* X = nullptr;
   float* P = nullptr;
   unsigned char* inr = nullptr;
   int64_t* list = nullptr;
@@ -313,6 +313,11 @@ void mlp_forward(const cfust_surrogate* s, const bf16* X, int64_t rows, bf16* co
   }
 }
 
+// inference: all four layers in one kernel per 64 rows (rows multiple of 64)
+void mlp_infer(const cfust_surrogate* s, const bf16* X, int64_t rows, float* P, hipStream_t st) {
+  if (rows > 0) mlp_infer_kernel<<<(unsigned)(rows / 64), 256, 0, st>>>(X, s->wb, s->params, P);
+}
+
 template <typename X>
 bool dev_alloc(X** p, size_t count) {
   if (*p) (void)hipFree(*p);
@@ -324,8 +329,7 @@ bool dev_alloc(X** p, size_t count) {
 int ensure_infer(cfust_surrogate* s, int64_t pairs) {
   if (pairs <= s->cap_pairs) return CFUST_OK;
   const int64_t rows = round64(2 * pairs);
-  bool ok = dev_alloc(&s->X, rows * kMlpPad) && dev_alloc(&s->Ha, rows * kMlpHid) &&
-            dev_alloc(&s->Hb, rows * kMlpHid) && dev_alloc(&s->P, rows * kMlpPad) &&
+  bool ok = dev_alloc(&s->X, rows * kMlpPad) && dev_alloc(&s->P, rows * kMlpPad) &&
             dev_alloc(&s->inr, pairs) && dev_alloc(&s->list, pairs);
   if (!ok) {
     s->cap_pairs = 0;
@@ -351,7 +355,6 @@ int launch_surrogate_pairs_q(const Ws& ws, const Plan& pl, const double* y, cons
   int* status = ws.at<int>(pl.o_status);
   surr_comp_kernel<<<1, 64, 0, ws.st>>>(pl.p, pl.q, pl.g, comp, s->rg, s->stdv, s->cf, s->cok);
   fill_u64_kernel<<<1, 64, 0, ws.st>>>(s->fb_total, 0ull);
-  bf16* const H[3] = {s->Ha, s->Hb, s->Ha};
   for (int64_t c0 = 0; c0 < pairs; c0 += chunk) {
     const int64_t cn = std::min(chunk, pairs - c0);
     const unsigned nb = (unsigned)((cn + 255) / 256);
@@ -359,7 +362,7 @@ int launch_surrogate_pairs_q(const Ws& ws, const Plan& pl, const double* y, cons
     surr_feat_kernel<Q, PM><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->rg, s->stdv,
                                                s->cf, s->cok, s->X, s->inr, s->list, s->count,
                                                status);
-    mlp_forward(s, s->X, round64(2 * cn), H, nullptr, s->P, ws.st);
+    mlp_infer(s, s->X, round64(2 * cn), s->P, ws.st);
     surr_assemble_kernel<Q, PM><<<nb, 256, 0, ws.st>>>(y, pl.p, pl.g, mu, comp, c0, cn, s->P,
                                                    s->stdv, s->inr, ws.at<double>(pl.o_pair),
                                                    pl.W);
@@ -1244,7 +1247,7 @@ int surr_targ_width(int q) { return 1 + q + q * (q + 1) / 2; }
 
 void free_surrogate(cfust_surrogate* s) {
   void* ptrs[] = {s->params, s->grad, s->adm,   s->adv,  s->wb,    s->stdv,  s->wo,
-                  s->fb_total, s->X,  s->Ha,    s->Hb,   s->P,     s->inr,   s->list,
+                  s->fb_total, s->X,  s->P,     s->inr,   s->list,
                   s->count,  s->cf,   s->cok,   s->tX,   s->tH[0], s->tH[1], s->tH[2],
                   s->tdPb,   s->tdZb[0], s->tdZb[1], s->tT, s->tZ[0], s->tZ[1], s->tZ[2],
                   s->tdPlo,  s->tdZlo[0], s->tdZlo[1],
@@ -1601,14 +1604,13 @@ int cfust_surrogate_eval(cfust_surrogate* s, const double* feat, int64_t M, cons
   const int64_t chunk_rows = 2 * kSurrChunkPairs;
   int rc = ensure_infer(s, std::min<int64_t>(kSurrChunkPairs, (M + 1) / 2));
   if (rc) return rc;
-  bf16* const H[3] = {s->Ha, s->Hb, s->Ha};
   for (int64_t r0 = 0; r0 < M; r0 += chunk_rows) {
     const int64_t B = std::min(chunk_rows, M - r0);
     const int64_t Bp = round64(B);
     gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
         feat, nullptr, nullptr, r0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
         s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->X, nullptr);
-    mlp_forward(s, s->X, Bp, H, nullptr, s->P, st);
+    mlp_infer(s, s->X, Bp, s->P, st);
     unstd_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(
         s->P, B, s->T, s->q, s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, out + r0 * s->T);
   }

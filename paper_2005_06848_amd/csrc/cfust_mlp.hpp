@@ -197,6 +197,94 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const bf16* __restrict__
       }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: one 256-thread block takes 64 rows through all four
+// layers.  The activations of the block's rows stay in LDS (one 64 x 256 bf16
+// tile, overwritten layer by layer after a barrier); weights are read
+// k-contiguous from global memory (L2-resident, [out][in] layout).  Wave w
+// owns output columns [w N/4, (w+1) N/4) of every layer and all 64 rows, as
+// 4 x (N/64) tiles of v_mfma_f32_16x16x32_bf16 (gfx950): lane l supplies
+// A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16] and receives
+// D[4(l/16) + i][l%16], i = 0..3.  HBM traffic is the input rows (bf16) and
+// the fp32 outputs only.  rows must be a multiple of 64.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kFusedLd = kMlpHid + 8;  // LDS row pitch (528 bytes)
+
+template <int K, int N, bool LAST>
+__device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* __restrict__ W,
+                                            const float* __restrict__ b, float* __restrict__ P,
+                                            int64_t row0, int lane, int w) {
+  constexpr int CT = N / 64;  // 16-column tiles per wave
+  const int colbase = w * (N / 4);
+  const int r16 = lane & 15, kg = lane >> 4;
+  float4_t acc[4][CT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8_t a[4], bw[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+      bw[j] = *reinterpret_cast<const bf16x8_t*>(W + (size_t)(colbase + 16 * j + r16) * K + k0 +
+                                                 8 * kg);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8_t*>(Hs + (16 * i + r16) * kFusedLd + k0 + 8 * kg);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[j], acc[i][j], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int col = colbase + 16 * j + r16;
+      const float bias = b[col];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int row = 16 * i + 4 * kg + t;
+        const float z = acc[i][j][t] + bias;
+        if (LAST)
+          P[(size_t)(row0 + row) * kMlpPad + col] = z;
+        else
+          Hs[row * kFusedLd + col] = f2bf(z * sigmoid_f(z));
+      }
+    }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const bf16* __restrict__ X,
+                                                        const bf16* __restrict__ wb,
+                                                        const float* __restrict__ params,
+                                                        float* __restrict__ P) {
+  __shared__ __attribute__((aligned(16))) bf16 Hs[64 * kFusedLd];
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  {
+    const int r = tid >> 2, c = (tid & 3) * 16;
+    const uint4* src = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * kMlpPad + c);
+    uint4* dst = reinterpret_cast<uint4*>(Hs + r * kFusedLd + c);
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+  __syncthreads();
+  fused_layer<mlp_k(0), mlp_n(0), false>(Hs, wb + mlp_wb_off(0), params + mlp_b_off(0), nullptr,
+                                         row0, lane, w);
+  fused_layer<mlp_k(1), mlp_n(1), false>(Hs, wb + mlp_wb_off(1), params + mlp_b_off(1), nullptr,
+                                         row0, lane, w);
+  fused_layer<mlp_k(2), mlp_n(2), false>(Hs, wb + mlp_wb_off(2), params + mlp_b_off(2), nullptr,
+                                         row0, lane, w);
+  fused_layer<mlp_k(3), mlp_n(3), true>(Hs, wb + mlp_wb_off(3), params + mlp_b_off(3), P, row0,
+                                        lane, w);
+}
+
 // out[i] = sum_s part[s * n + i] (fixed order)
 __global__ void sum_slices_kernel(const float* __restrict__ part, int S, int64_t n,
                                   float* __restrict__ out) {

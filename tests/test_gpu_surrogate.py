@@ -342,3 +342,46 @@ def test_surrogate_estep_gain(dev):
     print(f"  FP64 GHK {t_ghk * 1e3:.1f} ms, network {t_net * 1e3:.1f} ms "
           f"({t_ghk / t_net:.0f}x), adaptation + network {t_ad * 1e3:.1f} ms ({t_ghk / t_ad:.1f}x)")
     assert t_net * 20 < t_ghk and t_ad * 2 < t_ghk
+
+
+def test_fused_inference_matches_reference(dev):
+    """The fused four-layer inference kernel (v_mfma_f32_16x16x32_bf16, LDS-
+    resident activations) against the FP64 reference forward with the same
+    bf16 rounding of weights, inputs and activations, on a random network:
+    the raw network outputs agree to 1e-5 of their scale in the median and
+    2e-3 at worst (a rounding of a hidden activation that lands on the other
+    side of a bf16 tie moves an output by about 2^-9 of one term)."""
+    from oracle import mlp_oracle as mo
+    from paper_2005_06848_amd import native
+    m = 1000  # not a multiple of 64: the padded tail is exercised
+    net, feat, targ, stdv = _net_and_batch(dev, 9, m)
+    theta, _ = net.get_state()
+    # make every output live: random last layer and biases too
+    rng = np.random.default_rng(4)
+    ow3, ob3 = mo.OFFSETS[3]
+    W3 = theta[ow3:ow3 + 64 * 256].reshape(64, 256)
+    W3[:28] = rng.standard_normal((28, 256)).astype(np.float32) * 0.1
+    theta[ob3:ob3 + 28] = rng.standard_normal(28).astype(np.float32) * 0.1
+    net.set_state(theta, stdv)
+    print(f"[gpu] fused inference M={m}", flush=True)
+    out = net.eval(T(feat, dev)).cpu().numpy()
+    F = feat.shape[1]
+    X = np.zeros((m, 64))
+    X[:, :F] = ((feat - stdv[:F].astype(np.float64)) / stdv[64:64 + F].astype(np.float64)
+                ).astype(np.float32)
+    P, _ = mo.forward(theta.astype(np.float64), X, bf16=True)
+    # network outputs back to label rows, as the library does
+    q, Tw = 6, 28
+    v = P[:, :Tw] * stdv[192:192 + Tw].astype(np.float64) + stdv[128:128 + Tw].astype(np.float64)
+    ref = np.array(v, copy=True)
+    iu = np.triu_indices(q)
+    for r in range(m):
+        U = np.zeros((q, q))
+        U[iu] = v[r, 1 + q:]
+        U[np.arange(q), np.arange(q)] = np.exp(np.diag(U))
+        m1 = v[r, 1:1 + q]
+        ref[r, 1 + q:] = (U.T @ U + np.outer(m1, m1))[iu]
+    scale = np.abs(ref).max(0)
+    err = np.abs(out - ref) / scale
+    print(f"  median {np.median(err):.2e} max {err.max():.2e}")
+    assert np.median(err) < 1e-5 and err.max() < 2e-3
