@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "liboracle_cfust.so")
 SOURCES = [os.path.join(_HERE, "cfust_oracle.c")]
 
 OK, EINVAL, ENOTPD, ENONFINITE, ENOMEM = 0, 1, 2, 3, 5
-NU_OSL, NU_FIXED = 0, 2
+NU_OSL, NU_EXACT_FD, NU_FIXED = 0, 1, 2
+FD_REL = 1e-3
 
 
 def build(force: bool = True) -> str:

@@ -400,6 +400,8 @@ typedef struct {
   double* C;      /* chol(R), R = D^{-1} Lambda D^{-1}, q*q */
   double* sA;     /* chi scale table, dof nu+p, N */
   double* sB;     /* chi scale table, dof nu+p+2, N */
+  double* sAp;    /* chi scale tables, dof (nu+p)(1 +- ORC_FD_REL) (exact e1 only) */
+  double* sAm;
   double kappa;   /* log pi + q log 2 + log of t_p's normaliser */
   double nu;
 } comp_t;
@@ -436,6 +438,8 @@ static void free_comps(comp_t* cp, int g) {
     free(cp[i].C);
     free(cp[i].sA);
     free(cp[i].sB);
+    free(cp[i].sAp);
+    free(cp[i].sAm);
   }
   free(cp);
 }
@@ -468,7 +472,12 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
       c->sA = (double*)malloc(sizeof(double) * n_qmc);
       c->sB = (double*)malloc(sizeof(double) * n_qmc);
     }
-    if (!c->L || !c->B || !c->D || !c->C || (tables && (!c->sA || !c->sB))) {
+    if (tables == 2) {
+      c->sAp = (double*)malloc(sizeof(double) * n_qmc);
+      c->sAm = (double*)malloc(sizeof(double) * n_qmc);
+    }
+    if (!c->L || !c->B || !c->D || !c->C || (tables && (!c->sA || !c->sB)) ||
+        (tables == 2 && (!c->sAp || !c->sAm))) {
       rc = ORC_ENOMEM;
       break;
     }
@@ -527,6 +536,10 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
       chi_scale_table(u, n_qmc, q, v + p, c->sA);
       chi_scale_table(u, n_qmc, q, v + p + 2.0, c->sB);
     }
+    if (tables == 2) {
+      chi_scale_table(u, n_qmc, q, (v + p) * (1.0 + ORC_FD_REL), c->sAp);
+      chi_scale_table(u, n_qmc, q, (v + p) * (1.0 - ORC_FD_REL), c->sAm);
+    }
   }
   free(Om);
   free(Lam);
@@ -555,8 +568,13 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
  *   e3 = E[W U | y]     = e2 E[X],  e4 = E[W U U^T | y] = e2 E[X X^T],
  *       X ~ t_q(c, ((nu+d)/(nu+p+2)) Lambda, nu+p+2) truncated to X > 0,
  *       X = c - Ds V with Ds = sqrt((nu+d)/(nu+p+2)) D and V ~ t_q(0,R,nu+p+2), V <= h_B;
- *   e1 = E[log W | y] in its one-step-late form
- *       e1 - e2 = psi(a) - log b - a/b   (exact when Delta = 0).
+ *   e1 = E[log W | y]: with J(a') = T_q(D^{-1} c sqrt(a'/b); R, 2a') (J(a) = T_A),
+ *       e1 = psi(a) - log b + d/da log J(a);
+ *     nu_mode ORC_NU_OSL uses the one-step-late form d/da log J ~ e2 - a/b,
+ *       e1 - e2 = psi(a) - log b - a/b   (exact when Delta = 0);
+ *     nu_mode ORC_NU_EXACT_FD takes the central difference with step
+ *       ORC_FD_REL a on the same points: integrals at dof (nu+p)(1 +- eps)
+ *       and bounds h_A sqrt(1 +- eps).
  * Partial sums (Algorithm 2), centred at the current mu_i:
  *   s1 = sum tau, s2 = sum tau e2, s3 = sum tau e2 r, s4 = sum tau e3,
  *   s5 = sum tau e4, s6 = sum tau r e3^T, s7 = sum tau e2 r r^T,
@@ -572,10 +590,10 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
   if (n_qmc < 1) return ORC_EINVAL;
   int rc = validate_model(n, p, q, g, pi, mu, Sigma, Delta, nu, y);
   if (rc) return rc;
-  (void)nu_mode;
+  const int exact = nu_mode == ORC_NU_EXACT_FD;
   offs_t o = stat_offsets(p, q);
   comp_t* cp = NULL;
-  rc = make_comps(p, q, g, pi, Sigma, Delta, nu, u, n_qmc, 1, &cp, &bad);
+  rc = make_comps(p, q, g, pi, Sigma, Delta, nu, u, n_qmc, exact ? 2 : 1, &cp, &bad);
   if (rc) {
     if (bad_component) *bad_component = bad;
     return rc;
@@ -621,6 +639,17 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
       E1m2[i] = orc_digamma(aa) - log(bb) - aa / bb;
       if (isfinite(logTA) && isfinite(logTB)) {
         double e2v = (aa / bb) * exp(logTB - logTA);
+        if (exact) {
+          double hP[64], hM[64], lP, lM;
+          for (int k = 0; k < q; ++k) {
+            hP[k] = hA[k] * sqrt(1.0 + ORC_FD_REL);
+            hM[k] = hA[k] * sqrt(1.0 - ORC_FD_REL);
+          }
+          ghk_core(q, hP, c->C, c->sAp, u, n_qmc, 0, logw, ehat, &lP, NULL, NULL);
+          ghk_core(q, hM, c->C, c->sAm, u, n_qmc, 0, logw, ehat, &lM, NULL, NULL);
+          if (isfinite(lP) && isfinite(lM))
+            E1m2[i] = orc_digamma(aa) - log(bb) + (lP - lM) / (2.0 * ORC_FD_REL * aa) - e2v;
+        }
         double sc = sqrt((v + d) / (v + p + 2.0));
         double mx[64];
         for (int k = 0; k < q; ++k) mx[k] = sc * c->D[k] * EV[k];

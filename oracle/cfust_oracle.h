@@ -24,6 +24,8 @@
 #define ORC_ENOMEM 5
 
 #define ORC_NU_OSL 0
+#define ORC_NU_EXACT_FD 1   /* e1 = E[log W | y] with a central difference in a */
+#define ORC_FD_REL 1e-3     /* relative step of that difference */
 #define ORC_NU_FIXED 2
 
 #ifdef __cplusplus
