@@ -57,6 +57,11 @@ extern "C" {
                                everything else stays float64 */
 
 #define CFUST_NU_OSL 0      /* nu update with the one-step-late E[log W | y] */
+#define CFUST_NU_EXACT_FD 1 /* nu update with the exact E[log W | y] = psi(a) - log b
+                               + d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a, the
+                               derivative a central difference (relative step 1e-3 in
+                               a, two more integrals per pair on the same points);
+                               not with a surrogate nor in cfust_em_fit_batched */
 #define CFUST_NU_FIXED 2    /* nu held fixed */
 
 typedef struct cfust_opts {

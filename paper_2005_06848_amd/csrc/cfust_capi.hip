@@ -63,6 +63,8 @@ struct Plan {
   int64_t per_block;
   size_t lds_bytes;
   // byte offsets inside the workspace
+  bool exact = false;  // exact E[log W | y] (nu_mode EXACT_FD)
+  size_t o_sAp, o_sAm;
   size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp,
       o_ll, o_stats, total;
 };
@@ -108,6 +110,10 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec) {
   pl.o_sB = off;
   off = align_up(off + (size_t)g * N * es);
   pl.o_rsB = off;
+  off = align_up(off + (size_t)g * N * es);
+  pl.o_sAp = off;
+  off = align_up(off + (size_t)g * N * es);
+  pl.o_sAm = off;
   off = align_up(off + (size_t)g * N * es);
   pl.o_pair = off;
   off = align_up(off + (size_t)(n > 0 ? n : 1) * g * pl.W * sizeof(double));
@@ -234,10 +240,12 @@ void launch_prepare(const Ws& ws, const Plan& pl, const double* pi, const double
     points_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, ws.st>>>(
         u, pl.N, q1, ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), ws.at<int>(pl.o_status));
   }
-  int64_t tot = (int64_t)2 * pl.g * pl.N;
+  const int tables = pl.exact ? 4 : 2;
+  int64_t tot = (int64_t)tables * pl.g * pl.N;
   chi_kernel<T><<<(unsigned)((tot + 127) / 128), 128, 0, ws.st>>>(
       ws.at<double>(pl.o_comp), pl.stride, CompLayout(pl.p, pl.q).nu, pl.p, pl.g, u, pl.N, q1,
-      ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB), ws.at<T>(pl.o_rsB), ws.at<int>(pl.o_status));
+      ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB), ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_sAp),
+      ws.at<T>(pl.o_sAm), tables, ws.at<int>(pl.o_status));
 }
 
 template <typename T, int Q, bool MOM>
@@ -248,10 +256,17 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   // FP64 with q <= 4 fits four waves per SIMD with little spilling (2.5%
   // faster at p=q=4); larger q spill heavily there and keep the default
   constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4 : 0;
-  pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
-      y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
-      ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N, ws.at<double>(pl.o_pair),
-      pl.W, ws.at<int>(pl.o_status));
+  if (MOM && pl.exact)
+    pair_kernel<T, Q, MOM, 0, true><<<blocks, 256, 0, ws.st>>>(
+        y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
+        ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N,
+        ws.at<double>(pl.o_pair), pl.W, ws.at<int>(pl.o_status), ws.at<T>(pl.o_sAp),
+        ws.at<T>(pl.o_sAm));
+  else
+    pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
+        y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
+        ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N,
+        ws.at<double>(pl.o_pair), pl.W, ws.at<int>(pl.o_status));
 }
 
 template <typename T, bool MOM>
@@ -457,13 +472,17 @@ void run_mstep(Ws& ws, const Plan& pl, int64_t n, const double* stats, const dou
 int check_surrogate(const cfust_opts* o, int q) {
   if (!o || !o->surrogate) return CFUST_OK;
   const cfust_surrogate* s = o->surrogate;
+  // the network has no derivative output for the exact E[log W | y]
+  if (o->nu_mode == CFUST_NU_EXACT_FD) return CFUST_EINVAL;
   return (s->q == q && s->have_std) ? CFUST_OK : CFUST_EINVAL;
 }
 
 int check_opts(const cfust_opts* o) {
   if (!o) return CFUST_OK;
   if (o->precision != CFUST_FP64 && o->precision != CFUST_FP32) return CFUST_EINVAL;
-  if (o->nu_mode != CFUST_NU_OSL && o->nu_mode != CFUST_NU_FIXED) return CFUST_EINVAL;
+  if (o->nu_mode != CFUST_NU_OSL && o->nu_mode != CFUST_NU_EXACT_FD &&
+      o->nu_mode != CFUST_NU_FIXED)
+    return CFUST_EINVAL;
   if (!(o->nu_lo > 0.0) || !(o->nu_hi >= o->nu_lo)) return CFUST_EINVAL;
   return CFUST_OK;
 }
@@ -515,6 +534,7 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
     return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
   Plan pl = make_plan(n, p, q, g, n_qmc, prec);
+  pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
   clear_status(ws, pl);
@@ -593,6 +613,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   if (!o) o = &def;
   if (o->max_iter < 0) return CFUST_EINVAL;
   Plan pl = make_plan(n, p, q, g, n_qmc, o->precision);
+  pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
   double* stats = ws.at<double>(pl.o_stats);
@@ -1057,7 +1078,7 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   cfust_opts def;
   cfust_default_opts(&def);
   if (!o) o = &def;
-  if (o->max_iter < 0) return CFUST_EINVAL;
+  if (o->max_iter < 0 || o->nu_mode == CFUST_NU_EXACT_FD) return CFUST_EINVAL;
   BPlan pl;
   if ((rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, o->precision, o->max_iter, &pl))) return rc;
   hipStream_t caller = (hipStream_t)o->stream;

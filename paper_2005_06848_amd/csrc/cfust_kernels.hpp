@@ -27,6 +27,10 @@ constexpr int kMaxP = 32;
 constexpr int kMaxQ = 8;
 constexpr int kMaxG = 16;
 
+// relative step in a = (nu+p)/2 of the central difference that gives the
+// exact E[log W | y] (derivative of log T_A with respect to a)
+constexpr double kFdRel = 1e-3;
+
 enum Status : int {
   kOk = 0,
   kEInval = 1,
@@ -229,25 +233,37 @@ __global__ void points_kernel(const double* __restrict__ u, int N, int q1, T* __
 // (integral B), with 1/s for integral B.
 // ---------------------------------------------------------------------------
 template <typename T>
+// chi scale tables per component: `tables` = 2 gives sA (dof nu+p) and sB,
+// rsB (dof nu+p+2); 4 adds sAp, sAm at dof (nu+p)(1 +- kFdRel) for the
+// exact E[log W | y]
 __global__ void chi_kernel(const double* __restrict__ comp, int comp_stride, int nu_off, int p,
                            int g, const double* __restrict__ u, int N, int q1,
                            T* __restrict__ sA, T* __restrict__ sB, T* __restrict__ rsB,
+                           T* __restrict__ sAp, T* __restrict__ sAm, int tables,
                            const int* __restrict__ status) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)2 * g * N) return;
+  if (t >= (int64_t)tables * g * N) return;
   if (status[0] != kOk) return;
   int which = (int)(t / ((int64_t)g * N));
   int rem = (int)(t - (int64_t)which * g * N);
   int i = rem / N;
   int k = rem - i * N;
   double v = comp[(size_t)i * comp_stride + nu_off];
-  double dof = v + p + (which ? 2.0 : 0.0);
+  double dof = v + p;
+  if (which == 1) dof += 2.0;
+  if (which == 2) dof *= 1.0 + kFdRel;
+  if (which == 3) dof *= 1.0 - kFdRel;
   double s = sqrt(chi2_quantile(u[(size_t)k * q1], dof) / dof);
+  const size_t o = (size_t)i * N + k;
   if (which == 0) {
-    sA[(size_t)i * N + k] = (T)s;
+    sA[o] = (T)s;
+  } else if (which == 1) {
+    sB[o] = (T)s;
+    rsB[o] = (T)(1.0 / s);
+  } else if (which == 2) {
+    sAp[o] = (T)s;
   } else {
-    sB[(size_t)i * N + k] = (T)s;
-    rsB[(size_t)i * N + k] = (T)(1.0 / s);
+    sAm[o] = (T)s;
   }
 }
 
@@ -427,14 +443,15 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
 //   log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[Q] | e4 (upper triangle)
 // Returns false if y_j is not finite.
 // ---------------------------------------------------------------------------
-template <typename T, int Q, bool MOM>
+template <typename T, int Q, bool MOM, bool EXACT = false>
 __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
                                           const double* __restrict__ mui,
                                           const double* __restrict__ cp,
                                           const T* __restrict__ sAi, const T* __restrict__ sBi,
                                           const T* __restrict__ rsBi, const T* __restrict__ uT,
                                           const T* __restrict__ ubT, int N, int lane,
-                                          double* lane_out) {
+                                          double* lane_out, const T* __restrict__ sApi = nullptr,
+                                          const T* __restrict__ sAmi = nullptr) {
   constexpr int NT = Q * (Q + 1) / 2;
   const CompLayout cl(p, Q);
   const double v = cp[cl.nu];
@@ -470,11 +487,13 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
   // scaled bounds: ub_m = s * ht_m - sum_{l<m} Ct_ml eps_l, with
   // ht_m = h_m / C_mm and Ct_ml = C_ml / C_mm
   T htA[Q], htB[Q], Ct[Q][Q];
+  double hAd[Q];
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     double cmm = cp[cl.C + m * Q + m];
     double hbase = c[m] * cp[cl.Dinv + m];
-    htA[m] = (T)(hbase * fa / cmm);
+    hAd[m] = hbase * fa / cmm;
+    htA[m] = (T)hAd[m];
     htB[m] = (T)(hbase * fb / cmm);
 #pragma unroll
     for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(cp[cl.C + m * Q + l] / cmm) : T(0);
@@ -485,6 +504,24 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
   double m1[Q], m2[Q][Q];
   ghk_integral<T, Q, false>(htA, Ct, cp + cl.C, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
   if (MOM) ghk_integral<T, Q, true>(htB, Ct, cp + cl.C, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+
+  // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a
+  // by a central difference over the same points ----
+  double dlogJ = 0.0;
+  bool fd_ok = false;
+  if (EXACT && MOM) {
+    T hp[Q], hm[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      hp[m] = (T)(hAd[m] * sqrt(1.0 + kFdRel));
+      hm[m] = (T)(hAd[m] * sqrt(1.0 - kFdRel));
+    }
+    double lp, lm;
+    ghk_integral<T, Q, false>(hp, Ct, cp + cl.C, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
+    ghk_integral<T, Q, false>(hm, Ct, cp + cl.C, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
+    fd_ok = isfinite(lp) && isfinite(lm);
+    dlogJ = (lp - lm) / (2.0 * kFdRel * 0.5 * (v + p));
+  }
 
   // ---- a7: pair assembly (wave-uniform values; lane t stores entry t) ----
   const double aa = 0.5 * (v + p);
@@ -501,7 +538,10 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
       mx[k] = Ds[k] * m1[k];
     }
     out = (lane == 1) ? e2 : out;
-    out = (lane == 2) ? (cp[cl.psi_a] - log(bb) - aa / bb) : out;
+    // e1 - e2: one-step-late psi(a) - log b - a/b, or with the exact derivative
+    const double e1m2 = (EXACT && ok && fd_ok) ? (cp[cl.psi_a] - log(bb) + dlogJ - e2)
+                                               : (cp[cl.psi_a] - log(bb) - aa / bb);
+    out = (lane == 2) ? e1m2 : out;
 #pragma unroll
     for (int k = 0; k < Q; ++k) out = (lane == 3 + k) ? (ok ? e2 * (c[k] - mx[k]) : 0.0) : out;
     int t = 3 + Q;
@@ -525,14 +565,16 @@ __host__ __device__ constexpr int record_width() {
 }
 
 // one wave per pair, four pairs per 256-thread block; OCC > 0 asks for at
-// least OCC resident waves per SIMD (the register budget follows)
-template <typename T, int Q, bool MOM, int OCC = 0>
+// least OCC resident waves per SIMD (the register budget follows); EXACT adds
+// the two integrals of the exact E[log W | y]
+template <typename T, int Q, bool MOM, int OCC = 0, bool EXACT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 void pair_kernel(
     const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
     const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
-    double* __restrict__ pairbuf, int W, int* status) {
+    double* __restrict__ pairbuf, int W, int* status, const T* __restrict__ sAp = nullptr,
+    const T* __restrict__ sAm = nullptr) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
@@ -542,9 +584,10 @@ void pair_kernel(
   const int i = (int)(pair - j * g);
   const CompLayout cl(p, Q);
   double out;
-  bool ok = pair_eval<T, Q, MOM>(y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride,
-                                 sA + (size_t)i * N, sB + (size_t)i * N, rsB + (size_t)i * N, uT,
-                                 ubT, N, lane, &out);
+  bool ok = pair_eval<T, Q, MOM, EXACT>(
+      y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
+      sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, &out,
+      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr);
   if (!ok) {
     if (lane == 0) set_status(status, kENonFinite, -1);
     return;

@@ -1,0 +1,118 @@
+"""Exact E[log W | y] (nu_mode EXACT_FD) on the GPU against the FP64 oracle.
+
+Bar (FP64): 1e-10 per quantity as in tests/parity.py, e1 included; EM
+traces and parameters to 1e-9.  The exact nu step makes the ECM monotone
+up to the central difference's error, which the last test checks."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def P(par, dev):
+    return {k: T(v, dev) for k, v in par.items() if k in ("pi", "mu", "Sigma", "Delta", "nu")}
+
+
+def gpu_estep(dev, y, par, u, **opt):
+    from paper_2005_06848_amd import native
+    print(f"[gpu] exact estep n={y.shape[0]} p={y.shape[1]} q={par['Delta'].shape[2]} "
+          f"g={len(par['pi'])} N={u.shape[0]} {opt}", flush=True)
+    g = native.cfust_estep(T(y, dev), P(par, dev), T(u, dev), nu_mode="exact", **opt)
+    out = {k: v.cpu().numpy() for k, v in g.items()}
+    out["loglik"] = float(out["loglik"][0])
+    return out
+
+
+@pytest.mark.parametrize("shape", [(1, None), (0, (90, 3, 2, 3, 300)), (0, (65, 2, 4, 2, 1000)),
+                                   (0, (33, 5, 1, 2, 129))])
+def test_exact_estep_parity(dev, orc, shape):
+    from paper_2005_06848_amd import inputs
+    import parity
+    if shape[0] == 1:
+        c = inputs.config(1)
+        y, par, u = c["y"], c["init"], c["u"]
+    else:
+        n, p, q, g, N = shape[1]
+        c = inputs.random_case(31 + n, n, p, q, g, N)
+        y, par, u = c["y"], c["params"], c["u"]
+    ref = orc.estep(y, par, u, nu_mode=orc.NU_EXACT_FD)
+    got = gpu_estep(dev, y, par, u)
+    err = parity.estep_errors(got, ref, y.shape[1], par["Delta"].shape[2])
+    bad = {k: v for k, v in err.items() if not v <= TOL}
+    assert not bad, err
+    # the exact and one-step-late e1 differ on this data (the test is not vacuous)
+    osl = orc.estep(y, par, u, nu_mode=orc.NU_OSL, want=("e1",))["e1"]
+    assert np.max(np.abs(osl - ref["e1"])) > 1e-6
+
+
+def test_exact_em_fit_matches_oracle(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.config(1)
+    ref = orc.em_fit(c["y"], c["init"], c["u"], max_iter=10, tol=0.0, nu_mode=orc.NU_EXACT_FD)
+    print("[gpu] exact em_fit config 1", flush=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(c["u"], dev), max_iter=10,
+                              tol=0.0, nu_mode="exact")
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-9)
+    err = parity.params_rel_err({k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")},
+                                ref)
+    assert max(err.values()) < 1e-9, err
+
+
+def test_exact_fp32_form(dev, orc):
+    """FP32 integrand: e1 through the difference of two FP32 integrals, to
+    1e-4 relative like the other moments."""
+    from paper_2005_06848_amd import inputs
+    import parity
+    c = inputs.random_case(41, 200, 4, 3, 2, 2048)
+    ref = orc.estep(c["y"], c["params"], c["u"], nu_mode=orc.NU_EXACT_FD)
+    got = gpu_estep(dev, c["y"], c["params"], c["u"], precision="fp32")
+    err = parity.estep_errors(got, ref, 4, 3)
+    assert err["e1"] < 1e-4 and err["stats"] < 1e-4 and err["loglik"] < 1e-7, err
+
+
+def test_exact_em_is_monotone(dev):
+    """With the exact nu step every CM step maximises its conditional
+    likelihood, so l^(t) does not decrease (up to the difference's error)."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(2, n=4000)
+    print("[gpu] exact em_fit monotone n=4000", flush=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(c["u"], dev), max_iter=40,
+                              tol=0.0, nu_mode="exact")
+    tr = np.array(fit["trace"])
+    steps = np.diff(tr)
+    print("  smallest step", steps.min(), "final", tr[-1])
+    assert np.all(steps > -1e-8 * np.abs(tr[1:]))
+
+
+def test_exact_rejected_with_surrogate(dev):
+    from paper_2005_06848_amd import inputs, native, surrogate
+    c = inputs.random_case(5, 50, 6, 6, 2, 64)
+    net = native.Surrogate.load(surrogate.DEFAULT_PATH)
+    with pytest.raises(native.CfustError):
+        native.cfust_estep(T(c["y"], dev), P(c["params"], dev), T(c["u"], dev), nu_mode="exact",
+                           surrogate=net)
