@@ -66,7 +66,7 @@ extern "C" {
 
 typedef struct cfust_opts {
   int precision;          /* CFUST_FP64 or CFUST_FP32 */
-  int nu_mode;            /* CFUST_NU_OSL or CFUST_NU_FIXED */
+  int nu_mode;            /* CFUST_NU_OSL, CFUST_NU_EXACT_FD or CFUST_NU_FIXED */
   int fix_delta_zero;     /* nonzero: Delta held at 0 (t-mixture special case) */
   int max_iter;           /* cfust_em_fit: maximum number of M-steps */
   double tol;             /* cfust_em_fit: Aitken tolerance on |l_inf - l| */
@@ -183,6 +183,26 @@ int cfust_em_fit_batched(const double* y, int p, int q, int n_problems, const in
                          const int* g, double* pi, double* mu, double* Sigma, double* Delta,
                          double* nu, const double* u, int n_qmc, const cfust_opts* opts,
                          double* loglik_trace, int* n_iter, int* status);
+
+/* Parallel initialisation (section 3.1, Algorithm 1, read with the largest
+ * l selected) followed by the EM fit: m starting values Psi^(0)_k (device,
+ * concatenated: pi0[m][g], mu0[m][g][p], Sigma0[m][g][p][p],
+ * Delta0[m][g][p][q], nu0[m][g], e.g. from m initial partitions) are
+ * evaluated together on the same data y[n][p] (through the batched kernels:
+ * l^(0) and `burn_in` EM iterations per start, exactly that many unless a
+ * start fails); the start with the largest l after its burn-in continues
+ * with cfust_em_fit (opts->max_iter, opts->tol) into pi, mu, Sigma, Delta, nu
+ * (device outputs [g]...).  The burn-in uses the one-step-late nu update when
+ * opts->nu_mode is CFUST_NU_EXACT_FD.  start_loglik (host [m], may be NULL):
+ * l of each start after its burn-in (NaN if the start failed); best (host):
+ * the selected start; loglik_trace, n_iter, bad_component as cfust_em_fit.
+ * Needs m copies of y in device memory. */
+int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q, int g, int m,
+                            const double* pi0, const double* mu0, const double* Sigma0,
+                            const double* Delta0, const double* nu0, const double* u, int n_qmc,
+                            int burn_in, const cfust_opts* opts, double* pi, double* mu,
+                            double* Sigma, double* Delta, double* nu, double* start_loglik,
+                            int* best, double* loglik_trace, int* n_iter, int* bad_component);
 
 /* Bytes of device workspace cfust_em_fit_batched needs. */
 int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_obs, const int* g,

@@ -1125,6 +1125,98 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   return rc;
 }
 
+extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q, int g, int m,
+                                       const double* pi0, const double* mu0, const double* Sigma0,
+                                       const double* Delta0, const double* nu0, const double* u,
+                                       int n_qmc, int burn_in, const cfust_opts* o, double* pi,
+                                       double* mu, double* Sigma, double* Delta, double* nu,
+                                       double* start_loglik, int* best, double* loglik_trace,
+                                       int* n_iter, int* bad_component) {
+  if (bad_component) *bad_component = -1;
+  int rc = check_dims(n, p, q, g, n_qmc);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (n < 1 || m < 1 || burn_in < 0 || !y || !pi0 || !mu0 || !Sigma0 || !Delta0 || !nu0 || !u ||
+      !pi || !mu || !Sigma || !Delta || !nu || !best || !loglik_trace || !n_iter)
+    return CFUST_EINVAL;
+  cfust_opts def;
+  cfust_default_opts(&def);
+  if (!o) o = &def;
+  hipStream_t st = (hipStream_t)o->stream;
+  const size_t ny = (size_t)n * p, sp = (size_t)g, smu = (size_t)g * p,
+               sS = (size_t)g * p * p, sD = (size_t)g * p * q;
+  // m copies of y and of the starting values (the batched fit updates in place)
+  double *yr = nullptr, *pr = nullptr, *mr = nullptr, *Sr = nullptr, *Dr = nullptr, *nr = nullptr;
+  bool ok = hipMallocAsync((void**)&yr, m * ny * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&pr, m * sp * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&mr, m * smu * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&Sr, m * sS * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&Dr, m * sD * sizeof(double), st) == hipSuccess &&
+            hipMallocAsync((void**)&nr, m * sp * sizeof(double), st) == hipSuccess;
+  std::vector<double> trace((size_t)m * (burn_in + 1));
+  std::vector<int> nit((size_t)m), stat((size_t)2 * m);
+  std::vector<int64_t> nobs((size_t)m, n);
+  std::vector<int> gs((size_t)m, g);
+  if (ok) {
+    for (int k = 0; k < m; ++k)
+      ok = ok && hipMemcpyAsync(yr + k * ny, y, ny * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+                     hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(pr, pi0, m * sp * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(mr, mu0, m * smu * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(Sr, Sigma0, m * sS * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(Dr, Delta0, m * sD * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(nr, nu0, m * sp * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  }
+  if (!ok) rc = CFUST_ENOMEM;
+  // the batched fit runs on a stream of its own: the copies must be done
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = CFUST_EHIP;
+  if (!rc) {
+    cfust_opts ob = *o;
+    ob.max_iter = burn_in;
+    ob.tol = 0.0;  // exactly burn_in iterations
+    if (ob.nu_mode == CFUST_NU_EXACT_FD) ob.nu_mode = CFUST_NU_OSL;
+    ob.surrogate = nullptr;
+    ob.workspace = nullptr;
+    ob.workspace_bytes = 0;
+    rc = cfust_em_fit_batched(yr, p, q, m, nobs.data(), gs.data(), pr, mr, Sr, Dr, nr, u, n_qmc,
+                              &ob, trace.data(), nit.data(), stat.data());
+  }
+  int sel = -1;
+  if (!rc) {
+    double bestl = -INFINITY;
+    for (int k = 0; k < m; ++k) {
+      const double l = stat[2 * k] == 0 ? trace[(size_t)k * (burn_in + 1) + nit[k]] : NAN;
+      if (start_loglik) start_loglik[k] = l;
+      if (std::isfinite(l) && (sel < 0 || l > bestl)) {
+        sel = k;
+        bestl = l;
+      }
+    }
+    if (sel < 0) rc = CFUST_ENONFINITE;
+  }
+  if (!rc) {
+    *best = sel;
+    ok = hipMemcpyAsync(pi, pr + sel * sp, sp * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess &&
+         hipMemcpyAsync(mu, mr + sel * smu, smu * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess &&
+         hipMemcpyAsync(Sigma, Sr + sel * sS, sS * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess &&
+         hipMemcpyAsync(Delta, Dr + sel * sD, sD * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess &&
+         hipMemcpyAsync(nu, nr + sel * sp, sp * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess;
+    if (!ok) rc = CFUST_EHIP;
+  }
+  for (double* ptr : {yr, pr, mr, Sr, Dr, nr})
+    if (ptr) (void)hipFreeAsync(ptr, st);
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = CFUST_EHIP;
+  if (rc) return rc;
+  return cfust_em_fit(y, n, p, q, g, pi, mu, Sigma, Delta, nu, u, n_qmc, o, loglik_trace, n_iter,
+                      bad_component);
+}
+
 extern "C" int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_obs,
                                             const int* g, int n_qmc, int precision, int max_iter,
                                             size_t* bytes) {

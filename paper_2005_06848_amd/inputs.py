@@ -225,6 +225,17 @@ def init_from_partition(y: np.ndarray, lab: np.ndarray, g: int, q: int, nu0: flo
     return dict(pi=pi, mu=mu, Sigma=Sigma, Delta=Delta, nu=nu)
 
 
+def multistart_inits(y: np.ndarray, g: int, q: int, m: int, seed: int = 7):
+    """m starting values Psi^(0) from m initial partitions (k-means++ with one
+    restart each, seeds seed, seed+1, ...), as the parallel initialisation of
+    section 3.1 takes them."""
+    out = []
+    for k in range(m):
+        rng = np.random.default_rng(seed + k)
+        out.append(init_from_partition(y, kmeans_pp(rng, y, g, n_init=1), g, q))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------

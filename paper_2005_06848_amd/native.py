@@ -97,6 +97,11 @@ def _lib():
         L.cfust_em_fit_batched.argtypes = [P, i, i, i, P, P, P, P, P, P, P, P, i,
                                            ctypes.POINTER(Opts), P, P, P]
         L.cfust_em_fit_batched.restype = i
+        L.cfust_em_fit_multistart.argtypes = [P, i64, i, i, i, i, P, P, P, P, P, P, i, i,
+                                              ctypes.POINTER(Opts), P, P, P, P, P, P,
+                                              ctypes.POINTER(i), P, ctypes.POINTER(i),
+                                              ctypes.POINTER(i)]
+        L.cfust_em_fit_multistart.restype = i
         L.cfust_batched_workspace_size.argtypes = [i, i, i, P, P, i, i, i, ctypes.POINTER(sz)]
         L.cfust_batched_workspace_size.restype = i
         L.cfust_batched_config.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
@@ -336,6 +341,41 @@ def cfust_em_fit_batched(y, n_obs, g, params0, u, max_iter=50, tol=1e-6, **opt):
     if rc:
         raise CfustError(rc, "cfust_em_fit_batched")
     return par, trace, n_iter, status
+
+
+def cfust_em_fit_multistart(y, starts, u, burn_in=0, max_iter=100, tol=1e-6, **opt):
+    """Algorithm 1 (largest l selected) then the EM fit.  starts: list of m
+    parameter dicts.  Returns the fitted parameters with trace, n_iter,
+    best (selected start) and start_loglik (l of each start after burn-in)."""
+    import numpy as np
+    y = _dev(y, "y")
+    u = _dev(u, "u")
+    m = len(starts)
+    cat = {k: torch.cat([_dev(s_[k], k).reshape(1, *s_[k].shape) for s_ in starts]).contiguous()
+           for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    g, p = starts[0]["mu"].shape
+    q = starts[0]["Delta"].shape[2]
+    n = y.shape[0]
+    out = {k: torch.empty_like(v[0]) for k, v in cat.items()}
+    ll0 = np.zeros(m)
+    best = ctypes.c_int(-1)
+    trace = (ctypes.c_double * (max_iter + 1))()
+    n_iter = ctypes.c_int(0)
+    bad = ctypes.c_int(-1)
+    o = make_opts(max_iter=max_iter, tol=tol, **opt)
+    rc = _lib().cfust_em_fit_multistart(
+        _ptr(y), n, p, q, g, m, _ptr(cat["pi"]), _ptr(cat["mu"]), _ptr(cat["Sigma"]),
+        _ptr(cat["Delta"]), _ptr(cat["nu"]), _ptr(u), u.shape[0], int(burn_in), ctypes.byref(o),
+        _ptr(out["pi"]), _ptr(out["mu"]), _ptr(out["Sigma"]), _ptr(out["Delta"]), _ptr(out["nu"]),
+        ll0.ctypes.data, ctypes.byref(best), trace, ctypes.byref(n_iter), ctypes.byref(bad))
+    if rc:
+        raise CfustError(rc, "cfust_em_fit_multistart", bad.value)
+    k = n_iter.value
+    out["trace"] = [trace[t] for t in range(k + 1)]
+    out["n_iter"] = k
+    out["best"] = best.value
+    out["start_loglik"] = ll0
+    return out
 
 
 def cfust_batched_config():

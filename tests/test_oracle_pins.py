@@ -334,3 +334,20 @@ def test_resume_equals_straight_run(orc):
     for k in ("pi", "mu", "Sigma", "Delta", "nu"):
         np.testing.assert_array_equal(b[k], full[k])
     np.testing.assert_array_equal(b["trace"], full["trace"][2:])
+
+
+def test_multistart_picks_the_largest_loglik():
+    """Algorithm 1 composed in the oracle: the kept start is the one whose
+    l after the burn-in is largest, and the fit from it is the plain EM fit
+    from that start's burn-in result."""
+    import oracle as orc
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(1)
+    starts = inputs.multistart_inits(c["y"], c["g"], c["q"], 3, seed=11)
+    fit = orc.em_fit_multistart(c["y"], starts, c["u"], burn_in=1, max_iter=3, tol=0.0)
+    ll = [orc.em_fit(c["y"], s, c["u"], max_iter=1, tol=0.0)["trace"][-1] for s in starts]
+    assert fit["best"] == int(np.argmax(ll))
+    np.testing.assert_array_equal(fit["start_loglik"], ll)
+    run = orc.em_fit(c["y"], starts[fit["best"]], c["u"], max_iter=1, tol=0.0)
+    ref = orc.em_fit(c["y"], run, c["u"], max_iter=3, tol=0.0)
+    np.testing.assert_array_equal(fit["trace"], ref["trace"])
