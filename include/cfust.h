@@ -184,6 +184,16 @@ int cfust_em_fit_batched(const double* y, int p, int q, int n_problems, const in
                          double* nu, const double* u, int n_qmc, const cfust_opts* opts,
                          double* loglik_trace, int* n_iter, int* status);
 
+/* Randomised-QMC error bar of the log-likelihood eq. (3): l evaluated with
+ * each of K point sets (u: device [K][n_qmc][q+1], e.g. one base sequence
+ * under K independent random shifts); ll (host [K]) receives every value,
+ * *mean and *std_err (host) their mean and standard error sd / sqrt(K)
+ * (0 when K = 1). */
+int cfust_loglik_rqmc(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                      const double* mu, const double* Sigma, const double* Delta, const double* nu,
+                      const double* u, int n_qmc, int K, const cfust_opts* opts, double* ll,
+                      double* mean, double* std_err);
+
 /* Parallel initialisation (section 3.1, Algorithm 1, read with the largest
  * l selected) followed by the EM fit: m starting values Psi^(0)_k (device,
  * concatenated: pi0[m][g], mu0[m][g][p], Sigma0[m][g][p][p],

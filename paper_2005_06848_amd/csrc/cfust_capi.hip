@@ -1125,6 +1125,37 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   return rc;
 }
 
+extern "C" int cfust_loglik_rqmc(const double* y, int64_t n, int p, int q, int g,
+                                 const double* pi, const double* mu, const double* Sigma,
+                                 const double* Delta, const double* nu, const double* u,
+                                 int n_qmc, int K, const cfust_opts* o, double* ll, double* mean,
+                                 double* std_err) {
+  if (K < 1 || !ll || !mean || !std_err || !u || n_qmc < 1) return CFUST_EINVAL;
+  hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
+  double* dev_ll = nullptr;
+  if (hipMallocAsync((void**)&dev_ll, sizeof(double), st) != hipSuccess) return CFUST_ENOMEM;
+  int rc = CFUST_OK;
+  for (int k = 0; k < K && !rc; ++k) {
+    rc = cfust_loglik(y, n, p, q, g, pi, mu, Sigma, Delta, nu,
+                      u + (size_t)k * n_qmc * (q + 1), n_qmc, o, dev_ll, nullptr);
+    if (!rc && (hipMemcpyAsync(&ll[k], dev_ll, sizeof(double), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess))
+      rc = CFUST_EHIP;
+  }
+  (void)hipFreeAsync(dev_ll, st);
+  (void)hipStreamSynchronize(st);
+  if (rc) return rc;
+  double m = 0.0;
+  for (int k = 0; k < K; ++k) m += ll[k];
+  m /= K;
+  double v = 0.0;
+  for (int k = 0; k < K; ++k) v += (ll[k] - m) * (ll[k] - m);
+  *mean = m;
+  *std_err = K > 1 ? sqrt(v / (K - 1) / K) : 0.0;
+  return CFUST_OK;
+}
+
 extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q, int g, int m,
                                        const double* pi0, const double* mu0, const double* Sigma0,
                                        const double* Delta0, const double* nu0, const double* u,

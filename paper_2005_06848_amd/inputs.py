@@ -58,6 +58,42 @@ def wishart_sigma(rng: np.random.Generator, p: int) -> np.ndarray:
     return x.T @ x / (p + 2)
 
 
+def korobov_generator(n: int, d: int) -> np.ndarray:
+    """Generating vector z = (1, a, a^2, ...) mod n of a rank-1 Korobov lattice
+    rule, a chosen among the odd a < n/2 by the P_2 criterion of the rule
+    (the worst-case error in the Korobov space of smoothness 2):
+        P_2 = -1 + (1/n) sum_k prod_j (1 + 2 pi^2 B_2({k z_j / n})),
+    B_2(x) = x^2 - x + 1/6."""
+    k = np.arange(n)
+    best, best_a = np.inf, 1
+    for a in range(1, n // 2, 2):
+        z = np.array([pow(a, j, n) for j in range(d)])
+        x = (np.outer(k, z) % n) / n
+        b2 = x * x - x + 1.0 / 6.0
+        p2 = -1.0 + np.mean(np.prod(1.0 + 2.0 * np.pi ** 2 * b2, axis=1))
+        if p2 < best:
+            best, best_a = p2, a
+    return np.array([pow(best_a, j, n) for j in range(d)])
+
+
+def lattice_points(n_qmc: int, q: int, seed: int = QMC_SHIFT_SEED, z=None,
+                   tent: bool = True) -> np.ndarray:
+    """u[n_qmc][q+1] from a randomly shifted rank-1 lattice rule, with the
+    tent (baker's) transform x -> 1 - |2x - 1| unless tent is False, kept
+    inside (0, 1)."""
+    d = q + 1
+    if z is None:
+        z = korobov_generator(n_qmc, d)
+    rng = np.random.default_rng(seed)
+    shift = rng.random(d)
+    x = (np.outer(np.arange(n_qmc), z) % n_qmc) / n_qmc + shift[None, :]
+    x -= np.floor(x)
+    if tent:
+        x = 1.0 - np.abs(2.0 * x - 1.0)
+    eps = 2.0 ** -53
+    return np.ascontiguousarray(np.clip(x, eps, 1.0 - eps))
+
+
 def sample_cfust(rng: np.random.Generator, n: int, pi, mu, Sigma, Delta, nu):
     """Draw n observations and their labels from the CFUST mixture."""
     pi = np.asarray(pi, dtype=np.float64)

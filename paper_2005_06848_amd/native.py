@@ -97,6 +97,10 @@ def _lib():
         L.cfust_em_fit_batched.argtypes = [P, i, i, i, P, P, P, P, P, P, P, P, i,
                                            ctypes.POINTER(Opts), P, P, P]
         L.cfust_em_fit_batched.restype = i
+        L.cfust_loglik_rqmc.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i,
+                                        ctypes.POINTER(Opts), P, ctypes.POINTER(d),
+                                        ctypes.POINTER(d)]
+        L.cfust_loglik_rqmc.restype = i
         L.cfust_em_fit_multistart.argtypes = [P, i64, i, i, i, i, P, P, P, P, P, P, i, i,
                                               ctypes.POINTER(Opts), P, P, P, P, P, P,
                                               ctypes.POINTER(i), P, ctypes.POINTER(i),
@@ -341,6 +345,24 @@ def cfust_em_fit_batched(y, n_obs, g, params0, u, max_iter=50, tol=1e-6, **opt):
     if rc:
         raise CfustError(rc, "cfust_em_fit_batched")
     return par, trace, n_iter, status
+
+
+def cfust_loglik_rqmc(y, params, us, **opt):
+    """l under each of K point sets us [K][N][q+1]: (values, mean, std_err)."""
+    import numpy as np
+    y = _dev(y, "y")
+    us = _dev(us, "us")
+    (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
+    K, N = us.shape[0], us.shape[1]
+    ll = np.zeros(K)
+    mean, se = ctypes.c_double(0), ctypes.c_double(0)
+    o = make_opts(**opt)
+    rc = _lib().cfust_loglik_rqmc(_ptr(y), y.shape[0], p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma),
+                                  _ptr(Delta), _ptr(nu), _ptr(us), N, K, ctypes.byref(o),
+                                  ll.ctypes.data, ctypes.byref(mean), ctypes.byref(se))
+    if rc:
+        raise CfustError(rc, "cfust_loglik_rqmc")
+    return ll, mean.value, se.value
 
 
 def cfust_em_fit_multistart(y, starts, u, burn_in=0, max_iter=100, tol=1e-6, **opt):

@@ -44,3 +44,22 @@ def test_lkj_marginal_is_beta():
         rs.append(R[2, 5])
     ks = stats.kstest((np.array(rs) + 1) / 2, stats.beta(4, 4).cdf)
     assert ks.pvalue > 1e-3
+
+
+def test_lattice_rule_structure():
+    """A rank-1 lattice rule with generator z integrates exp(2 pi i h.x) to
+    zero unless h.z = 0 mod n: every one-dimensional projection is a shifted
+    full grid, and low-order Fourier modes integrate to zero."""
+    n, q = 1024, 3
+    z = inputs.korobov_generator(n, q + 1)
+    assert z[0] == 1 and np.all(z % 2 == 1)
+    x = inputs.lattice_points(n, q, seed=5, z=z, tent=False)
+    for j in range(q + 1):
+        grid = np.sort(np.round((x[:, j] - x[0, j]) * n) % n)
+        np.testing.assert_array_equal(grid, np.arange(n))
+    for h in ([1, 0, 0, 0], [0, 2, 0, 0], [1, 1, 0, 0], [0, 1, -1, 1], [3, 0, 0, -2]):
+        h = np.array(h)
+        assert (h @ z) % n != 0
+        assert abs(np.mean(np.exp(2j * np.pi * (x @ h)))) < 1e-12
+    u = inputs.lattice_points(n, q, seed=5, z=z)
+    assert np.all(u > 0) and np.all(u < 1)
