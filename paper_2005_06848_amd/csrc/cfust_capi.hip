@@ -35,6 +35,8 @@ struct cfust_surrogate {
   bool have_std = false;
   int64_t adam_t = 0;
   int em_switch = -1;                      // first GHK E-step of the last cfust_em_fit
+  hipStream_t own = nullptr;               // training stream (capturable)
+  int64_t* dstep = nullptr;                // device step counter of a training run
   unsigned long long* fb_total = nullptr;  // device: fallback pairs of the last E-step
   // inference buffers (pairs per chunk)
   int64_t cap_pairs = 0;
@@ -1398,6 +1400,8 @@ void free_surrogate(cfust_surrogate* s) {
                   s->tP,     s->tdP,  s->tdZ[0], s->tdZ[1], s->tpart, s->tbpart, s->tloss};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (s->dstep) (void)hipFree(s->dstep);
+  if (s->own) (void)hipStreamDestroy(s->own);
   delete s;
 }
 
@@ -1454,14 +1458,19 @@ void weight_grad(cfust_surrogate* s, const bf16* dZb, const bf16* dZlo, int n_ou
 }
 
 // one minibatch already gathered into tX / tT (Bp rows, B valid): forward,
-// loss (added to lacc[slot]) and gradient into s->grad
+// loss (added to lacc[slot], or lacc[*dstep / per_epoch] when dstep is given)
+// and gradient into s->grad
 void forward_backward(cfust_surrogate* s, int64_t B, int64_t Bp, float wsum, double* lacc,
-                      int slot, hipStream_t st) {
+                      int slot, hipStream_t st, const int64_t* dstep = nullptr,
+                      int64_t per_epoch = 1) {
   mlp_forward(s, s->tX, Bp, s->tH, s->tZ, s->tP, st);
   const unsigned nlb = (unsigned)(Bp * kMlpPad / 256);
   mse_grad_kernel<<<nlb, 256, 0, st>>>(s->tP, s->tT, Bp, B, s->T, s->wo, wsum, s->tdP, s->tdPb,
                                        s->tdPlo, s->tloss);
-  accumulate_kernel<<<1, 256, 0, st>>>(s->tloss, (int)nlb, lacc, slot);
+  if (dstep)
+    accumulate_step_kernel<<<1, 256, 0, st>>>(s->tloss, (int)nlb, lacc, dstep, per_epoch);
+  else
+    accumulate_kernel<<<1, 256, 0, st>>>(s->tloss, (int)nlb, lacc, slot);
   // layer 3 (linear output)
   weight_grad(s, s->tdPb, s->tdPlo, kMlpPad, s->tH[2], kMlpHid, Bp, s->grad + mlp_w_off(3), st);
   colsum(s, s->tdP, Bp, kMlpPad, s->grad + mlp_b_off(3), st);
@@ -1584,7 +1593,9 @@ int cfust_surrogate_create(int q, const double* range, unsigned long long seed,
             dev_alloc(&s->adm, kMlpParams) && dev_alloc(&s->adv, kMlpParams) &&
             dev_alloc(&s->wb, kMlpWeightsBf) && dev_alloc(&s->stdv, CFUST_SURR_STD) &&
             dev_alloc(&s->wo, kMlpPad) && dev_alloc(&s->fb_total, 1) &&
-            dev_alloc(&s->count, 1) && dev_alloc(&s->cf, kMaxG * 32) && dev_alloc(&s->cok, kMaxG);
+            dev_alloc(&s->count, 1) && dev_alloc(&s->cf, kMaxG * 32) && dev_alloc(&s->cok, kMaxG) &&
+            dev_alloc(&s->dstep, 1) &&
+            hipStreamCreateWithFlags(&s->own, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     free_surrogate(s);
     return CFUST_ENOMEM;
@@ -1654,41 +1665,72 @@ int cfust_surrogate_train(cfust_surrogate* s, const double* feat, const double* 
     return CFUST_ENOMEM;
   }
   (void)hipMemsetAsync(lacc, 0, (epochs + 1) * sizeof(double), st);
+  // The run goes on the handle's own stream (capturable): every step is the
+  // same launch sequence reading its minibatch offset, loss slot and Adam
+  // step from the device counter s->dstep; with opts->graph (default) it is
+  // captured once and replayed.  Each epoch takes floor(M / B) minibatches of
+  // B = min(batch, M) rows of a fresh shuffle.
+  if (hipStreamSynchronize(st) != hipSuccess) rc = CFUST_EHIP;
+  hipStream_t ow = s->own;
+  const int64_t B = std::min<int64_t>(batch, M);
+  const int64_t Bp = round64(B);
+  const int64_t steps = M / B;
+  const int64_t total = steps * (int64_t)epochs;
+  TrainStep ts{s->dstep, steps, total, B, Bp, s->adam_t, lr0, lr1};
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  auto one_step = [&]() {
+    gather_step_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, ow>>>(
+        feat, nt, idx, ts, s->F, s->T, s->stdv, s->stdv + kMlpPad, s->stdv + 2 * kMlpPad,
+        s->stdv + 3 * kMlpPad, s->tX, s->tT);
+    forward_backward(s, B, Bp, wsum, lacc, 0, ow, s->dstep, steps);
+    adam_step_kernel<<<(unsigned)((kMlpParams + 255) / 256), 256, 0, ow>>>(
+        s->params, s->grad, s->adm, s->adv, kMlpParams, ts, b1, b2, eps);
+    weights_to_bf16_kernel<<<(unsigned)((kMlpWeightsBf + 255) / 256), 256, 0, ow>>>(s->params,
+                                                                                    s->wb);
+    step_inc_kernel<<<1, 64, 0, ow>>>(s->dstep);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const bool use_graph = !o || o->graph;
+  if (!rc && hipMemsetAsync(s->dstep, 0, sizeof(int64_t), ow) != hipSuccess) rc = CFUST_EHIP;
+  if (!rc && use_graph && total > 0) {
+    if (hipStreamBeginCapture(ow, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = CFUST_EHIP;
+    } else {
+      one_step();
+      if (hipStreamEndCapture(ow, &graph) != hipSuccess ||
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = CFUST_EHIP;
+    }
+  }
   std::vector<int64_t> perm((size_t)M);
   Rng rng{seed};
-  const int64_t steps = (M + batch - 1) / batch;
-  const int64_t total = steps * (int64_t)epochs;
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  int64_t step = 0;
   for (int ep = 0; ep < epochs && !rc; ++ep) {
     for (int64_t k = 0; k < M; ++k) perm[k] = k;
     for (int64_t k = M - 1; k > 0; --k) std::swap(perm[k], perm[rng.next() % (uint64_t)(k + 1)]);
-    if (hipMemcpyAsync(idx, perm.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+    if (hipMemcpyAsync(idx, perm.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, ow) !=
         hipSuccess) {
       rc = CFUST_EHIP;
       break;
     }
-    for (int64_t b0 = 0; b0 < M; b0 += batch, ++step) {
-      const int64_t B = std::min<int64_t>(batch, M - b0);
-      const int64_t Bp = round64(B);
-      gather_rows_kernel<<<(unsigned)(Bp * kMlpPad / 256), 256, 0, st>>>(
-          feat, nt, idx, b0, B, Bp, s->F, s->T, s->stdv, s->stdv + kMlpPad,
-          s->stdv + 2 * kMlpPad, s->stdv + 3 * kMlpPad, s->tX, s->tT);
-      forward_backward(s, B, Bp, wsum, lacc, ep, st);
-      ++s->adam_t;
-      const double lr =
-          lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(3.141592653589793 * (double)step / (double)total));
-      const float bc1 = (float)(1.0 - pow((double)b1, (double)s->adam_t));
-      const float bc2 = (float)(1.0 - pow((double)b2, (double)s->adam_t));
-      adam_kernel<<<(unsigned)((kMlpParams + 255) / 256), 256, 0, st>>>(
-          s->params, s->grad, s->adm, s->adv, kMlpParams, (float)lr, b1, b2, eps, bc1, bc2);
-      weights_to_bf16_kernel<<<(unsigned)((kMlpWeightsBf + 255) / 256), 256, 0, st>>>(s->params,
-                                                                                      s->wb);
+    for (int64_t k = 0; k < steps; ++k) {
+      if (exec) {
+        if (hipGraphLaunch(exec, ow) != hipSuccess) {
+          rc = CFUST_EHIP;
+          break;
+        }
+      } else {
+        one_step();
+      }
     }
-    if ((rc = launch_check())) break;
+    if (!rc) rc = launch_check();
     // the host permutation is rewritten next epoch: wait for the upload
-    if (hipStreamSynchronize(st) != hipSuccess) rc = CFUST_EHIP;
+    if (hipStreamSynchronize(ow) != hipSuccess && !rc) rc = CFUST_EHIP;
   }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (hipStreamSynchronize(ow) != hipSuccess && !rc) rc = CFUST_EHIP;
+  if (!rc) s->adam_t += total;
   if (!rc && loss_trace && epochs > 0) {
     std::vector<double> h((size_t)epochs);
     if (hipMemcpyAsync(h.data(), lacc, epochs * sizeof(double), hipMemcpyDeviceToHost, st) !=

@@ -356,6 +356,79 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__
   if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
 }
 
+// Per-step scalars of a training run come from a device step counter, so
+// that one step is the same launch sequence every time (it is captured once
+// in a hipGraph and replayed): minibatch k of the epoch is rows
+// [k B, (k+1) B) of the shuffled index, the loss goes to slot epoch, and
+// Adam's learning rate follows a cosine from lr0 to lr1 over `total` steps.
+struct TrainStep {
+  const int64_t* step;  // steps done in this run (device)
+  int64_t per_epoch, total, B, Bp, t0;  // t0: Adam steps before this run
+  double lr0, lr1;
+};
+
+__global__ void gather_step_kernel(const double* __restrict__ feat, const double* __restrict__ targ,
+                                   const int64_t* __restrict__ idx, TrainStep ts, int IN, int OUT,
+                                   const float* __restrict__ mx, const float* __restrict__ sx,
+                                   const float* __restrict__ my, const float* __restrict__ sy,
+                                   bf16* __restrict__ X, float* __restrict__ T) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ts.Bp * kMlpPad) return;
+  const int64_t base = (ts.step[0] % ts.per_epoch) * ts.B;
+  const int64_t r = t / kMlpPad;
+  const int c = (int)(t % kMlpPad);
+  const int64_t s = r < ts.B ? idx[base + r] : 0;
+  float xv = 0.f;
+  if (r < ts.B && c < IN) xv = (float)((feat[s * IN + c] - (double)mx[c]) / (double)sx[c]);
+  X[t] = f2bf(xv);
+  if (c < OUT) {
+    float tv = 0.f;
+    if (r < ts.B) tv = (float)((targ[s * OUT + c] - (double)my[c]) / (double)sy[c]);
+    T[r * OUT + c] = tv;
+  }
+}
+
+__global__ void adam_step_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                 float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                 TrainStep ts, float b1, float b2, float eps) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t k = ts.step[0];
+  const double tt = (double)(ts.t0 + k + 1);
+  const float lr = (float)(ts.lr1 + 0.5 * (ts.lr0 - ts.lr1) *
+                                        (1.0 + cos(3.141592653589793 * (double)k / (double)ts.total)));
+  const float bc1 = (float)(1.0 - pow((double)b1, tt));
+  const float bc2 = (float)(1.0 - pow((double)b2, tt));
+  const float gt = g[t];
+  const float mt = b1 * m[t] + (1.f - b1) * gt;
+  const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+  m[t] = mt;
+  v[t] = vt;
+  w[t] -= lr * (mt / bc1) / (sqrtf(vt / bc2) + eps);
+}
+
+__global__ void step_inc_kernel(int64_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
+}
+
+// acc[slot] += sum of part[0..n) (one block of 256 threads, fixed order);
+// with step given the slot is step[0] / per_epoch
+__global__ __launch_bounds__(256) void accumulate_step_kernel(const float* __restrict__ part, int n,
+                                                              double* __restrict__ acc,
+                                                              const int64_t* __restrict__ step,
+                                                              int64_t per_epoch) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[step[0] / per_epoch] += red[0];
+}
+
 // acc[slot] += sum of part[0..n) (one block of 256 threads, fixed order)
 __global__ __launch_bounds__(256) void accumulate_kernel(const float* __restrict__ part, int n,
                                                          double* __restrict__ acc, int slot) {
