@@ -52,15 +52,19 @@ def lib():
         L.orc_ghk.restype = i
         L.orc_ghk.argtypes = [i, P, P, d, P, i, i, P, P, P]
         L.orc_estep.restype = i
-        L.orc_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i,
+        L.orc_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i, i,
                                 P, P, P, P, P, P, P, P, P]
         L.orc_mstep.restype = i
         L.orc_mstep.argtypes = [P, i64, i, i, i, P, P, P, i, i, d, d, P, P, P, P, P, P]
         L.orc_loglik.restype = i
-        L.orc_loglik.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, P, P]
+        L.orc_loglik.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i, P, P]
         L.orc_em_fit.restype = i
-        L.orc_em_fit.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i, i, i, d, d, d,
+        L.orc_em_fit.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i, i, i, i, d, d, d,
                                  P, P, P]
+        L.orc_genz_order.restype = i
+        L.orc_genz_order.argtypes = [i, P, P, P, P]
+        L.orc_ghk_ordered.restype = i
+        L.orc_ghk_ordered.argtypes = [i, P, P, d, P, i, i, P, P, P, P]
         _lib = L
     return _lib
 
@@ -136,12 +140,44 @@ def ghk(h, C, dof, u, moments=True):
     return float(logT[0]), EV, EVV
 
 
+def genz_order(h, R):
+    """Genz-Bretz variable order of P(Z <= h), Z ~ N(0, R): (perm, chol(R[perm][perm]))."""
+    h = _f64(h)
+    R = _f64(R)
+    q = h.size
+    perm = np.zeros(q, dtype=np.int32)
+    Cp = np.zeros((q, q))
+    rc = lib().orc_genz_order(q, _ptr(h), _ptr(R), perm.ctypes.data, _ptr(Cp))
+    if rc:
+        raise OracleError(rc)
+    return perm, Cp
+
+
+def ghk_ordered(h, R, dof, u, moments=True):
+    """GHK with the Genz-Bretz order: (logT, EV, EVV, perm), moments in the
+    original labelling; R is a correlation matrix."""
+    h = _f64(h)
+    R = _f64(R)
+    u = _f64(u)
+    q = h.size
+    logT = np.zeros(1)
+    EV = np.zeros(q)
+    EVV = np.zeros((q, q))
+    perm = np.zeros(q, dtype=np.int32)
+    rc = lib().orc_ghk_ordered(q, _ptr(h), _ptr(R), float(dof), _ptr(u), u.shape[0],
+                               int(moments), _ptr(logT), _ptr(EV), _ptr(EVV), perm.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return float(logT[0]), EV, EVV, perm
+
+
 def _model(params):
     return (_f64(params["pi"]), _f64(params["mu"]), _f64(params["Sigma"]),
             _f64(params["Delta"]), _f64(params["nu"]))
 
 
-def estep(y, params, u, nu_mode=NU_OSL, want=("tau", "logf", "e1", "e2", "e3", "e4")):
+def estep(y, params, u, nu_mode=NU_OSL, want=("tau", "logf", "e1", "e2", "e3", "e4"),
+          reorder=False):
     y = _f64(y)
     u = _f64(u)
     n, p = y.shape
@@ -155,7 +191,7 @@ def estep(y, params, u, nu_mode=NU_OSL, want=("tau", "logf", "e1", "e2", "e3", "
     ll = np.zeros(1)
     bad = ctypes.c_int(-1)
     rc = lib().orc_estep(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
-                         _ptr(nu), _ptr(u), u.shape[0], nu_mode,
+                         _ptr(nu), _ptr(u), u.shape[0], nu_mode, int(reorder),
                          _ptr(out["tau"]), _ptr(out["logf"]), _ptr(out["e1"]), _ptr(out["e2"]),
                          _ptr(out["e3"]), _ptr(out["e4"]), _ptr(stats), _ptr(ll),
                          ctypes.addressof(bad))
@@ -186,7 +222,7 @@ def mstep(stats, n, params_old, nu_mode=NU_OSL, fix_delta_zero=False, nu_lo=1.0,
     return dict(pi=pi, mu=mu, Sigma=Sigma, Delta=Delta, nu=nu)
 
 
-def loglik(y, params, u, want_logf=False):
+def loglik(y, params, u, want_logf=False, reorder=False):
     y = _f64(y)
     u = _f64(u)
     n, p = y.shape
@@ -195,14 +231,14 @@ def loglik(y, params, u, want_logf=False):
     ll = np.zeros(1)
     lf = np.zeros((n, g)) if want_logf else None
     rc = lib().orc_loglik(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
-                          _ptr(nu), _ptr(u), u.shape[0], _ptr(ll), _ptr(lf))
+                          _ptr(nu), _ptr(u), u.shape[0], int(reorder), _ptr(ll), _ptr(lf))
     if rc:
         raise OracleError(rc)
     return (float(ll[0]), lf) if want_logf else float(ll[0])
 
 
 def em_fit(y, params0, u, max_iter=10, tol=1e-6, nu_mode=NU_OSL, fix_delta_zero=False,
-           nu_lo=1.0, nu_hi=200.0):
+           nu_lo=1.0, nu_hi=200.0, reorder=False):
     y = _f64(y)
     u = _f64(u)
     n, p = y.shape
@@ -212,7 +248,8 @@ def em_fit(y, params0, u, max_iter=10, tol=1e-6, nu_mode=NU_OSL, fix_delta_zero=
     n_iter = ctypes.c_int(0)
     bad = ctypes.c_int(-1)
     rc = lib().orc_em_fit(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
-                          _ptr(nu), _ptr(u), u.shape[0], nu_mode, int(fix_delta_zero), max_iter,
+                          _ptr(nu), _ptr(u), u.shape[0], nu_mode, int(reorder),
+                          int(fix_delta_zero), max_iter,
                           tol, nu_lo, nu_hi, _ptr(trace), ctypes.addressof(n_iter),
                           ctypes.addressof(bad))
     if rc:

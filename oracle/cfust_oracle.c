@@ -390,6 +390,114 @@ int orc_ghk(int q, const double* h, const double* C, double dof, const double* u
 }
 
 /* ------------------------------------------------------------------------- */
+/* variable ordering for the GHK estimator                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Genz-Bretz variable prioritisation (Genz & Bretz, "Computation of
+ * Multivariate Normal and t Probabilities", 2009, section 4.1.3) for the
+ * upper-orthant probability P(Z <= h), Z ~ N(0, R), R a correlation matrix
+ * (unit diagonal).  The variables are placed one at a time.  At step i every
+ * variable j not yet placed has the standardised conditional bound
+ *   b_j = (h_j - sum_{k<i} L_jk y_k) / sqrt(1 - sum_{k<i} L_jk^2),
+ * where L_jk (k < i) are the entries of the Cholesky factor computed so far;
+ * the variable with the smallest b_j (the smallest conditional probability
+ * Phi(b_j); ties go to the lowest index) is placed at step i, the factor is
+ * extended by its column, and y_i = E[Z | Z <= b_i] = -phi(b_i) / Phi(b_i).
+ * On return perm[i] is the variable placed at step i and Cp (q*q row-major,
+ * lower) is the Cholesky factor of R[perm][perm].  The multivariate-t
+ * integrals use the order found for the normal one (scale s = 1).
+ * Returns ORC_ENOTPD when a pivot is not positive. */
+static int genz_order(int q, const double* h, const double* R, int* perm, double* Cp) {
+  double Lr[64 * 64]; /* Lr[j][k]: variable j, step k */
+  double y[64];
+  int used[64];
+  for (int j = 0; j < q; ++j) used[j] = 0;
+  for (int i = 0; i < q; ++i) {
+    int jb = -1;
+    double best = 0.0;
+    for (int j = 0; j < q; ++j) {
+      if (used[j]) continue;
+      double s2 = 1.0, num = h[j];
+      for (int k = 0; k < i; ++k) {
+        s2 -= Lr[j * 64 + k] * Lr[j * 64 + k];
+        num -= Lr[j * 64 + k] * y[k];
+      }
+      double b = num / sqrt(s2);
+      if (jb < 0 || b < best) {
+        jb = j;
+        best = b;
+      }
+    }
+    perm[i] = jb;
+    used[jb] = 1;
+    double s2 = 1.0;
+    for (int k = 0; k < i; ++k) s2 -= Lr[jb * 64 + k] * Lr[jb * 64 + k];
+    if (!(s2 > 0.0)) return ORC_ENOTPD;
+    double piv = sqrt(s2);
+    Lr[jb * 64 + i] = piv;
+    for (int j = 0; j < q; ++j) {
+      if (used[j]) continue;
+      double t = R[j * q + jb];
+      for (int k = 0; k < i; ++k) t -= Lr[j * 64 + k] * Lr[jb * 64 + k];
+      Lr[j * 64 + i] = t / piv;
+    }
+    y[i] = -exp(-0.5 * best * best - LOG_SQRT_2PI_ - orc_log_norm_cdf(best));
+  }
+  for (int i = 0; i < q; ++i)
+    for (int k = 0; k < q; ++k) Cp[i * q + k] = (k <= i) ? Lr[perm[i] * 64 + k] : 0.0;
+  return ORC_OK;
+}
+
+int orc_genz_order(int q, const double* h, const double* R, int* perm, double* Cp) {
+  if (q < 1 || q > 64 || !h || !R || !perm || !Cp) return ORC_EINVAL;
+  return genz_order(q, h, R, perm, Cp);
+}
+
+/* GHK over the variables taken in the order perm (perm NULL: natural order
+ * with factor C; otherwise C is the factor of R[perm][perm]).  The bounds are
+ * taken in that order, step m uses column m+1 of the points as in ghk_core,
+ * and the moments come back in the original labelling. */
+static void ghk_in_order(int q, const double* h, const double* C, const int* perm,
+                         const double* s, const double* u, int n_qmc, int moments, double* logw,
+                         double* ehat, double* logT, double* EV, double* EVV) {
+  if (!perm) {
+    ghk_core(q, h, C, s, u, n_qmc, moments, logw, ehat, logT, EV, EVV);
+    return;
+  }
+  double hp[64], EVp[64], EVVp[64 * 64];
+  for (int i = 0; i < q; ++i) hp[i] = h[perm[i]];
+  ghk_core(q, hp, C, s, u, n_qmc, moments, logw, ehat, logT, EVp, EVVp);
+  if (moments) {
+    for (int i = 0; i < q; ++i) EV[perm[i]] = EVp[i];
+    for (int i = 0; i < q; ++i)
+      for (int k = 0; k < q; ++k) EVV[perm[i] * q + perm[k]] = EVVp[i * q + k];
+  }
+}
+
+int orc_ghk_ordered(int q, const double* h, const double* R, double dof, const double* u,
+                    int n_qmc, int moments, double* logT, double* EV, double* EVV, int* perm) {
+  if (q < 1 || q > 64 || n_qmc < 1 || !(dof > 0.0) || !h || !R || !perm) return ORC_EINVAL;
+  for (int j = 0; j < q; ++j)
+    if (fabs(R[j * q + j] - 1.0) > 1e-12) return ORC_EINVAL;
+  double* Cp = (double*)malloc(sizeof(double) * q * q);
+  double* s = (double*)malloc(sizeof(double) * n_qmc);
+  double* logw = (double*)malloc(sizeof(double) * n_qmc);
+  double* ehat = (double*)malloc(sizeof(double) * (size_t)n_qmc * q);
+  int rc = ORC_OK;
+  if (!Cp || !s || !logw || !ehat) rc = ORC_ENOMEM;
+  if (!rc) rc = genz_order(q, h, R, perm, Cp);
+  if (!rc) {
+    chi_scale_table(u, n_qmc, q, dof, s);
+    ghk_in_order(q, h, Cp, perm, s, u, n_qmc, moments, logw, ehat, logT, EV, EVV);
+  }
+  free(Cp);
+  free(s);
+  free(logw);
+  free(ehat);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* per-component quantities of eq. (2)                                       */
 /* ------------------------------------------------------------------------- */
 
@@ -398,6 +506,7 @@ typedef struct {
   double* B;      /* Omega^{-1} Delta, p*q */
   double* D;      /* sqrt(diag Lambda), q */
   double* C;      /* chol(R), R = D^{-1} Lambda D^{-1}, q*q */
+  double* R;      /* R itself, q*q (for the variable ordering) */
   double* sA;     /* chi scale table, dof nu+p, N */
   double* sB;     /* chi scale table, dof nu+p+2, N */
   double* sAp;    /* chi scale tables, dof (nu+p)(1 +- ORC_FD_REL) (exact e1 only) */
@@ -436,6 +545,7 @@ static void free_comps(comp_t* cp, int g) {
     free(cp[i].B);
     free(cp[i].D);
     free(cp[i].C);
+    free(cp[i].R);
     free(cp[i].sA);
     free(cp[i].sB);
     free(cp[i].sAp);
@@ -468,6 +578,7 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
     c->B = (double*)malloc(sizeof(double) * p * q);
     c->D = (double*)malloc(sizeof(double) * q);
     c->C = (double*)malloc(sizeof(double) * q * q);
+    c->R = (double*)malloc(sizeof(double) * q * q);
     if (tables) {
       c->sA = (double*)malloc(sizeof(double) * n_qmc);
       c->sB = (double*)malloc(sizeof(double) * n_qmc);
@@ -476,7 +587,7 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
       c->sAp = (double*)malloc(sizeof(double) * n_qmc);
       c->sAm = (double*)malloc(sizeof(double) * n_qmc);
     }
-    if (!c->L || !c->B || !c->D || !c->C || (tables && (!c->sA || !c->sB)) ||
+    if (!c->L || !c->B || !c->D || !c->C || !c->R || (tables && (!c->sA || !c->sB)) ||
         (tables == 2 && (!c->sAp || !c->sAm))) {
       rc = ORC_ENOMEM;
       break;
@@ -523,6 +634,7 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
     if (rc) break;
     for (int k = 0; k < q; ++k)
       for (int l = 0; l < q; ++l) Rm[k * q + l] = Lam[k * q + l] / (c->D[k] * c->D[l]);
+    memcpy(c->R, Rm, sizeof(double) * q * q);
     if (cholesky(Rm, q, c->C)) {
       rc = ORC_ENOTPD;
       *bad = i;
@@ -581,8 +693,8 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
  *   s8 = sum tau (e1 - e2). */
 int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
               const double* mu, const double* Sigma, const double* Delta, const double* nu,
-              const double* u, int n_qmc, int nu_mode, double* tau, double* logf, double* e1,
-              double* e2, double* e3, double* e4, double* stats, double* loglik,
+              const double* u, int n_qmc, int nu_mode, int reorder, double* tau, double* logf,
+              double* e1, double* e2, double* e3, double* e4, double* stats, double* loglik,
               int* bad_component) {
   int bad = -1;
   if (bad_component) *bad_component = -1;
@@ -631,9 +743,24 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
         hA[k] = t / c->D[k] * sqrt((v + p) / (v + d));
         hB[k] = t / c->D[k] * sqrt((v + p + 2.0) / (v + d));
       }
+      /* optional variable ordering, found from h_A and used for every
+       * integral of the pair */
+      int perm[64];
+      double Cp[64 * 64];
+      const int* pm = NULL;
+      const double* Cu = c->C;
+      if (reorder) {
+        if (genz_order(q, hA, c->R, perm, Cp)) {
+          rc = ORC_ENOTPD;
+          if (bad_component) *bad_component = i;
+          goto done;
+        }
+        pm = perm;
+        Cu = Cp;
+      }
       double logTA, logTB, EV[64], EVV[64 * 64];
-      ghk_core(q, hA, c->C, c->sA, u, n_qmc, 0, logw, ehat, &logTA, NULL, NULL);
-      ghk_core(q, hB, c->C, c->sB, u, n_qmc, 1, logw, ehat, &logTB, EV, EVV);
+      ghk_in_order(q, hA, Cu, pm, c->sA, u, n_qmc, 0, logw, ehat, &logTA, NULL, NULL);
+      ghk_in_order(q, hB, Cu, pm, c->sB, u, n_qmc, 1, logw, ehat, &logTB, EV, EVV);
       double aa = 0.5 * (v + p), bb = 0.5 * (v + d);
       lf[i] = c->kappa - aa * log1p(d / v) + logTA;
       E1m2[i] = orc_digamma(aa) - log(bb) - aa / bb;
@@ -645,8 +772,8 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
             hP[k] = hA[k] * sqrt(1.0 + ORC_FD_REL);
             hM[k] = hA[k] * sqrt(1.0 - ORC_FD_REL);
           }
-          ghk_core(q, hP, c->C, c->sAp, u, n_qmc, 0, logw, ehat, &lP, NULL, NULL);
-          ghk_core(q, hM, c->C, c->sAm, u, n_qmc, 0, logw, ehat, &lM, NULL, NULL);
+          ghk_in_order(q, hP, Cu, pm, c->sAp, u, n_qmc, 0, logw, ehat, &lP, NULL, NULL);
+          ghk_in_order(q, hM, Cu, pm, c->sAm, u, n_qmc, 0, logw, ehat, &lM, NULL, NULL);
           if (isfinite(lP) && isfinite(lM))
             E1m2[i] = orc_digamma(aa) - log(bb) + (lP - lM) / (2.0 * ORC_FD_REL * aa) - e2v;
         }
@@ -721,7 +848,7 @@ done:
 /* eq. (3) with integral A only. */
 int orc_loglik(const double* y, int64_t n, int p, int q, int g, const double* pi,
                const double* mu, const double* Sigma, const double* Delta, const double* nu,
-               const double* u, int n_qmc, double* loglik, double* logf) {
+               const double* u, int n_qmc, int reorder, double* loglik, double* logf) {
   if (!y || !pi || !mu || !Sigma || !Delta || !nu || !u || !loglik) return ORC_EINVAL;
   if (n_qmc < 1) return ORC_EINVAL;
   int rc = validate_model(n, p, q, g, pi, mu, Sigma, Delta, nu, y);
@@ -753,8 +880,20 @@ int orc_loglik(const double* y, int64_t n, int p, int q, int g, const double* pi
         for (int a = 0; a < p; ++a) t += c->B[a * q + k] * r[a];
         hA[k] = t / c->D[k] * sqrt((v + p) / (v + d));
       }
+      int perm[64];
+      double Cp[64 * 64];
+      const int* pm = NULL;
+      const double* Cu = c->C;
+      if (reorder) {
+        if (genz_order(q, hA, c->R, perm, Cp)) {
+          rc = ORC_ENOTPD;
+          goto done;
+        }
+        pm = perm;
+        Cu = Cp;
+      }
       double logTA;
-      ghk_core(q, hA, c->C, c->sA, u, n_qmc, 0, logw, NULL, &logTA, NULL, NULL);
+      ghk_in_order(q, hA, Cu, pm, c->sA, u, n_qmc, 0, logw, NULL, &logTA, NULL, NULL);
       lf[i] = c->kappa - 0.5 * (v + p) * log1p(d / v) + logTA;
       if (logf) logf[(size_t)j * g + i] = lf[i];
     }
@@ -918,8 +1057,8 @@ double orc_aitken_linf(double l0, double l1, double l2) {
 
 int orc_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, double* mu,
                double* Sigma, double* Delta, double* nu, const double* u, int n_qmc, int nu_mode,
-               int fix_delta_zero, int max_iter, double tol, double nu_lo, double nu_hi,
-               double* loglik_trace, int* n_iter, int* bad_component) {
+               int reorder, int fix_delta_zero, int max_iter, double tol, double nu_lo,
+               double nu_hi, double* loglik_trace, int* n_iter, int* bad_component) {
   if (!loglik_trace || !n_iter || max_iter < 0) return ORC_EINVAL;
   if (n < 1) return ORC_EINVAL;
   offs_t o = stat_offsets(p, q);
@@ -928,8 +1067,8 @@ int orc_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, doub
   int rc = ORC_OK;
   for (int t = 0;; ++t) {
     double ll;
-    rc = orc_estep(y, n, p, q, g, pi, mu, Sigma, Delta, nu, u, n_qmc, nu_mode, NULL, NULL, NULL,
-                   NULL, NULL, NULL, stats, &ll, bad_component);
+    rc = orc_estep(y, n, p, q, g, pi, mu, Sigma, Delta, nu, u, n_qmc, nu_mode, reorder, NULL,
+                   NULL, NULL, NULL, NULL, NULL, stats, &ll, bad_component);
     if (rc) break;
     loglik_trace[t] = ll;
     *n_iter = t;

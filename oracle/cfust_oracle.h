@@ -48,9 +48,21 @@ double orc_chi2_quantile(double u, double dof);
 int orc_ghk(int q, const double* h, const double* C, double dof, const double* u,
             int n_qmc, int moments, double* logT, double* EV, double* EVV);
 
+/* Genz-Bretz variable ordering of P(Z <= h), Z ~ N(0, R), R with unit
+ * diagonal: perm[i] = variable placed at step i, Cp = chol(R[perm][perm]). */
+int orc_genz_order(int q, const double* h, const double* R, int* perm, double* Cp);
+
+/* orc_ghk with the variables in the Genz-Bretz order found from h and R
+ * (R a correlation matrix); moments in the original labelling; perm[q]
+ * returns the order. */
+int orc_ghk_ordered(int q, const double* h, const double* R, double dof, const double* u,
+                    int n_qmc, int moments, double* logT, double* EV, double* EVV, int* perm);
+
+/* reorder != 0: every pair's integrals take the variables in the Genz-Bretz
+ * order found from that pair's bound h_A (orc_genz_order). */
 int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
               const double* mu, const double* Sigma, const double* Delta, const double* nu,
-              const double* u, int n_qmc, int nu_mode,
+              const double* u, int n_qmc, int nu_mode, int reorder,
               double* tau, double* logf, double* e1, double* e2, double* e3, double* e4,
               double* stats, double* loglik, int* bad_component);
 
@@ -61,11 +73,11 @@ int orc_mstep(const double* stats, int64_t n, int p, int q, int g, const double*
 
 int orc_loglik(const double* y, int64_t n, int p, int q, int g, const double* pi,
                const double* mu, const double* Sigma, const double* Delta, const double* nu,
-               const double* u, int n_qmc, double* loglik, double* logf);
+               const double* u, int n_qmc, int reorder, double* loglik, double* logf);
 
 int orc_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, double* mu,
                double* Sigma, double* Delta, double* nu, const double* u, int n_qmc,
-               int nu_mode, int fix_delta_zero, int max_iter, double tol, double nu_lo,
+               int nu_mode, int reorder, int fix_delta_zero, int max_iter, double tol, double nu_lo,
                double nu_hi, double* loglik_trace, int* n_iter, int* bad_component);
 
 int orc_stats_size(int p, int q);
