@@ -92,6 +92,15 @@ typedef struct cfust_opts {
                              cfust_surrogate_adapt before every surrogate E-step
                              (0 = no adaptation) */
   int adapt_epochs;       /* epochs of each of those adaptations */
+  int reorder;            /* 1: every pair's GHK integrals take the variables in the
+                             Genz-Bretz order (Genz & Bretz 2009, section 4.1.3) found
+                             from that pair's bound h_A: at each step the variable with
+                             the smallest standardised conditional bound goes next.
+                             Changes only the QMC error, not the quantity estimated.
+                             cfust_estep, cfust_loglik, cfust_loglik_rqmc, cfust_em_fit,
+                             and cfust_em_fit_multistart after its burn-in; EINVAL with a
+                             surrogate, in cfust_em_fit_batched and cfust_ghk_batch.
+                             0 (default): natural order */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4
@@ -114,6 +123,9 @@ void cfust_default_opts(cfust_opts* opts);
 
 /* Number of statistics per component, S above. */
 int cfust_stats_size(int p, int q);
+
+/* sizeof(cfust_opts) as compiled into the library (bindings check it). */
+size_t cfust_opts_size(void);
 
 /* Bytes of device workspace the entry points need for this problem size. */
 int cfust_workspace_size(int64_t n, int p, int q, int g, int n_qmc, int precision,

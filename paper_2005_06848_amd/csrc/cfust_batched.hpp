@@ -97,8 +97,18 @@ __global__ void bchi_kernel(BatchDev b, const double* __restrict__ comp, int com
 
 // Persistent pair kernel: waves take `chunk` consecutive pair indices at a
 // time from *counter until the index space is exhausted (every wave exits).
+// The loop and slot lookup around pair_eval cost registers: for FP32 at
+// Q = 5 they push the kernel from 3 to 2 waves per SIMD (170 VGPRs), so its
+// budget is held at 3 waves (161 VGPRs, no spill).  At Q = 4 and Q = 6 the
+// same cap would spill, and the compiler's own choice stands.
 template <typename T, int Q>
-__global__ __launch_bounds__(256) void bpair_kernel(BatchDev b, const double* __restrict__ y,
+constexpr int bpair_occupancy() {
+  return (sizeof(T) == 4 && Q == 5) ? 3 : 1;
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bpair_occupancy<T, Q>())))
+void bpair_kernel(BatchDev b, const double* __restrict__ y,
                              const double* __restrict__ mu, const double* __restrict__ comp,
                              const T* __restrict__ sA, const T* __restrict__ sB,
                              const T* __restrict__ rsB, const T* __restrict__ uT,
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(256) void bpair_kernel(BatchDev b, const double* __
       const int i = (int)(local - j * g);
       const int c = c0 + i;
       double out;
-      bool ok = pair_eval<T, Q, true>(y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
+      bool ok = kOk == pair_eval<T, Q, true>(y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
                                       comp + (size_t)c * cl.stride, sA + (size_t)c * N,
                                       sB + (size_t)c * N, rsB + (size_t)c * N, uT, ubT, N, lane,
                                       &out);

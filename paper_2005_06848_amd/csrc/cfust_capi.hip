@@ -66,6 +66,7 @@ struct Plan {
   size_t lds_bytes;
   // byte offsets inside the workspace
   bool exact = false;  // exact E[log W | y] (nu_mode EXACT_FD)
+  bool reorder = false;  // Genz-Bretz variable order per pair (opts.reorder)
   size_t o_sAp, o_sAm;
   size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp,
       o_ll, o_stats, total;
@@ -258,17 +259,36 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   // FP64 with q <= 4 fits four waves per SIMD with little spilling (2.5%
   // faster at p=q=4); larger q spill heavily there and keep the default
   constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4 : 0;
-  if (MOM && pl.exact)
-    pair_kernel<T, Q, MOM, 0, true><<<blocks, 256, 0, ws.st>>>(
-        y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
-        ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N,
-        ws.at<double>(pl.o_pair), pl.W, ws.at<int>(pl.o_status), ws.at<T>(pl.o_sAp),
-        ws.at<T>(pl.o_sAm));
-  else
-    pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
-        y, pl.n, pl.p, pl.g, mu, ws.at<double>(pl.o_comp), ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB),
-        ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), pl.N,
-        ws.at<double>(pl.o_pair), pl.W, ws.at<int>(pl.o_status));
+  const double* comp = ws.at<double>(pl.o_comp);
+  double* pairs_out = ws.at<double>(pl.o_pair);
+  int* status = ws.at<int>(pl.o_status);
+  const T *sA = ws.at<T>(pl.o_sA), *sB = ws.at<T>(pl.o_sB), *rsB = ws.at<T>(pl.o_rsB);
+  const T *uT = ws.at<T>(pl.o_uT), *ubT = ws.at<T>(pl.o_ubT);
+  // the exact-nu variants exist for the E-step only (MOM); the ordered ones
+  // keep the default occupancy (the ordering adds registers)
+  if constexpr (MOM) {
+    if (pl.exact && pl.reorder)
+      pair_kernel<T, Q, MOM, 0, true, true><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
+          ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
+    else if (pl.exact)
+      pair_kernel<T, Q, MOM, 0, true><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
+          ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
+    else if (pl.reorder)
+      pair_kernel<T, Q, MOM, 0, false, true><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+    else
+      pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+  } else {
+    if (pl.reorder)
+      pair_kernel<T, Q, MOM, 0, false, true><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+    else
+      pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+  }
 }
 
 template <typename T, bool MOM>
@@ -474,8 +494,9 @@ void run_mstep(Ws& ws, const Plan& pl, int64_t n, const double* stats, const dou
 int check_surrogate(const cfust_opts* o, int q) {
   if (!o || !o->surrogate) return CFUST_OK;
   const cfust_surrogate* s = o->surrogate;
-  // the network has no derivative output for the exact E[log W | y]
-  if (o->nu_mode == CFUST_NU_EXACT_FD) return CFUST_EINVAL;
+  // the network has no derivative output for the exact E[log W | y], and it
+  // was trained on natural-order GHK labels
+  if (o->nu_mode == CFUST_NU_EXACT_FD || o->reorder) return CFUST_EINVAL;
   return (s->q == q && s->have_std) ? CFUST_OK : CFUST_EINVAL;
 }
 
@@ -486,6 +507,7 @@ int check_opts(const cfust_opts* o) {
       o->nu_mode != CFUST_NU_FIXED)
     return CFUST_EINVAL;
   if (!(o->nu_lo > 0.0) || !(o->nu_hi >= o->nu_lo)) return CFUST_EINVAL;
+  if (o->reorder != 0 && o->reorder != 1) return CFUST_EINVAL;
   return CFUST_OK;
 }
 
@@ -507,6 +529,8 @@ void cfust_default_opts(cfust_opts* o) {
 }
 
 int cfust_stats_size(int p, int q) { return StatLayout(p, q).S; }
+
+size_t cfust_opts_size(void) { return sizeof(cfust_opts); }
 
 int cfust_workspace_size(int64_t n, int p, int q, int g, int n_qmc, int precision, size_t* bytes) {
   if (!bytes) return CFUST_EINVAL;
@@ -537,6 +561,7 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
   const int prec = o ? o->precision : CFUST_FP64;
   Plan pl = make_plan(n, p, q, g, n_qmc, prec);
   pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
+  pl.reorder = o && o->reorder;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
   clear_status(ws, pl);
@@ -562,6 +587,7 @@ int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* 
   if ((n > 0 && !y) || !pi || !mu || !Sigma || !Delta || !nu || !u || !loglik) return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
   Plan pl = make_plan(n, p, q, g, n_qmc, prec);
+  pl.reorder = o && o->reorder;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
   clear_status(ws, pl);
@@ -616,6 +642,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   if (o->max_iter < 0) return CFUST_EINVAL;
   Plan pl = make_plan(n, p, q, g, n_qmc, o->precision);
   pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
+  pl.reorder = o->reorder != 0;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
   double* stats = ws.at<double>(pl.o_stats);
@@ -1080,7 +1107,7 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   cfust_opts def;
   cfust_default_opts(&def);
   if (!o) o = &def;
-  if (o->max_iter < 0 || o->nu_mode == CFUST_NU_EXACT_FD) return CFUST_EINVAL;
+  if (o->max_iter < 0 || o->nu_mode == CFUST_NU_EXACT_FD || o->reorder) return CFUST_EINVAL;
   BPlan pl;
   if ((rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, o->precision, o->max_iter, &pl))) return rc;
   hipStream_t caller = (hipStream_t)o->stream;
@@ -1209,6 +1236,7 @@ extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q,
     ob.max_iter = burn_in;
     ob.tol = 0.0;  // exactly burn_in iterations
     if (ob.nu_mode == CFUST_NU_EXACT_FD) ob.nu_mode = CFUST_NU_OSL;
+    ob.reorder = 0;  // the batched kernels integrate in the natural order
     ob.surrogate = nullptr;
     ob.workspace = nullptr;
     ob.workspace_bytes = 0;
@@ -1360,6 +1388,7 @@ extern "C" int cfust_ghk_batch(int q, int64_t M, const double* h, const double* 
     return CFUST_EINVAL;
   int rc = check_opts(o);
   if (rc) return rc;
+  if (o && o->reorder) return CFUST_EINVAL;
   if (M == 0) return CFUST_OK;
   hipStream_t st = o ? (hipStream_t)o->stream : nullptr;
   if (o && o->precision == CFUST_FP32) return run_ghk_batch<float>(q, M, h, R, dof, u, n_qmc, out, st);

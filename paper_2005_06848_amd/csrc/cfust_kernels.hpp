@@ -40,7 +40,7 @@ enum Status : int {
 
 // Layout of one component's precomputed block (doubles).
 struct CompLayout {
-  int kappa, nu, psi_a, L, B, D, Dinv, C, stride;
+  int kappa, nu, psi_a, L, B, D, Dinv, C, Rm, stride;
   __host__ __device__ CompLayout(int p, int q) {
     kappa = 0;
     nu = 1;
@@ -50,7 +50,8 @@ struct CompLayout {
     D = B + p * q;
     Dinv = D + q;
     C = Dinv + q;
-    stride = (C + q * q + 3) & ~3;
+    Rm = C + q * q;
+    stride = (Rm + q * q + 3) & ~3;
   }
 };
 
@@ -170,6 +171,9 @@ __device__ int precompute_component(int p, int q, double w, double v, const doub
     Dinv[k] = 1.0 / D[k];
   }
   double* C = out + cl.C;
+  double* Rm = out + cl.Rm;
+  for (int k = 0; k < q; ++k)
+    for (int l = 0; l < q; ++l) Rm[k * q + l] = (k == l) ? 1.0 : lam[k * q + l] / (D[k] * D[l]);
   for (int k = 0; k < q; ++k)
     for (int l = 0; l < q; ++l) C[k * q + l] = (l <= k) ? lam[k * q + l] / (D[k] * D[l]) : 0.0;
   for (int j = 0; j < q; ++j) {
@@ -437,21 +441,113 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
 }
 
 // ---------------------------------------------------------------------------
+// Variable ordering (Genz & Bretz 2009, section 4.1.3) for the GHK integrals
+// of one pair.
+// ---------------------------------------------------------------------------
+constexpr double kSqrt2OverPi = 0.79788456080286535588;  // sqrt(2 / pi)
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;   // 1 / sqrt(2 pi)
+
+// E[Z | Z <= b] for Z ~ N(0, 1), i.e. -phi(b) / Phi(b); for b < 0 written
+// with the scaled complementary error function, phi(b)/Phi(b) =
+// sqrt(2/pi) / erfcx(-b/sqrt 2), which stays accurate in the lower tail.
+__device__ __forceinline__ double trunc_mean_upper(double b) {
+  if (b < 0.0) return -kSqrt2OverPi / erfcx(-b * kSqrtHalf);
+  return -kInvSqrt2Pi * exp(-0.5 * b * b) / (1.0 - 0.5 * erfc(b * kSqrtHalf));
+}
+
+// Prioritisation for P(Z <= h), Z ~ N(0, R), R a correlation matrix (Q x Q
+// row-major in global memory; its diagonal is not read).  Step i places the
+// unplaced variable with the smallest standardised conditional bound
+//   b_j = (h_j - sum_{k<i} L_jk y_k) / sqrt(1 - sum_{k<i} L_jk^2)
+// (ties to the lowest index), extends the Cholesky factor by its column and
+// sets y_i = E[Z | Z <= b_i].  perm[i] is the variable placed at step i and
+// Cp the Cholesky factor of R[perm][perm].  Every lane runs it on the same
+// wave-uniform values; the chosen variable's entries are picked out with
+// selects so that every register-array index is a compile-time constant.
+// Returns false if a pivot is not positive.
+template <int Q>
+__device__ __forceinline__ bool genz_order(const double (&h)[Q], const double* __restrict__ R,
+                                           int (&perm)[Q], double (&Cp)[Q][Q]) {
+  double Lr[Q][Q];  // Lr[j][k]: variable j, step k
+  double yv[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    yv[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) Lr[j][k] = 0.0;
+  }
+  unsigned used = 0;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int jb = -1;
+    double best = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (used & (1u << j)) continue;
+      double s2 = 1.0, num = h[j];
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        s2 -= Lr[j][k] * Lr[j][k];
+        num -= Lr[j][k] * yv[k];
+      }
+      const double b = num / sqrt(s2);
+      if (jb < 0 || b < best) {
+        jb = j;
+        best = b;
+      }
+    }
+    perm[i] = jb;
+    used |= 1u << jb;
+    double row[Q];
+    double s2 = 1.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) v = (j == jb) ? Lr[j][k] : v;
+      row[k] = v;
+      if (k < i) s2 -= v * v;
+    }
+    ok = ok && (s2 > 0.0);
+    const double piv = sqrt(s2);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) Cp[i][k] = (k < i) ? row[k] : (k == i ? piv : 0.0);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (used & (1u << j)) continue;
+      double t = R[j * Q + jb];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= Lr[j][k] * row[k];
+      Lr[j][i] = t / piv;
+    }
+    yv[i] = trunc_mean_upper(best);
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // one (observation, component) pair on one wave: lanes split the QMC points
 // of both GHK integrals; after the wave reductions every lane holds the same
 // record and lane t returns entry t of
 //   log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[Q] | e4 (upper triangle)
-// Returns false if y_j is not finite.
+// With REORDER the integrals take the variables in the Genz-Bretz order
+// found from h_A (genz_order), the pair's permuted Cholesky factor is kept in
+// the wave's LDS slot cw[Q*Q] for the moment transform, and the moments are
+// mapped back to the original labelling.
+// Returns kOk, kENonFinite if y_j is not finite, or kENotPD if the ordered
+// factorisation meets a non-positive pivot.
 // ---------------------------------------------------------------------------
-template <typename T, int Q, bool MOM, bool EXACT = false>
-__device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
-                                          const double* __restrict__ mui,
-                                          const double* __restrict__ cp,
-                                          const T* __restrict__ sAi, const T* __restrict__ sBi,
-                                          const T* __restrict__ rsBi, const T* __restrict__ uT,
-                                          const T* __restrict__ ubT, int N, int lane,
-                                          double* lane_out, const T* __restrict__ sApi = nullptr,
-                                          const T* __restrict__ sAmi = nullptr) {
+template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false>
+__device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
+                                         const double* __restrict__ mui,
+                                         const double* __restrict__ cp,
+                                         const T* __restrict__ sAi, const T* __restrict__ sBi,
+                                         const T* __restrict__ rsBi, const T* __restrict__ uT,
+                                         const T* __restrict__ ubT, int N, int lane,
+                                         double* lane_out, const T* __restrict__ sApi = nullptr,
+                                         const T* __restrict__ sAmi = nullptr,
+                                         double* cw = nullptr) {
   constexpr int NT = Q * (Q + 1) / 2;
   const CompLayout cl(p, Q);
   const double v = cp[cl.nu];
@@ -465,7 +561,7 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
     bad = !isfinite(ya);
     ra = ya - mui[lane];
   }
-  if (__ballot(bad) != 0) return false;
+  if (__ballot(bad) != 0) return kENonFinite;
   // forward substitution L z = r, column by column: z_b = t_b / L_bb is
   // broadcast from lane b, then lanes a > b update t_a -= L_ab z_b
   double d = 0.0;
@@ -488,22 +584,60 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
   // ht_m = h_m / C_mm and Ct_ml = C_ml / C_mm
   T htA[Q], htB[Q], Ct[Q][Q];
   double hAd[Q];
+  int perm[Q];
+  const double* Cm = cp + cl.C;  // Cholesky factor in integration order
+  if constexpr (!REORDER) {
 #pragma unroll
-  for (int m = 0; m < Q; ++m) {
-    double cmm = cp[cl.C + m * Q + m];
-    double hbase = c[m] * cp[cl.Dinv + m];
-    hAd[m] = hbase * fa / cmm;
-    htA[m] = (T)hAd[m];
-    htB[m] = (T)(hbase * fb / cmm);
+    for (int m = 0; m < Q; ++m) {
+      double cmm = cp[cl.C + m * Q + m];
+      double hbase = c[m] * cp[cl.Dinv + m];
+      hAd[m] = hbase * fa / cmm;
+      htA[m] = (T)hAd[m];
+      htB[m] = (T)(hbase * fb / cmm);
 #pragma unroll
-    for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(cp[cl.C + m * Q + l] / cmm) : T(0);
+      for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(cp[cl.C + m * Q + l] / cmm) : T(0);
+    }
+  } else {
+    double hbase[Q], hA0[Q], Cp[Q][Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      hbase[m] = c[m] * cp[cl.Dinv + m];
+      hA0[m] = hbase[m] * fa;
+    }
+    if (!genz_order<Q>(hA0, cp + cl.Rm, perm, Cp)) return kENotPD;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      double hb = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) hb = (perm[m] == j) ? hbase[j] : hb;
+      const double cmm = Cp[m][m];
+      hAd[m] = hb * fa / cmm;
+      htA[m] = (T)hAd[m];
+      htB[m] = (T)(hb * fb / cmm);
+#pragma unroll
+      for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(Cp[m][l] / cmm) : T(0);
+    }
+    if (MOM) {
+      // the factor is read again only by the moment transform after the
+      // point loops: park it in this wave's LDS slot instead of registers
+      if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+#pragma unroll
+          for (int l = 0; l < Q; ++l) cw[a * Q + l] = Cp[a][l];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      Cm = cw;
+    }
   }
 
   // ---- a5 / a6: the two GHK integrals over this lane's points ----
   double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
-  ghk_integral<T, Q, false>(htA, Ct, cp + cl.C, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
-  if (MOM) ghk_integral<T, Q, true>(htB, Ct, cp + cl.C, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+  ghk_integral<T, Q, false>(htA, Ct, Cm, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
+  if (MOM) ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
 
   // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a
   // by a central difference over the same points ----
@@ -517,10 +651,43 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
       hm[m] = (T)(hAd[m] * sqrt(1.0 - kFdRel));
     }
     double lp, lm;
-    ghk_integral<T, Q, false>(hp, Ct, cp + cl.C, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
-    ghk_integral<T, Q, false>(hm, Ct, cp + cl.C, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
+    ghk_integral<T, Q, false>(hp, Ct, Cm, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
+    ghk_integral<T, Q, false>(hm, Ct, Cm, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
     fd_ok = isfinite(lp) && isfinite(lm);
     dlogJ = (lp - lm) / (2.0 * kFdRel * 0.5 * (v + p));
+  }
+
+  // moments back to the original labelling: m1[perm[m]] = m1'[m],
+  // m2[perm[m]][perm[n]] = m2'[m][n] (rows, then columns, by selects)
+  if constexpr (REORDER) {
+    if (MOM) {
+      double u1[Q], t2[Q][Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        double v1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) v1 = (perm[m] == a) ? m1[m] : v1;
+        u1[a] = v1;
+#pragma unroll
+        for (int n = 0; n < Q; ++n) {
+          double v2 = 0.0;
+#pragma unroll
+          for (int m = 0; m < Q; ++m) v2 = (perm[m] == a) ? m2[m][n] : v2;
+          t2[a][n] = v2;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        m1[a] = u1[a];
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+          double v2 = 0.0;
+#pragma unroll
+          for (int n = 0; n < Q; ++n) v2 = (perm[n] == b) ? t2[a][n] : v2;
+          m2[a][b] = v2;
+        }
+      }
+    }
   }
 
   // ---- a7: pair assembly (wave-uniform values; lane t stores entry t) ----
@@ -555,7 +722,7 @@ __device__ __forceinline__ bool pair_eval(const double* __restrict__ yj, int p,
       }
   }
   *lane_out = out;
-  return true;
+  return kOk;
 }
 
 
@@ -567,7 +734,7 @@ __host__ __device__ constexpr int record_width() {
 // one wave per pair, four pairs per 256-thread block; OCC > 0 asks for at
 // least OCC resident waves per SIMD (the register budget follows); EXACT adds
 // the two integrals of the exact E[log W | y]
-template <typename T, int Q, bool MOM, int OCC = 0, bool EXACT = false>
+template <typename T, int Q, bool MOM, int OCC = 0, bool EXACT = false, bool REORDER = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 void pair_kernel(
     const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
@@ -583,13 +750,16 @@ void pair_kernel(
   const int64_t j = pair / g;
   const int i = (int)(pair - j * g);
   const CompLayout cl(p, Q);
+  // per-wave slot for the ordered Cholesky factor (REORDER only)
+  __shared__ double cfac[REORDER ? 4 * Q * Q : 1];
   double out;
-  bool ok = pair_eval<T, Q, MOM, EXACT>(
+  const int rc = pair_eval<T, Q, MOM, EXACT, REORDER>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
       sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, &out,
-      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr);
-  if (!ok) {
-    if (lane == 0) set_status(status, kENonFinite, -1);
+      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr,
+      REORDER ? cfac + wv * Q * Q : nullptr);
+  if (rc != kOk) {
+    if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
     return;
   }
   if (lane < record_width<Q, MOM>()) pairbuf[pair * W + lane] = out;

@@ -33,6 +33,12 @@ __host__ __device__ constexpr int64_t mlp_b_off(int l) {
 __host__ __device__ constexpr int64_t mlp_wb_off(int l) {
   return l == 0 ? 0 : mlp_wb_off(l - 1) + (int64_t)mlp_n(l - 1) * mlp_k(l - 1);
 }
+// the same offsets as compile-time constants (device code must not call the
+// recursive helpers at run time: that is a real call with a dynamic stack)
+template <int L>
+struct MlpOff {
+  static constexpr int64_t w = mlp_w_off(L), b = mlp_b_off(L), wb = mlp_wb_off(L);
+};
 constexpr int64_t kMlpParams = mlp_b_off(kMlpLayers - 1) + mlp_n(kMlpLayers - 1);
 constexpr int64_t kMlpWeightsBf = mlp_wb_off(kMlpLayers);
 
@@ -275,13 +281,13 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const bf16* __restrict__
     dst[1] = src[1];
   }
   __syncthreads();
-  fused_layer<mlp_k(0), mlp_n(0), false>(Hs, wb + mlp_wb_off(0), params + mlp_b_off(0), nullptr,
+  fused_layer<mlp_k(0), mlp_n(0), false>(Hs, wb + MlpOff<0>::wb, params + MlpOff<0>::b, nullptr,
                                          row0, lane, w);
-  fused_layer<mlp_k(1), mlp_n(1), false>(Hs, wb + mlp_wb_off(1), params + mlp_b_off(1), nullptr,
+  fused_layer<mlp_k(1), mlp_n(1), false>(Hs, wb + MlpOff<1>::wb, params + MlpOff<1>::b, nullptr,
                                          row0, lane, w);
-  fused_layer<mlp_k(2), mlp_n(2), false>(Hs, wb + mlp_wb_off(2), params + mlp_b_off(2), nullptr,
+  fused_layer<mlp_k(2), mlp_n(2), false>(Hs, wb + MlpOff<2>::wb, params + MlpOff<2>::b, nullptr,
                                          row0, lane, w);
-  fused_layer<mlp_k(3), mlp_n(3), true>(Hs, wb + mlp_wb_off(3), params + mlp_b_off(3), P, row0,
+  fused_layer<mlp_k(3), mlp_n(3), true>(Hs, wb + MlpOff<3>::wb, params + MlpOff<3>::b, P, row0,
                                         lane, w);
 }
 
@@ -462,9 +468,14 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
 __global__ void weights_to_bf16_kernel(const float* __restrict__ w, bf16* __restrict__ wb) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= kMlpWeightsBf) return;
-  int l = 0;
-  while (l < kMlpLayers - 1 && t >= mlp_wb_off(l + 1)) ++l;
-  wb[t] = f2bf(w[mlp_w_off(l) + (t - mlp_wb_off(l))]);
+  static_assert(kMlpLayers == 4, "one branch per layer");
+  // W_l sits at MlpOff<l>::w in the parameter vector (after b_{l-1}) and at
+  // MlpOff<l>::wb in the bf16 copy (weights only)
+  const int64_t shift = t >= MlpOff<3>::wb   ? MlpOff<3>::w - MlpOff<3>::wb
+                        : t >= MlpOff<2>::wb ? MlpOff<2>::w - MlpOff<2>::wb
+                        : t >= MlpOff<1>::wb ? MlpOff<1>::w - MlpOff<1>::wb
+                                             : 0;
+  wb[t] = f2bf(w[t + shift]);
 }
 
 // per-column mean and standard deviation of X[M][D] (double), two passes,

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void pair_list_kernel(
     const int64_t j = pair / g;
     const int i = (int)(pair - j * g);
     double out;
-    bool ok = pair_eval<T, Q, true>(y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride,
+    bool ok = kOk == pair_eval<T, Q, true>(y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride,
                                     sA + (size_t)i * N, sB + (size_t)i * N, rsB + (size_t)i * N,
                                     uT, ubT, N, lane, &out);
     if (!ok) {

@@ -45,6 +45,7 @@ class Opts(ctypes.Structure):
         ("surrogate", ctypes.c_void_p),
         ("adapt_samples", ctypes.c_int),
         ("adapt_epochs", ctypes.c_int),
+        ("reorder", ctypes.c_int),
     ]
 
 
@@ -149,6 +150,11 @@ def _lib():
         L.cfust_mlp_gemm.restype = i
         L.cfust_strerror.argtypes = [i]
         L.cfust_strerror.restype = ctypes.c_char_p
+        L.cfust_opts_size.argtypes = []
+        L.cfust_opts_size.restype = sz
+        if L.cfust_opts_size() != ctypes.sizeof(Opts):
+            raise ImportError(f"{LIB_PATH}: cfust_opts is {L.cfust_opts_size()} bytes in the "
+                              f"library but {ctypes.sizeof(Opts)} in this binding (stale build?)")
         _LIB = L
     return _LIB
 
@@ -171,7 +177,7 @@ def _ptr(t):
 
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
               nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0,
-              surrogate=None, adapt_samples=0, adapt_epochs=0):
+              surrogate=None, adapt_samples=0, adapt_epochs=0, reorder=False):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -196,6 +202,7 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
         o.surrogate = surrogate.handle
     o.adapt_samples = int(adapt_samples)
     o.adapt_epochs = int(adapt_epochs)
+    o.reorder = int(bool(reorder))
     return o
 
 

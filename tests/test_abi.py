@@ -44,6 +44,9 @@ def test_host_only_entry_points(libpath):
         assert abs(L.cfust_aitken_linf(*l) - lstar) < 1e-9 * abs(lstar)
     L.cfust_strerror.restype = ctypes.c_char_p
     assert L.cfust_strerror(2) == b"matrix not positive definite"
+    from paper_2005_06848_amd import native
+    L.cfust_opts_size.restype = ctypes.c_size_t
+    assert L.cfust_opts_size() == ctypes.sizeof(native.Opts)
 
 
 def test_workspace_size_and_limits(libpath):

@@ -1,0 +1,176 @@
+"""Genz-Bretz variable ordering (opts.reorder) on the GPU against the FP64
+oracle with the same ordering.
+
+Bar: FP64 1e-10 per quantity as in tests/parity.py (the order is an integer
+decision taken in FP64 on both sides from the same bound h_A); FP32 1e-4 on
+moments and statistics, 1e-7 on the log-likelihood; EM traces and parameters
+1e-9.  Sizes span q = 1..8, ragged point counts and observation counts."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def P(par, dev):
+    return {k: T(v, dev) for k, v in par.items() if k in ("pi", "mu", "Sigma", "Delta", "nu")}
+
+
+def gpu_estep(dev, y, par, u, **opt):
+    from paper_2005_06848_amd import native
+    print(f"[gpu] reorder estep n={y.shape[0]} p={y.shape[1]} q={par['Delta'].shape[2]} "
+          f"g={len(par['pi'])} N={u.shape[0]} {opt}", flush=True)
+    g = native.cfust_estep(T(y, dev), P(par, dev), T(u, dev), reorder=True, **opt)
+    out = {k: v.cpu().numpy() for k, v in g.items()}
+    out["loglik"] = float(out["loglik"][0])
+    return out
+
+
+SHAPES = [(1, None), (0, (90, 3, 2, 3, 300)), (0, (65, 2, 4, 2, 1000)), (0, (33, 5, 1, 2, 129)),
+          (0, (41, 6, 6, 3, 257)), (0, (17, 7, 7, 2, 65)), (0, (23, 8, 8, 2, 100)),
+          (0, (12, 5, 5, 4, 63))]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_reorder_estep_parity(dev, orc, shape):
+    from paper_2005_06848_amd import inputs
+    import parity
+    if shape[0] == 1:
+        c = inputs.config(1)
+        y, par, u = c["y"], c["init"], c["u"]
+    else:
+        n, p, q, g, N = shape[1]
+        c = inputs.random_case(71 + n, n, p, q, g, N)
+        y, par, u = c["y"], c["params"], c["u"]
+    q = par["Delta"].shape[2]
+    ref = orc.estep(y, par, u, reorder=True)
+    got = gpu_estep(dev, y, par, u)
+    err = parity.estep_errors(got, ref, y.shape[1], q)
+    bad = {k: v for k, v in err.items() if not v <= TOL}
+    assert not bad, err
+    if q > 1:
+        # the order changes the estimates (the test is not vacuous)
+        nat = orc.estep(y, par, u, want=("logf",))["logf"]
+        assert np.max(np.abs(nat - ref["logf"])) > 1e-9
+
+
+def test_reorder_loglik_and_exact_nu(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.random_case(81, 70, 5, 4, 3, 515)
+    y, par, u = c["y"], c["params"], c["u"]
+    ll_ref, lf_ref = orc.loglik(y, par, u, want_logf=True, reorder=True)
+    print("[gpu] reorder loglik n=70 p=5 q=4 g=3 N=515", flush=True)
+    ll, lf = native.cfust_loglik(T(y, dev), P(par, dev), T(u, dev), want_logf=True, reorder=True)
+    assert abs(float(ll) - ll_ref) <= TOL * abs(ll_ref)
+    assert np.max(np.abs(lf.cpu().numpy() - lf_ref)) <= TOL
+    ref = orc.estep(y, par, u, nu_mode=orc.NU_EXACT_FD, reorder=True)
+    got = gpu_estep(dev, y, par, u, nu_mode="exact")
+    err = parity.estep_errors(got, ref, 5, 4)
+    assert max(err.values()) <= TOL, err
+
+
+def test_reorder_fp32_form(dev, orc):
+    from paper_2005_06848_amd import inputs
+    import parity
+    c = inputs.random_case(91, 200, 6, 6, 2, 2048)
+    ref = orc.estep(c["y"], c["params"], c["u"], reorder=True)
+    got = gpu_estep(dev, c["y"], c["params"], c["u"], precision="fp32")
+    err = parity.estep_errors(got, ref, 6, 6)
+    assert err["e3"] < 1e-4 and err["e4"] < 1e-4 and err["stats"] < 1e-4, err
+    assert err["loglik"] < 1e-7, err
+
+
+def test_reorder_full_size_sampled_rows(dev, orc):
+    """Workload 2 at full size (n = 20000, p = q = 4, g = 3, N = 4096) in the
+    launch the benchmark uses; 24 sampled observations against the oracle
+    (pair quantities and tau of a row depend on that row only)."""
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(2)
+    y, par, u = c["y"], c["init"], c["u"]
+    got = gpu_estep(dev, y, par, u)
+    rows = np.random.default_rng(5).choice(len(y), 24, replace=False)
+    ref = orc.estep(y[rows], par, u, reorder=True)
+    sub = {k: got[k][rows] for k in ("tau", "logf", "e1", "e2", "e3", "e4")}
+    sub["stats"], sub["loglik"] = ref["stats"], ref["loglik"]
+    import parity
+    err = parity.estep_errors(sub, ref, 4, 4)
+    assert max(err.values()) <= TOL, err
+
+
+def test_reorder_em_fit_and_multistart(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.random_case(95, 300, 4, 3, 2, 1024)
+    y, par, u = c["y"], c["params"], c["u"]
+    ref = orc.em_fit(y, par, u, max_iter=6, tol=0.0, reorder=True)
+    print("[gpu] reorder em_fit n=300", flush=True)
+    fit = native.cfust_em_fit(T(y, dev), P(par, dev), T(u, dev), max_iter=6, tol=0.0,
+                              reorder=True)
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-9)
+    err = parity.params_rel_err({k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")},
+                                ref)
+    assert max(err.values()) < 1e-9, err
+    starts = inputs.multistart_inits(y, 2, 3, 3, seed=3)
+    # k-means++ finds one partition here: spread the starts so that the
+    # selection has something to choose
+    for k, s in enumerate(starts):
+        s["mu"] = s["mu"] + 0.4 * k * np.random.default_rng(k).standard_normal(s["mu"].shape)
+    mref = orc.em_fit_multistart(y, starts, u, burn_in=2, max_iter=4, tol=0.0, reorder=True)
+    print("[gpu] reorder multistart m=3", flush=True)
+    ms = native.cfust_em_fit_multistart(T(y, dev), [P(s, dev) for s in starts], T(u, dev),
+                                        burn_in=2, max_iter=4, tol=0.0, reorder=True)
+    assert ms["best"] == mref["best"]
+    np.testing.assert_allclose(ms["trace"], mref["trace"], rtol=1e-9)
+
+
+def test_reorder_rejected_where_unsupported(dev):
+    from paper_2005_06848_amd import inputs, native, surrogate
+    c = inputs.random_case(5, 50, 6, 6, 2, 64)
+    net = native.Surrogate.load(surrogate.DEFAULT_PATH)
+    with pytest.raises(native.CfustError):
+        native.cfust_estep(T(c["y"], dev), P(c["params"], dev), T(c["u"], dev), reorder=True,
+                           surrogate=net)
+    h = T(np.zeros((4, 6)), dev)
+    R = T(np.broadcast_to(np.eye(6), (4, 6, 6)), dev)
+    with pytest.raises(native.CfustError):
+        native.cfust_ghk_batch(h, R, T(np.full(4, 8.0), dev), T(c["u"], dev), reorder=True)
+
+
+def test_reorder_rqmc_error_bar(dev):
+    """Randomised-QMC standard error of l on workload 1 over K = 16 shifts,
+    natural order and Genz-Bretz order: the means agree within the combined
+    error bar (both estimate the same l)."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(1)
+    q = c["init"]["Delta"].shape[2]
+    us = T(np.stack([inputs.qmc_points(1024, q, seed=300 + k) for k in range(16)]), dev)
+    y, par = T(c["y"], dev), P(c["init"], dev)
+    print("[gpu] reorder rqmc workload 1 K=16 N=1024", flush=True)
+    _, ma, sa = native.cfust_loglik_rqmc(y, par, us)
+    _, mb, sb = native.cfust_loglik_rqmc(y, par, us, reorder=True)
+    print(f"  natural: {ma:.6f} +- {sa:.2e}; ordered: {mb:.6f} +- {sb:.2e}")
+    assert abs(ma - mb) < 5 * np.hypot(sa, sb)
