@@ -23,7 +23,11 @@
  *    stream).  Every entry point waits for its own work before returning, so
  *    that it can report errors found on the device.
  *  - Functions return CFUST_OK (0) or an error code; they never throw.
- *  - Limits: 1 <= p <= 32, 1 <= q <= 8, 1 <= g <= 16, n_qmc >= 1, n >= 0.
+ *  - Limits: 1 <= p <= 32, 1 <= q <= 12, 1 <= g <= 16, n_qmc >= 1, n >= 0.
+ *    For 9 <= q <= 12 the natural-order E-step, log-likelihood, M-step and
+ *    EM fit exist (FP64 and FP32); the exact nu step, the variable ordering,
+ *    the surrogate, the batched form, the multistart fit and the GHK label
+ *    batch return CFUST_EINVAL there.
  *
  * Sufficient statistics ("partial sums" of Algorithm 2) are stats[g][S] with
  * S = cfust_stats_size(p, q) = 3 + p + q + p q + p(p+1)/2 + q(q+1)/2, per

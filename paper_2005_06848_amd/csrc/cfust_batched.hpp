@@ -117,6 +117,7 @@ void bpair_kernel(BatchDev b, const double* __restrict__ y,
   const int lane = threadIdx.x & 63;
   const CompLayout cl(b.p, Q);
   constexpr int RW = record_width<Q, true>();
+  static_assert(RW <= 64, "one record entry per lane");
   for (;;) {
     unsigned int base = 0;
     if (lane == 0) base = atomicAdd(counter, (unsigned int)chunk);
@@ -225,7 +226,7 @@ __global__ void baitken_kernel(BatchDev b, int max_iter, double tol) {
 __global__ void bmstep_kernel(BatchDev b, const double* __restrict__ stats, int nu_fixed,
                               int fix_delta_zero, double nu_lo, double nu_hi, double* pi,
                               double* mu, double* Sigma, double* Delta, double* nu,
-                              double* __restrict__ pi_tmp) {
+                              double* __restrict__ pi_tmp, double* __restrict__ mwork) {
   const int k = blockIdx.x;
   if (!b.active[k]) return;
   const int c0 = b.g_off[k], g = b.g_off[k + 1] - c0;
@@ -235,7 +236,7 @@ __global__ void bmstep_kernel(BatchDev b, const double* __restrict__ stats, int 
   mstep_body(stats + (size_t)c0 * b.S, n, p, q, g, mu + (size_t)c0 * p,
              Delta + (size_t)c0 * p * q, nu + c0, nu_fixed, fix_delta_zero, nu_lo, nu_hi,
              pi + c0, mu + (size_t)c0 * p, Sigma + (size_t)c0 * p * p, Delta + (size_t)c0 * p * q,
-             nu + c0, pi_tmp + c0, st);
+             nu + c0, pi_tmp + c0, mwork + (size_t)c0 * mstep_work_doubles(p, q), st);
   __syncthreads();
   if (threadIdx.x == 0 && st[0] != kOk) b.active[k] = 0;
 }

@@ -68,7 +68,7 @@ struct Plan {
   bool exact = false;  // exact E[log W | y] (nu_mode EXACT_FD)
   bool reorder = false;  // Genz-Bretz variable order per pair (opts.reorder)
   size_t o_sAp, o_sAm;
-  size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp,
+  size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp, o_mwork,
       o_ll, o_stats, total;
 };
 
@@ -126,6 +126,8 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec) {
   off = align_up(off + (size_t)pl.nb * sizeof(double));
   pl.o_pitmp = off;
   off = align_up(off + (size_t)g * sizeof(double));
+  pl.o_mwork = off;
+  off = align_up(off + (size_t)g * mstep_work_doubles(p, q) * sizeof(double));
   pl.o_ll = off;
   off = align_up(off + sizeof(double));
   pl.o_stats = off;
@@ -265,8 +267,13 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   const T *sA = ws.at<T>(pl.o_sA), *sB = ws.at<T>(pl.o_sB), *rsB = ws.at<T>(pl.o_rsB);
   const T *uT = ws.at<T>(pl.o_uT), *ubT = ws.at<T>(pl.o_ubT);
   // the exact-nu variants exist for the E-step only (MOM); the ordered ones
-  // keep the default occupancy (the ordering adds registers)
-  if constexpr (MOM) {
+  // keep the default occupancy (the ordering adds registers).  Above
+  // kMaxQFull only the natural-order kernel exists (the entry points reject
+  // the other forms there).
+  if constexpr (Q > kMaxQFull) {
+    pair_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
+        y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+  } else if constexpr (MOM) {
     if (pl.exact && pl.reorder)
       pair_kernel<T, Q, MOM, 0, true, true><<<blocks, 256, 0, ws.st>>>(
           y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
@@ -302,6 +309,10 @@ void launch_pairs(const Ws& ws, const Plan& pl, const double* y, const double* m
     case 6: launch_pairs_q<T, 6, MOM>(ws, pl, y, mu); break;
     case 7: launch_pairs_q<T, 7, MOM>(ws, pl, y, mu); break;
     case 8: launch_pairs_q<T, 8, MOM>(ws, pl, y, mu); break;
+    case 9: launch_pairs_q<T, 9, MOM>(ws, pl, y, mu); break;
+    case 10: launch_pairs_q<T, 10, MOM>(ws, pl, y, mu); break;
+    case 11: launch_pairs_q<T, 11, MOM>(ws, pl, y, mu); break;
+    case 12: launch_pairs_q<T, 12, MOM>(ws, pl, y, mu); break;
   }
 }
 
@@ -487,7 +498,8 @@ void run_mstep(Ws& ws, const Plan& pl, int64_t n, const double* stats, const dou
   prof_begin(ws, 3);
   mstep_kernel<<<1, 64, 0, ws.st>>>(stats, n, pl.p, pl.q, pl.g, mu_old, Delta_old, nu_old,
                                     fixed, fixd, lo, hi, pi, mu, Sigma, Delta, nu,
-                                    ws.at<double>(pl.o_pitmp), ws.at<int>(pl.o_status));
+                                    ws.at<double>(pl.o_pitmp), ws.at<double>(pl.o_mwork),
+                                    ws.at<int>(pl.o_status));
   prof_end(ws, 3);
 }
 
@@ -498,6 +510,13 @@ int check_surrogate(const cfust_opts* o, int q) {
   // was trained on natural-order GHK labels
   if (o->nu_mode == CFUST_NU_EXACT_FD || o->reorder) return CFUST_EINVAL;
   return (s->q == q && s->have_std) ? CFUST_OK : CFUST_EINVAL;
+}
+
+// forms that exist only up to kMaxQFull
+int check_q_forms(const cfust_opts* o, int q) {
+  if (!o || q <= kMaxQFull) return CFUST_OK;
+  return (o->nu_mode == CFUST_NU_EXACT_FD || o->reorder || o->surrogate) ? CFUST_EINVAL
+                                                                          : CFUST_OK;
 }
 
 int check_opts(const cfust_opts* o) {
@@ -556,6 +575,7 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
   if (rc) return rc;
   if ((rc = check_opts(o))) return rc;
   if ((rc = check_surrogate(o, q))) return rc;
+  if ((rc = check_q_forms(o, q))) return rc;
   if ((n > 0 && !y) || !pi || !mu || !Sigma || !Delta || !nu || !u || !out->stats || !out->loglik)
     return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
@@ -584,6 +604,7 @@ int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* 
   if (rc) return rc;
   if ((rc = check_opts(o))) return rc;
   if ((rc = check_surrogate(o, q))) return rc;
+  if ((rc = check_q_forms(o, q))) return rc;
   if ((n > 0 && !y) || !pi || !mu || !Sigma || !Delta || !nu || !u || !loglik) return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
   Plan pl = make_plan(n, p, q, g, n_qmc, prec);
@@ -634,6 +655,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   if (n < 1) return CFUST_EINVAL;
   if ((rc = check_opts(o))) return rc;
   if ((rc = check_surrogate(o, q))) return rc;
+  if ((rc = check_q_forms(o, q))) return rc;
   if (!y || !pi || !mu || !Sigma || !Delta || !nu || !u || !loglik_trace || !n_iter)
     return CFUST_EINVAL;
   cfust_opts def;
@@ -758,7 +780,7 @@ struct BPlan {
   // workspace offsets
   size_t o_noff, o_goff, o_poff, o_boff, o_perb, o_partoff, o_roff, o_active, o_status, o_iter,
       o_niter, o_llcur, o_trace, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll,
-      o_stats, o_pitmp, o_counter, o_pstat, total;
+      o_stats, o_pitmp, o_mwork, o_counter, o_pstat, total;
 };
 
 int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, int prec,
@@ -843,6 +865,7 @@ int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, i
   pl->o_pll = take((size_t)pl->total_blocks * sizeof(double));
   pl->o_stats = take((size_t)pl->G * pl->S * sizeof(double));
   pl->o_pitmp = take((size_t)pl->G * sizeof(double));
+  pl->o_mwork = take((size_t)pl->G * mstep_work_doubles(p, q) * sizeof(double));
   pl->o_counter = take(64);
   pl->o_pstat = take(4 * sizeof(int));
   pl->total = off;
@@ -935,7 +958,8 @@ void batched_iteration(const BPlan& pl, const BatchDev& b, char* base, const BAr
   baitken_kernel<<<(pl.P + 63) / 64, 64, 0, st>>>(b, pl.max_iter, a.tol);
   bmstep_kernel<<<pl.P, 64, 0, st>>>(b, (const double*)(base + pl.o_stats), a.nu_fixed,
                                      a.fix_delta_zero, a.nu_lo, a.nu_hi, a.pi, a.mu, a.Sigma,
-                                     a.Delta, a.nu, (double*)(base + pl.o_pitmp));
+                                     a.Delta, a.nu, (double*)(base + pl.o_pitmp),
+                                     (double*)(base + pl.o_mwork));
 }
 
 // Autotuner: times the persistent pair kernel of every candidate shape on the
@@ -1101,7 +1125,7 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   if (n_problems < 1 || !n_obs || !g || !y || !pi || !mu || !Sigma || !Delta || !nu || !u ||
       !loglik_trace || !n_iter || !status)
     return CFUST_EINVAL;
-  if (p < 1 || p > kMaxP || q < 1 || q > kMaxQ || n_qmc < 1) return CFUST_EINVAL;
+  if (p < 1 || p > kMaxP || q < 1 || q > kMaxQFull || n_qmc < 1) return CFUST_EINVAL;
   int rc = check_opts(o);
   if (rc) return rc;
   cfust_opts def;
@@ -1196,6 +1220,7 @@ extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q,
   int rc = check_dims(n, p, q, g, n_qmc);
   if (rc) return rc;
   if ((rc = check_opts(o))) return rc;
+  if (q > kMaxQFull) return CFUST_EINVAL;  // the burn-in runs in the batched form
   if (n < 1 || m < 1 || burn_in < 0 || !y || !pi0 || !mu0 || !Sigma0 || !Delta0 || !nu0 || !u ||
       !pi || !mu || !Sigma || !Delta || !nu || !best || !loglik_trace || !n_iter)
     return CFUST_EINVAL;
@@ -1281,7 +1306,7 @@ extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q,
 extern "C" int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_obs,
                                             const int* g, int n_qmc, int precision, int max_iter,
                                             size_t* bytes) {
-  if (!bytes || n_problems < 1 || !n_obs || !g || p < 1 || p > kMaxP || q < 1 || q > kMaxQ ||
+  if (!bytes || n_problems < 1 || !n_obs || !g || p < 1 || p > kMaxP || q < 1 || q > kMaxQFull ||
       n_qmc < 1 || max_iter < 0)
     return CFUST_EINVAL;
   BPlan pl;
@@ -1384,7 +1409,7 @@ int run_ghk_batch(int q, int64_t M, const double* h, const double* R, const doub
 extern "C" int cfust_ghk_batch(int q, int64_t M, const double* h, const double* R,
                                const double* dof, const double* u, int n_qmc, const cfust_opts* o,
                                double* out) {
-  if (q < 1 || q > kMaxQ || M < 0 || n_qmc < 1 || (M > 0 && (!h || !R || !dof || !out)) || !u)
+  if (q < 1 || q > kMaxQFull || M < 0 || n_qmc < 1 || (M > 0 && (!h || !R || !dof || !out)) || !u)
     return CFUST_EINVAL;
   int rc = check_opts(o);
   if (rc) return rc;
@@ -1607,7 +1632,7 @@ extern "C" {
 
 int cfust_surrogate_create(int q, const double* range, unsigned long long seed,
                            cfust_surrogate** out) {
-  if (!out || !range || q < 1 || q > kMaxQ) return CFUST_EINVAL;
+  if (!out || !range || q < 1 || q > kMaxQFull) return CFUST_EINVAL;
   *out = nullptr;
   if (!(range[0] < range[1]) || !(range[2] > 0.0) || !(range[2] <= range[3]) ||
       !(range[4] > 0.0) || !(range[5] >= 0.0))
@@ -1901,7 +1926,7 @@ int cfust_surrogate_load(const char* path, cfust_surrogate** out) {
   SurrFileHeader hd{};
   std::vector<float> stdv(CFUST_SURR_STD), w((size_t)kMlpParams);
   bool ok = fread(&hd, sizeof(hd), 1, f) == 1 && memcmp(hd.magic, "CFUSTNN1", 8) == 0 &&
-            hd.version == 1 && hd.q >= 1 && hd.q <= kMaxQ && hd.F == surr_feat_width(hd.q) &&
+            hd.version == 1 && hd.q >= 1 && hd.q <= kMaxQFull && hd.F == surr_feat_width(hd.q) &&
             hd.T == surr_targ_width(hd.q) && hd.hidden == kMlpHid && hd.layers == kMlpLayers &&
             hd.nparams == kMlpParams &&
             fread(stdv.data(), sizeof(float), CFUST_SURR_STD, f) == (size_t)CFUST_SURR_STD &&
@@ -2052,6 +2077,7 @@ int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const d
   int rc = check_dims(n, p, q, g, 1);
   if (rc) return rc;
   if ((rc = check_opts(o))) return rc;
+  if (q > kMaxQFull) return CFUST_EINVAL;
   if ((n > 0 && (!y || !out)) || !pi || !mu || !Sigma || !Delta || !nu) return CFUST_EINVAL;
   Plan pl = make_plan(0, p, q, g, 1, CFUST_FP64);
   Ws ws;

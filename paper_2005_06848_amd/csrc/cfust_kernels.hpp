@@ -24,7 +24,8 @@
 namespace cfust {
 
 constexpr int kMaxP = 32;
-constexpr int kMaxQ = 8;
+constexpr int kMaxQ = 12;      // E-step, log-likelihood, M-step and EM fit (FP64, FP32)
+constexpr int kMaxQFull = 8;   // exact nu step, variable ordering, batched form, surrogate
 constexpr int kMaxG = 16;
 
 // relative step in a = (nu+p)/2 of the central difference that gives the
@@ -134,23 +135,24 @@ __device__ int precompute_component(int p, int q, double w, double v, const doub
   double logdet = 0.0;
   for (int a = 0; a < p; ++a) logdet += log(L[a * p + a]);
   logdet *= 2.0;
-  // B = Omega^{-1} Delta by two triangular solves per column
+  // B = Omega^{-1} Delta by two triangular solves per column, in place in
+  // B's column (the forward solve leaves L^{-1} Delta there)
   double* B = out + cl.B;
   for (int k = 0; k < q; ++k) {
-    double tmp[kMaxP];
     for (int a = 0; a < p; ++a) {
       double t = Dl[a * q + k];
-      for (int b = 0; b < a; ++b) t -= L[a * p + b] * tmp[b];
-      tmp[a] = t / L[a * p + a];
+      for (int b = 0; b < a; ++b) t -= L[a * p + b] * B[b * q + k];
+      B[a * q + k] = t / L[a * p + a];
     }
     for (int a = p - 1; a >= 0; --a) {
-      double t = tmp[a];
+      double t = B[a * q + k];
       for (int b = a + 1; b < p; ++b) t -= L[b * p + a] * B[b * q + k];
       B[a * q + k] = t / L[a * p + a];
     }
   }
-  // Lambda = I - Delta^T B (symmetrised), D = sqrt(diag), R = D^-1 Lambda D^-1
-  double lam[kMaxQ * kMaxQ];
+  // Lambda = I - Delta^T B (symmetrised), D = sqrt(diag), R = D^-1 Lambda D^-1;
+  // Lambda is built in R's slot and scaled there in place
+  double* lam = out + cl.Rm;
   for (int k = 0; k < q; ++k)
     for (int l = 0; l < q; ++l) {
       double t = (k == l) ? 1.0 : 0.0;
@@ -173,9 +175,9 @@ __device__ int precompute_component(int p, int q, double w, double v, const doub
   double* C = out + cl.C;
   double* Rm = out + cl.Rm;
   for (int k = 0; k < q; ++k)
-    for (int l = 0; l < q; ++l) Rm[k * q + l] = (k == l) ? 1.0 : lam[k * q + l] / (D[k] * D[l]);
-  for (int k = 0; k < q; ++k)
     for (int l = 0; l < q; ++l) C[k * q + l] = (l <= k) ? lam[k * q + l] / (D[k] * D[l]) : 0.0;
+  for (int k = 0; k < q; ++k)
+    for (int l = 0; l < q; ++l) Rm[k * q + l] = (k == l) ? 1.0 : lam[k * q + l] / (D[k] * D[l]);
   for (int j = 0; j < q; ++j) {
     double s = C[j * q + j];
     for (int k = 0; k < j; ++k) s -= C[j * q + k] * C[j * q + k];
@@ -526,10 +528,17 @@ __device__ __forceinline__ bool genz_order(const double (&h)[Q], const double* _
   return ok;
 }
 
+// doubles in the record of one pair (see pair_eval)
+template <int Q, bool MOM>
+__host__ __device__ constexpr int record_width() {
+  return MOM ? (3 + Q + Q * (Q + 1) / 2) : 1;
+}
+
 // ---------------------------------------------------------------------------
 // one (observation, component) pair on one wave: lanes split the QMC points
 // of both GHK integrals; after the wave reductions every lane holds the same
-// record and lane t returns entry t of
+// record and lane t returns entry t (and entry t + 64 in lane_out[1] when the
+// record is wider than 64) of
 //   log(pi_i f_i(y_j)) | e2 | e1 - e2 | e3[Q] | e4 (upper triangle)
 // With REORDER the integrals take the variables in the Genz-Bretz order
 // found from h_A (genz_order), the pair's permuted Cholesky factor is kept in
@@ -693,7 +702,17 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
   // ---- a7: pair assembly (wave-uniform values; lane t stores entry t) ----
   const double aa = 0.5 * (v + p);
   const double bb = 0.5 * (v + d);
+  // records wider than a wave (Q >= 10: 3 + Q + Q(Q+1)/2 > 64) put entry
+  // t >= 64 in the second slot of lane t - 64; t is a compile-time constant
+  // in every call below
   double out = cp[cl.kappa] - aa * log1p(d / v) + logTA;
+  double out2 = 0.0;
+  auto put = [&](int t, double val) {
+    if (t < 64)
+      out = (lane == t) ? val : out;
+    else
+      out2 = (lane == t - 64) ? val : out2;
+  };
   if (MOM) {
     const bool ok = isfinite(logTA) && isfinite(logTB);
     const double e2 = ok ? (aa / bb) * exp(logTB - logTA) : 0.0;
@@ -704,32 +723,29 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
       Ds[k] = sc * cp[cl.D + k];
       mx[k] = Ds[k] * m1[k];
     }
-    out = (lane == 1) ? e2 : out;
+    put(1, e2);
     // e1 - e2: one-step-late psi(a) - log b - a/b, or with the exact derivative
     const double e1m2 = (EXACT && ok && fd_ok) ? (cp[cl.psi_a] - log(bb) + dlogJ - e2)
                                                : (cp[cl.psi_a] - log(bb) - aa / bb);
-    out = (lane == 2) ? e1m2 : out;
+    put(2, e1m2);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) out = (lane == 3 + k) ? (ok ? e2 * (c[k] - mx[k]) : 0.0) : out;
+    for (int k = 0; k < Q; ++k) put(3 + k, ok ? e2 * (c[k] - mx[k]) : 0.0);
     int t = 3 + Q;
 #pragma unroll
     for (int a = 0; a < Q; ++a)
 #pragma unroll
       for (int b = a; b < Q; ++b) {
         double exx = c[a] * c[b] - c[a] * mx[b] - mx[a] * c[b] + Ds[a] * m2[a][b] * Ds[b];
-        out = (lane == t) ? (ok ? e2 * exx : 0.0) : out;
+        put(t, ok ? e2 * exx : 0.0);
         ++t;
       }
   }
-  *lane_out = out;
+  lane_out[0] = out;
+  if constexpr (record_width<Q, MOM>() > 64) lane_out[1] = out2;
   return kOk;
 }
 
 
-template <int Q, bool MOM>
-__host__ __device__ constexpr int record_width() {
-  return MOM ? (3 + Q + Q * (Q + 1) / 2) : 1;
-}
 
 // one wave per pair, four pairs per 256-thread block; OCC > 0 asks for at
 // least OCC resident waves per SIMD (the register budget follows); EXACT adds
@@ -752,17 +768,21 @@ void pair_kernel(
   const CompLayout cl(p, Q);
   // per-wave slot for the ordered Cholesky factor (REORDER only)
   __shared__ double cfac[REORDER ? 4 * Q * Q : 1];
-  double out;
+  constexpr int RW = record_width<Q, MOM>();
+  double out[RW > 64 ? 2 : 1];
   const int rc = pair_eval<T, Q, MOM, EXACT, REORDER>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
-      sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, &out,
+      sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
       EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr,
       REORDER ? cfac + wv * Q * Q : nullptr);
   if (rc != kOk) {
     if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
     return;
   }
-  if (lane < record_width<Q, MOM>()) pairbuf[pair * W + lane] = out;
+  if (lane < RW) pairbuf[pair * W + lane] = out[0];
+  if constexpr (RW > 64) {
+    if (lane + 64 < RW) pairbuf[pair * W + 64 + lane] = out[1];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,24 +1095,39 @@ __device__ double nu_root(double cst, double lo, double hi, double v0) {
   return v;
 }
 
+// doubles of M-step work space per component (mstep_body)
+__host__ __device__ inline int mstep_work_doubles(int p, int q) {
+  return 2 * q * q + 2 * p * q + 3 * p * p + 2 * p + 2 * q;
+}
+
 // One problem's M-step on one block, lane i = component i.  Statuses go to
 // status[0..1].  Parameters may alias the old ones: every lane reads its old
-// values before any lane writes.
+// values before any lane writes.  work holds g * mstep_work_doubles(p, q)
+// doubles of device memory (the per-component matrices; in private memory
+// they would need tens of KB of scratch per lane at the largest p and q).
 __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int64_t n, int p,
                                            int q, int g, const double* mu_old,
                                            const double* Delta_old, const double* nu_old,
                                            int nu_fixed, int fix_delta_zero, double nu_lo,
                                            double nu_hi, double* pi, double* mu, double* Sigma,
                                            double* Delta, double* nu, double* __restrict__ pi_tmp,
-                                           int* status) {
+                                           double* __restrict__ work, int* status) {
   const int i = threadIdx.x;
   const StatLayout sl(p, q);
   __shared__ int fail;
   if (i == 0) fail = 0;
   __syncthreads();
-  double s5[kMaxQ * kMaxQ], L5[kMaxQ * kMaxQ], s6[kMaxP * kMaxQ], s7[kMaxP * kMaxP];
-  double Dn[kMaxP * kMaxQ], dmu[kMaxP], s3[kMaxP], s4[kMaxQ];
-  double Sg[kMaxP * kMaxP];
+  double* s5 = work + (size_t)(i < g ? i : 0) * mstep_work_doubles(p, q);
+  double* L5 = s5 + q * q;
+  double* s6 = L5 + q * q;
+  double* s7 = s6 + p * q;
+  double* Dn = s7 + p * p;
+  double* dmu = Dn + p * q;
+  double* s3 = dmu + p;
+  double* s4 = s3 + p;
+  double* Sg = s4 + q;
+  double* Lc = Sg + p * p;
+  double* tmp = Lc + p * p;  // q doubles
   double s1 = 0.0, vnew = 0.0;
   bool ok = true;
   if (i < g) {
@@ -1137,7 +1172,6 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
           fail = 1;
         } else {
           for (int a = 0; a < p; ++a) {
-            double tmp[kMaxQ];
             for (int k = 0; k < q; ++k) {
               double t = s6[a * q + k];
               for (int l = 0; l < k; ++l) t -= L5[k * q + l] * tmp[l];
@@ -1170,7 +1204,6 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
           Sg[a * p + b] = t;
           Sg[b * p + a] = t;
         }
-      double Lc[kMaxP * kMaxP];
       for (int x = 0; x < p * p; ++x) Lc[x] = Sg[x];
       if (!chol_small(Lc, p)) {
         ok = false;
@@ -1202,9 +1235,10 @@ __global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p,
                              const double* mu_old, const double* Delta_old, const double* nu_old,
                              int nu_fixed, int fix_delta_zero, double nu_lo, double nu_hi,
                              double* pi, double* mu, double* Sigma, double* Delta, double* nu,
-                             double* __restrict__ pi_tmp, int* status) {
+                             double* __restrict__ pi_tmp, double* __restrict__ work,
+                             int* status) {
   mstep_body(stats, n, p, q, g, mu_old, Delta_old, nu_old, nu_fixed, fix_delta_zero, nu_lo, nu_hi,
-             pi, mu, Sigma, Delta, nu, pi_tmp, status);
+             pi, mu, Sigma, Delta, nu, pi_tmp, work, status);
 }
 
 // ---------------------------------------------------------------------------

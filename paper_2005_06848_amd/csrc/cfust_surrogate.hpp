@@ -20,7 +20,7 @@ struct SurrRange {
   double h_lo, h_hi, dof_lo, dof_hi, r_max, eig_min;
 };
 
-// smallest eigenvalue of a symmetric m x m matrix (m <= kMaxQ) by cyclic
+// smallest eigenvalue of a symmetric m x m matrix (m <= kMaxQFull) by cyclic
 // Jacobi rotations
 __device__ double min_eig_sym(double* a, int m) {
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -70,7 +70,7 @@ __global__ void surr_comp_kernel(int p, int q, int g, const double* __restrict__
   const int NR = q * (q - 1) / 2;
   const float* mx = stdv;
   const float* sx = stdv + kMlpPad;
-  double R[kMaxQ * kMaxQ];
+  double R[kMaxQFull * kMaxQFull];
   bool in = true;
   int t = 0;
   for (int k = 0; k < q; ++k)
@@ -307,6 +307,7 @@ __global__ __launch_bounds__(256) void pair_list_kernel(
       if (lane == 0) set_status(status, kENonFinite, -1);
       continue;
     }
+    static_assert(record_width<Q, true>() <= 64, "one record entry per lane");
     if (lane < record_width<Q, true>()) pairbuf[pair * W + lane] = out;
   }
 }

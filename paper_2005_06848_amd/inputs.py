@@ -281,6 +281,7 @@ CONFIG_DOC = {
     3: "FP32 precision form: n=200000 p=6 q=6 g=4 nu~U(3,10) N=8192",
     4: "batched: 64 starts, n~U{5000..50000} g~U{2..6} p=q=5 N=4096",
     5: "surrogate use: n=1000000 p=6 q=6 g=4 nu~U(3,10)",
+    6: "high-q stress: n=202 p=q=11 g=2 nu~U(4,12) N=8192, whole fit",
 }
 
 
@@ -333,6 +334,14 @@ def config(k: int, n: int | None = None, seed: int | None = None, kmeans_restart
         true = _true_params_basic(rng, p, q, g, rng.uniform(3, 10, size=g), 2.0, np.full(g, 0.25))
         n = 1000000 if n is None else n
         iters = 1
+    elif k == 6:
+        # the shape of the paper's data set (202 observations of 11 variables,
+        # two groups of 102 and 100) with q = p: a stress case for large q
+        p, q, g, N = 11, 11, 2, 8192
+        true = _true_params_basic(rng, p, q, g, rng.uniform(4, 12, size=g), 1.0,
+                                  [102 / 202, 100 / 202])
+        n = 202 if n is None else n
+        iters = 1000
     else:
         raise ValueError("workload 4 is built by batched_problems()")
     y, z = sample_cfust(rng, n, **true)

@@ -53,7 +53,8 @@ def test_workspace_size_and_limits(libpath):
     from paper_2005_06848_amd import native
     assert native.workspace_size(20000, 4, 4, 3, 4096) > 20000 * 3 * 8 * 17
     with pytest.raises(native.CfustError):
-        native.workspace_size(10, 2, 9, 2, 64)  # q above the kernels' limit
+        native.workspace_size(10, 2, 13, 2, 64)  # q above the kernels' limit
+    assert native.workspace_size(202, 11, 11, 2, 8192) > 202 * 2 * 8 * (3 + 11 + 66)
     with pytest.raises(native.CfustError):
         native.workspace_size(10, 33, 2, 2, 64)  # p above the limit
     with pytest.raises(native.CfustError):

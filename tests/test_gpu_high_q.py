@@ -1,0 +1,141 @@
+"""q above 8 (up to 12) on the GPU against the FP64 oracle.
+
+At q >= 10 a pair's record (3 + q + q(q+1)/2 doubles) is wider than a
+wave, so lanes carry a second entry; these cases check every entry.  Bar as
+in tests/parity.py: FP64 1e-10 per quantity; FP32 1e-4 on moments and
+statistics, 1e-7 on the log-likelihood; EM traces and parameters 1e-9.
+Workload 6 is the high-q stress case (n = 202, p = q = 11, g = 2, N = 8192).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_06848_amd import native
+    native.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def T(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def P(par, dev):
+    return {k: T(v, dev) for k, v in par.items() if k in ("pi", "mu", "Sigma", "Delta", "nu")}
+
+
+def gpu_estep(dev, y, par, u, **opt):
+    from paper_2005_06848_amd import native
+    print(f"[gpu] high-q estep n={y.shape[0]} p={y.shape[1]} q={par['Delta'].shape[2]} "
+          f"g={len(par['pi'])} N={u.shape[0]} {opt}", flush=True)
+    g = native.cfust_estep(T(y, dev), P(par, dev), T(u, dev), **opt)
+    out = {k: v.cpu().numpy() for k, v in g.items()}
+    out["loglik"] = float(out["loglik"][0])
+    return out
+
+
+@pytest.mark.parametrize("shape", [(21, 9, 9, 2, 129), (15, 6, 10, 3, 100), (19, 11, 11, 2, 257),
+                                   (13, 12, 12, 2, 65), (7, 3, 12, 1, 64)])
+def test_high_q_estep_parity(dev, orc, shape):
+    from paper_2005_06848_amd import inputs
+    import parity
+    n, p, q, g, N = shape
+    c = inputs.random_case(131 + n, n, p, q, g, N)
+    ref = orc.estep(c["y"], c["params"], c["u"])
+    got = gpu_estep(dev, c["y"], c["params"], c["u"])
+    err = parity.estep_errors(got, ref, p, q)
+    bad = {k: v for k, v in err.items() if not v <= TOL}
+    assert not bad, err
+    # the entries past the first 64 of each record are the last e4 entries
+    assert np.max(np.abs(got["e4"][..., q - 1, q - 1])) > 0
+
+
+def test_high_q_loglik_and_fp32(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.random_case(151, 40, 11, 11, 2, 1024)
+    y, par, u = c["y"], c["params"], c["u"]
+    ll_ref, lf_ref = orc.loglik(y, par, u, want_logf=True)
+    print("[gpu] high-q loglik n=40 q=11", flush=True)
+    ll, lf = native.cfust_loglik(T(y, dev), P(par, dev), T(u, dev), want_logf=True)
+    assert abs(float(ll) - ll_ref) <= TOL * abs(ll_ref)
+    assert np.max(np.abs(lf.cpu().numpy() - lf_ref)) <= TOL
+    ref = orc.estep(y, par, u)
+    got = gpu_estep(dev, y, par, u, precision="fp32")
+    err = parity.estep_errors(got, ref, 11, 11)
+    assert err["e3"] < 1e-4 and err["e4"] < 1e-4 and err["stats"] < 1e-4, err
+    assert err["loglik"] < 1e-7, err
+
+
+def test_high_q_em_fit_matches_oracle(dev, orc):
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.config(6, n=60)
+    u = c["u"][:1024]
+    ref = orc.em_fit(c["y"], c["init"], u, max_iter=4, tol=0.0)
+    print("[gpu] high-q em_fit workload 6 n=60 N=1024", flush=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(u, dev), max_iter=4, tol=0.0)
+    np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-9)
+    err = parity.params_rel_err({k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")},
+                                ref)
+    assert max(err.values()) < 1e-9, err
+
+
+def test_workload6_full_size_sampled_rows(dev, orc):
+    """Workload 6 at full size (N = 8192) in one launch; 24 sampled
+    observations against the oracle."""
+    from paper_2005_06848_amd import inputs
+    import parity
+    c = inputs.config(6)
+    y, par, u = c["y"], c["init"], c["u"]
+    got = gpu_estep(dev, y, par, u)
+    rows = np.random.default_rng(6).choice(len(y), 24, replace=False)
+    ref = orc.estep(y[rows], par, u)
+    sub = {k: got[k][rows] for k in ("tau", "logf", "e1", "e2", "e3", "e4")}
+    sub["stats"], sub["loglik"] = ref["stats"], ref["loglik"]
+    err = parity.estep_errors(sub, ref, 11, 11)
+    assert max(err.values()) <= TOL, err
+
+
+def test_workload6_whole_fit_increases_loglik(dev):
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(6)
+    print("[gpu] high-q whole fit workload 6 (max 200 iterations)", flush=True)
+    fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(c["u"], dev), max_iter=200,
+                              tol=1e-6)
+    tr = np.array(fit["trace"])
+    print(f"  iterations {fit['n_iter']}, l {tr[0]:.4f} -> {tr[-1]:.4f}")
+    assert tr[-1] > tr[0]
+    assert np.all(np.isfinite(tr))
+
+
+def test_high_q_forms_rejected(dev):
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.random_case(161, 10, 11, 11, 2, 64)
+    y, par, u = T(c["y"], dev), P(c["params"], dev), T(c["u"], dev)
+    for opt in ({"nu_mode": "exact"}, {"reorder": True}):
+        with pytest.raises(native.CfustError):
+            native.cfust_estep(y, par, u, **opt)
+    with pytest.raises(native.CfustError):
+        native.cfust_em_fit_batched(y, [10], [2], par, u, max_iter=2)
+    with pytest.raises(native.CfustError):
+        native.cfust_em_fit_multistart(y, [par, par], u, burn_in=1, max_iter=2)
+    with pytest.raises(native.CfustError):
+        native.cfust_ghk_batch(T(np.zeros((2, 11)), dev), T(np.broadcast_to(np.eye(11), (2, 11, 11)), dev),
+                               T(np.full(2, 8.0), dev), u)
