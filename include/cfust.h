@@ -105,6 +105,14 @@ typedef struct cfust_opts {
                              and cfust_em_fit_multistart after its burn-in; EINVAL with a
                              surrogate, in cfust_em_fit_batched and cfust_ghk_batch.
                              0 (default): natural order */
+  int surrogate_check;    /* with a surrogate: m > 0 samples the observations
+                             j_i = floor((2i+1) n / (2m)), i < m (the same ones every call),
+                             evaluates their pairs with the GHK kernel as well, and corrects
+                             the partial sums and the log-likelihood by (n/m) times the
+                             sample's GHK-minus-network totals (a difference estimator;
+                             m >= n gives the GHK E-step).  Per-pair outputs (tau, logf,
+                             e1..e4) stay the network's.  The workspace then needs
+                             cfust_workspace_size_opts bytes.  0 (default): no check */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4
@@ -127,6 +135,11 @@ void cfust_default_opts(cfust_opts* opts);
 
 /* Number of statistics per component, S above. */
 int cfust_stats_size(int p, int q);
+
+/* Bytes of workspace for this problem size under these options (precision
+ * and the surrogate check's sample); opts may be NULL (the defaults). */
+int cfust_workspace_size_opts(int64_t n, int p, int q, int g, int n_qmc, const cfust_opts* opts,
+                              size_t* bytes);
 
 /* sizeof(cfust_opts) as compiled into the library (bindings check it). */
 size_t cfust_opts_size(void);

@@ -70,11 +70,24 @@ struct Plan {
   size_t o_sAp, o_sAm;
   size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp, o_mwork,
       o_ll, o_stats, total;
+  // surrogate check (difference estimator over m sampled observations)
+  int64_t check_m = 0;
+  int64_t chk_per_block = 0;
+  int chk_nb = 0;
+  size_t o_chk_y = 0, o_chk_rnet = 0, o_chk_rghk = 0, o_chk_part = 0, o_chk_pll = 0,
+         o_chk_stats = 0;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Plan make_plan(int64_t n, int p, int q, int g, int N, int prec) {
+// observations per statistics block for n observations (a multiple of tile)
+int64_t stats_per_block(int64_t n, int tile) {
+  int64_t per = (n + 1023) / 1024;
+  if (per < tile) per = tile;
+  return ((per + tile - 1) / tile) * tile;
+}
+
+Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m = 0) {
   Plan pl;
   pl.n = n;
   pl.p = p;
@@ -90,9 +103,7 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec) {
   size_t per_obs = (size_t)(g * pl.W + g + p + 1) * sizeof(double);
   int tile = (int)((48 * 1024) / per_obs);
   pl.tile = tile < 1 ? 1 : (tile > 16 ? 16 : tile);
-  int64_t per = (n + 1023) / 1024;
-  if (per < pl.tile) per = pl.tile;
-  per = ((per + pl.tile - 1) / pl.tile) * pl.tile;
+  const int64_t per = stats_per_block(n, pl.tile);
   pl.per_block = per;
   pl.nb = (int)((n + per - 1) / per);
   if (pl.nb < 1) pl.nb = 1;
@@ -132,8 +143,43 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec) {
   off = align_up(off + sizeof(double));
   pl.o_stats = off;
   off = align_up(off + (size_t)pl.GS * sizeof(double));
+  if (check_m > 0) {
+    const int64_t m = check_m < n ? check_m : n;
+    pl.check_m = m;
+    pl.chk_per_block = stats_per_block(m, pl.tile);
+    pl.chk_nb = (int)((m + pl.chk_per_block - 1) / pl.chk_per_block);
+    if (pl.chk_nb < 1) pl.chk_nb = 1;
+    const size_t rec = (size_t)(m > 0 ? m : 1) * g * pl.W * sizeof(double);
+    pl.o_chk_y = off;
+    off = align_up(off + (size_t)(m > 0 ? m : 1) * p * sizeof(double));
+    pl.o_chk_rnet = off;
+    off = align_up(off + rec);
+    pl.o_chk_rghk = off;
+    off = align_up(off + rec);
+    pl.o_chk_part = off;
+    off = align_up(off + (size_t)pl.chk_nb * pl.GS * sizeof(double));
+    pl.o_chk_pll = off;
+    off = align_up(off + (size_t)pl.chk_nb * sizeof(double));
+    pl.o_chk_stats = off;  // network then GHK: GS statistics + log-likelihood each
+    off = align_up(off + (size_t)2 * (pl.GS + 1) * sizeof(double));
+  }
   pl.total = off;
   return pl;
+}
+
+// the plan of the m sampled observations of the surrogate check: shares the
+// per-component blocks, chi tables and points; records in `rec`
+Plan check_plan(const Plan& pl, size_t rec) {
+  Plan ps = pl;
+  ps.n = pl.check_m;
+  ps.per_block = pl.chk_per_block;
+  ps.nb = pl.chk_nb;
+  ps.o_pair = rec;
+  ps.o_part = pl.o_chk_part;
+  ps.o_pll = pl.o_chk_pll;
+  ps.exact = false;
+  ps.reorder = false;
+  return ps;
 }
 
 struct Ws {
@@ -481,6 +527,30 @@ int run_estep(Ws& ws, const Plan& pl, const double* y, const double* pi, const d
   prof_begin(ws, 2);
   launch_stats(ws, pl, y, mu, moments, stats, loglik, out, logf_only);
   prof_end(ws, 2);
+  if (ws.surr && pl.check_m > 0) {
+    // difference estimator: totals += (n/m) (GHK - network) over the m
+    // sampled observations, whose network records are copied out first
+    const int64_t m = pl.check_m;
+    double* ysub = ws.at<double>(pl.o_chk_y);
+    double* cst = ws.at<double>(pl.o_chk_stats);
+    const int64_t cells = m * (int64_t)(pl.p > pl.g * pl.W ? pl.p : pl.g * pl.W);
+    check_gather_kernel<<<(unsigned)((cells + 255) / 256), 256, 0, ws.st>>>(
+        y, pl.n, pl.p, ws.at<double>(pl.o_pair), pl.g * pl.W, m, ysub,
+        ws.at<double>(pl.o_chk_rnet));
+    const Plan pg = check_plan(pl, pl.o_chk_rghk);
+    if (moments)
+      launch_pairs<T, true>(ws, pg, ysub, mu);
+    else
+      launch_pairs<T, false>(ws, pg, ysub, mu);
+    launch_stats(ws, pg, ysub, mu, moments, moments ? cst + pl.GS + 1 : nullptr,
+                 cst + 2 * pl.GS + 1, nullptr, nullptr);
+    const Plan pn = check_plan(pl, pl.o_chk_rnet);
+    launch_stats(ws, pn, ysub, mu, moments, moments ? cst : nullptr, cst + pl.GS, nullptr,
+                 nullptr);
+    check_combine_kernel<<<(pl.GS + 256) / 256, 256, 0, ws.st>>>(
+        cst, pl.GS, moments ? 1 : 0, (double)pl.n / (double)m, moments ? stats : nullptr, loglik,
+        ws.at<int>(pl.o_status));
+  }
   return CFUST_OK;
 }
 
@@ -512,6 +582,11 @@ int check_surrogate(const cfust_opts* o, int q) {
   return (s->q == q && s->have_std) ? CFUST_OK : CFUST_EINVAL;
 }
 
+// sampled observations of the surrogate check (0: none)
+int64_t check_of(const cfust_opts* o) {
+  return (o && o->surrogate && o->surrogate_check > 0) ? (int64_t)o->surrogate_check : 0;
+}
+
 // forms that exist only up to kMaxQFull
 int check_q_forms(const cfust_opts* o, int q) {
   if (!o || q <= kMaxQFull) return CFUST_OK;
@@ -527,6 +602,7 @@ int check_opts(const cfust_opts* o) {
     return CFUST_EINVAL;
   if (!(o->nu_lo > 0.0) || !(o->nu_hi >= o->nu_lo)) return CFUST_EINVAL;
   if (o->reorder != 0 && o->reorder != 1) return CFUST_EINVAL;
+  if (o->surrogate_check < 0) return CFUST_EINVAL;
   return CFUST_OK;
 }
 
@@ -560,6 +636,16 @@ int cfust_workspace_size(int64_t n, int p, int q, int g, int n_qmc, int precisio
   return CFUST_OK;
 }
 
+int cfust_workspace_size_opts(int64_t n, int p, int q, int g, int n_qmc, const cfust_opts* o,
+                              size_t* bytes) {
+  if (!bytes) return CFUST_EINVAL;
+  int rc = check_dims(n, p, q, g, n_qmc);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  *bytes = make_plan(n, p, q, g, n_qmc, o ? o->precision : CFUST_FP64, check_of(o)).total;
+  return CFUST_OK;
+}
+
 double cfust_aitken_linf(double l0, double l1, double l2) {
   double den = l1 - l0;
   double a = den != 0.0 ? (l2 - l1) / den : 0.0;
@@ -579,7 +665,7 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
   if ((n > 0 && !y) || !pi || !mu || !Sigma || !Delta || !nu || !u || !out->stats || !out->loglik)
     return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
-  Plan pl = make_plan(n, p, q, g, n_qmc, prec);
+  Plan pl = make_plan(n, p, q, g, n_qmc, prec, check_of(o));
   pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
   pl.reorder = o && o->reorder;
   Ws ws;
@@ -607,7 +693,7 @@ int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* 
   if ((rc = check_q_forms(o, q))) return rc;
   if ((n > 0 && !y) || !pi || !mu || !Sigma || !Delta || !nu || !u || !loglik) return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
-  Plan pl = make_plan(n, p, q, g, n_qmc, prec);
+  Plan pl = make_plan(n, p, q, g, n_qmc, prec, check_of(o));
   pl.reorder = o && o->reorder;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
@@ -662,7 +748,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   cfust_default_opts(&def);
   if (!o) o = &def;
   if (o->max_iter < 0) return CFUST_EINVAL;
-  Plan pl = make_plan(n, p, q, g, n_qmc, o->precision);
+  Plan pl = make_plan(n, p, q, g, n_qmc, o->precision, check_of(o));
   pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
   pl.reorder = o->reorder != 0;
   Ws ws;

@@ -403,4 +403,40 @@ __global__ void pair_features_kernel(const double* __restrict__ y, int64_t n, in
   ob[F - 1] = v + p + 2.0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Surrogate check: a difference estimator of the E-step totals.  The m
+// sampled observations are j_i = floor((2i + 1) n / (2m)), i < m (the same
+// every call, so the corrected E-step is a smooth function of the
+// parameters); the totals T (partial sums s1..s8 and the log-likelihood) of
+// the network E-step are corrected by (n/m) (T_GHK - T_net) over the sample.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t check_obs(int64_t i, int64_t n, int64_t m) {
+  return (2 * i + 1) * n / (2 * m);
+}
+
+// ysub[i] = y[j_i], rnet[i] = the g records of observation j_i
+__global__ void check_gather_kernel(const double* __restrict__ y, int64_t n, int p,
+                                    const double* __restrict__ pairbuf, int gW, int64_t m,
+                                    double* __restrict__ ysub, double* __restrict__ rnet) {
+  const int C = p > gW ? p : gW;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * C) return;
+  const int64_t i = t / C;
+  const int c = (int)(t - i * C);
+  const int64_t j = check_obs(i, n, m);
+  if (c < p) ysub[i * p + c] = y[j * p + c];
+  if (c < gW) rnet[i * gW + c] = pairbuf[j * gW + c];
+}
+
+// cst = net statistics [GS] | net l | GHK statistics [GS] | GHK l
+__global__ void check_combine_kernel(const double* __restrict__ cst, int GS, int with_stats,
+                                     double scale, double* __restrict__ stats,
+                                     double* __restrict__ loglik, const int* __restrict__ status) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (status[0] != kOk) return;
+  if (with_stats && e < GS) stats[e] += scale * (cst[GS + 1 + e] - cst[e]);
+  if (e == GS) loglik[0] += scale * (cst[2 * GS + 1] - cst[GS]);
+}
+
 }  // namespace cfust

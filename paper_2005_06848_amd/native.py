@@ -46,6 +46,7 @@ class Opts(ctypes.Structure):
         ("adapt_samples", ctypes.c_int),
         ("adapt_epochs", ctypes.c_int),
         ("reorder", ctypes.c_int),
+        ("surrogate_check", ctypes.c_int),
     ]
 
 
@@ -80,6 +81,9 @@ def _lib():
         L.cfust_stats_size.restype = i
         L.cfust_workspace_size.argtypes = [i64, i, i, i, i, i, ctypes.POINTER(sz)]
         L.cfust_workspace_size.restype = i
+        L.cfust_workspace_size_opts.argtypes = [i64, i, i, i, i, ctypes.POINTER(Opts),
+                                                ctypes.POINTER(sz)]
+        L.cfust_workspace_size_opts.restype = i
         L.cfust_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, ctypes.POINTER(Opts),
                                   ctypes.POINTER(EstepOut)]
         L.cfust_estep.restype = i
@@ -177,7 +181,8 @@ def _ptr(t):
 
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
               nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0,
-              surrogate=None, adapt_samples=0, adapt_epochs=0, reorder=False):
+              surrogate=None, adapt_samples=0, adapt_epochs=0, reorder=False,
+              surrogate_check=0):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -203,11 +208,22 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
     o.adapt_samples = int(adapt_samples)
     o.adapt_epochs = int(adapt_epochs)
     o.reorder = int(bool(reorder))
+    o.surrogate_check = int(surrogate_check)
     return o
 
 
 def stats_size(p, q):
     return _lib().cfust_stats_size(p, q)
+
+
+def workspace_size_opts(n, p, q, g, n_qmc, **opt):
+    """Workspace bytes under these options (precision, surrogate check)."""
+    b = ctypes.c_size_t(0)
+    o = make_opts(**opt)
+    rc = _lib().cfust_workspace_size_opts(n, p, q, g, n_qmc, ctypes.byref(o), ctypes.byref(b))
+    if rc:
+        raise CfustError(rc, "cfust_workspace_size_opts")
+    return b.value
 
 
 def workspace_size(n, p, q, g, n_qmc, precision="fp64"):

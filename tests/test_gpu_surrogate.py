@@ -385,3 +385,80 @@ def test_fused_inference_matches_reference(dev):
     err = np.abs(out - ref) / scale
     print(f"  median {np.median(err):.2e} max {err.max():.2e}")
     assert np.median(err) < 1e-5 and err.max() < 2e-3
+
+
+def _estep_totals(dev, y, par, u, **opt):
+    from paper_2005_06848_amd import native
+    r = native.cfust_estep(y, par, u, want=(), **opt)
+    return r["stats"].cpu().numpy(), r["loglik"].item()
+
+
+def _rel_errors(st, ll, st_ref, ll_ref):
+    per = np.abs(st - st_ref).max(1) / np.abs(st_ref).max(1)
+    return float(per.max()), abs(ll / ll_ref - 1)
+
+
+def test_surrogate_check_with_every_observation_is_the_ghk_estep(dev):
+    """With m >= n the sample is every observation and the difference
+    estimator returns the GHK totals (up to the rounding of the correction)."""
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(5, n=3000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    st_ref, ll_ref = _estep_totals(dev, y, par, u)
+    print("[gpu] surrogate check m = n = 3000", flush=True)
+    for m in (3000, 10 ** 6):
+        st, ll = _estep_totals(dev, y, par, u, surrogate=_shipped(), surrogate_check=m)
+        e_st, e_ll = _rel_errors(st, ll, st_ref, ll_ref)
+        assert e_st < 1e-12 and e_ll < 1e-14, (m, e_st, e_ll)
+
+
+def test_surrogate_check_meets_the_accuracy_targets(dev):
+    """One adaptation (16384 sampled pairs, 20 epochs) and a check over
+    m = 65536 sampled observations (n = 200000, 800000 pairs) against the
+    FP64 GHK E-step: partial sums within 1e-3 (normwise per component) and
+    log-likelihood within 1e-5.  The check's noise is the spread of the
+    per-observation network error over sqrt(m) (about 2e-2 in log f, so m
+    near 65536 for 1e-5 in l).  The shipped network alone, with the check
+    alone and adapted alone are printed for comparison."""
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(5, n=200000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    print("[gpu] surrogate check n=200000 m=65536", flush=True)
+    st_ref, ll_ref = _estep_totals(dev, y, par, u)
+    net = _shipped()
+    e = {"shipped": _rel_errors(*_estep_totals(dev, y, par, u, surrogate=net), st_ref, ll_ref),
+         "checked": _rel_errors(*_estep_totals(dev, y, par, u, surrogate=net,
+                                               surrogate_check=65536), st_ref, ll_ref)}
+    net.adapt(y, par, u, samples=16384, epochs=20)
+    e["adapted"] = _rel_errors(*_estep_totals(dev, y, par, u, surrogate=net), st_ref, ll_ref)
+    e["adapted+checked"] = _rel_errors(*_estep_totals(dev, y, par, u, surrogate=net,
+                                                      surrogate_check=65536), st_ref, ll_ref)
+    for k, v in e.items():
+        print(f"  {k}: stats {v[0]:.2e} loglik {v[1]:.2e}")
+    assert e["adapted+checked"][0] < 1e-3 and e["adapted+checked"][1] < 1e-5
+    assert e["checked"][0] < e["shipped"][0] and e["checked"][1] < e["shipped"][1]
+
+
+def test_surrogate_check_in_em(dev):
+    """Two-phase EM with the adapted, checked surrogate (n = 20000,
+    adaptation of 8192 pairs before each surrogate E-step, m = 16384): the
+    surrogate phase stops by Aitken's rule, and its last log-likelihood and
+    the GHK log-likelihood at the same parameters agree within 1e-5.  (The
+    shipped network alone drifts from its training distribution along the
+    fit; the check then has more to correct.)"""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=20000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    print("[gpu] checked two-phase EM n=20000 m=16384", flush=True)
+    net = _shipped()
+    rs = native.cfust_em_fit(y, par, u, max_iter=150, tol=0.5, surrogate=net,
+                             adapt_samples=8192, adapt_epochs=10, surrogate_check=16384)
+    sw = net.em_switch()
+    ts = np.array(rs["trace"])
+    print(f"  {rs['n_iter']} its, switch at {sw}: surrogate l {ts[sw - 1]:.6f}, "
+          f"GHK l {ts[sw]:.6f}, final {ts[-1]:.6f}")
+    assert sw > 0
+    assert abs(ts[sw - 1] / ts[sw] - 1) < 1e-5
