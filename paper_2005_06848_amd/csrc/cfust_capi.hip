@@ -70,6 +70,9 @@ struct Plan {
   size_t o_sAp, o_sAm;
   size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp, o_mwork,
       o_ll, o_stats, total;
+  // waves per pair (pair_part_kernel + pair_finish_kernel when > 1)
+  int split = 1;
+  size_t o_parts = 0;
   // surrogate check (difference estimator over m sampled observations)
   int64_t check_m = 0;
   int64_t chk_per_block = 0;
@@ -85,6 +88,22 @@ int64_t stats_per_block(int64_t n, int tile) {
   int64_t per = (n + 1023) / 1024;
   if (per < tile) per = tile;
   return ((per + tile - 1) / tile) * tile;
+}
+
+// A launch of fewer than kSplitWaves pairs spreads each pair's points over
+// up to kSplitMax waves (FP64 form; each wave keeps at least 4 points per
+// lane).  The FP32 form keeps one wave per pair, so that the single-problem
+// path sums in the same order as the batched form (which serves many small
+// problems).
+constexpr int64_t kSplitWaves = 4096;
+constexpr int kSplitMax = 16;
+
+int split_of(int64_t pairs, int N, int prec) {
+  if (prec != CFUST_FP64 || pairs < 1 || pairs >= kSplitWaves) return 1;
+  int64_t K = (kSplitWaves + pairs - 1) / pairs;
+  K = std::min<int64_t>(K, kSplitMax);
+  K = std::min<int64_t>(K, N / 256);
+  return K >= 2 ? (int)K : 1;
 }
 
 Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m = 0) {
@@ -131,6 +150,13 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m 
   off = align_up(off + (size_t)g * N * es);
   pl.o_pair = off;
   off = align_up(off + (size_t)(n > 0 ? n : 1) * g * pl.W * sizeof(double));
+  pl.split = split_of(n * g, N, prec);
+  if (pl.split > 1) {
+    // widest record: B with moments plus the two exact-nu integrals
+    const size_t pw = 2 + 2 + q + (size_t)q * (q + 1) / 2 + 4;
+    pl.o_parts = off;
+    off = align_up(off + (size_t)n * g * pl.split * pw * sizeof(double));
+  }
   pl.o_part = off;
   off = align_up(off + (size_t)pl.nb * pl.GS * sizeof(double));
   pl.o_pll = off;
@@ -179,6 +205,7 @@ Plan check_plan(const Plan& pl, size_t rec) {
   ps.o_pll = pl.o_chk_pll;
   ps.exact = false;
   ps.reorder = false;
+  ps.split = 1;
   return ps;
 }
 
@@ -316,6 +343,28 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   // keep the default occupancy (the ordering adds registers).  Above
   // kMaxQFull only the natural-order kernel exists (the entry points reject
   // the other forms there).
+  if constexpr (sizeof(T) == 8) {
+    if (pl.split > 1 && !pl.reorder) {
+      const int K = pl.split;
+      double* parts = ws.at<double>(pl.o_parts);
+      const unsigned pblocks = (unsigned)((pairs * K + 3) / 4);
+      if constexpr (MOM && Q <= kMaxQFull) {
+        if (pl.exact) {
+          pair_part_kernel<T, Q, MOM, OCC, true><<<pblocks, 256, 0, ws.st>>>(
+              y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status,
+              ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
+          pair_finish_kernel<T, Q, MOM, true><<<blocks, 256, 0, ws.st>>>(
+              y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
+          return;
+        }
+      }
+      pair_part_kernel<T, Q, MOM, OCC><<<pblocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status);
+      pair_finish_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
+      return;
+    }
+  }
   if constexpr (Q > kMaxQFull) {
     pair_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
         y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);

@@ -330,14 +330,27 @@ __device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
 // E[V | V <= h] and E[V V^T | V <= h], otherwise the last draw is skipped.
 // Every lane returns log P(V <= h) and the moments.
 // ---------------------------------------------------------------------------
+// Wave-uniform sums of one GHK integral over a subset of the points, scaled
+// by 2^-R: S0 = sum w, S1 = sum w ehat, S2 = sum w ehat ehat^T (upper
+// triangle).  A subset's R is the largest exponent of its lanes; an empty
+// subset has R at the exponent floor and zero sums.
+template <int Q, bool MOM>
+struct GhkPart {
+  static constexpr int NT = Q * (Q + 1) / 2;
+  double R, S0;
+  double S1[MOM ? Q : 1];
+  double S2[MOM ? NT : 1];
+};
+
+// Sums of the points k0 + lane, k0 + lane + kstep, ... below N (lane t of
+// the wave; kstep a multiple of 64).  Every lane returns the wave's sums.
 template <typename T, int Q, bool MOM>
-__device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][Q],
-                                             const double* __restrict__ C,
-                                             const T* __restrict__ s_tab,
-                                             const T* __restrict__ rs_tab,
-                                             const T* __restrict__ uT, const T* __restrict__ ubT,
-                                             int N, int lane, double* logT, double (&m1)[Q],
-                                             double (&m2)[Q][Q]) {
+__device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
+                                         const T* __restrict__ s_tab,
+                                         const T* __restrict__ rs_tab,
+                                         const T* __restrict__ uT, const T* __restrict__ ubT,
+                                         int N, int k0, int kstep, int lane,
+                                         GhkPart<Q, MOM>& part) {
   constexpr int NT = Q * (Q + 1) / 2;
   using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
   Acc<T> b0, b1[MOM ? Q : 1], b2[MOM ? NT : 1];
@@ -350,7 +363,7 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
   }
   E ref = exp_floor<E>();
 #pragma unroll 1
-  for (int k = lane; k < N; k += 64) {
+  for (int k = k0 + lane; k < N; k += kstep) {
     const T s = s_tab[k];
     T eps[Q];
     T prod = T(1);
@@ -398,29 +411,42 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
   // wave reduction with exponent alignment
   E R = wave_max(ref);
   double sc = ldexp(1.0, shift_of(ref - R));
-  double S0 = wave_sum(b0.value() * sc);
-  *logT = log(S0) + R * kLn2 - log((double)N);
+  part.R = (double)R;
+  part.S0 = wave_sum(b0.value() * sc);
   if (MOM) {
-    double S1[Q], S2[Q][Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) S1[m] = wave_sum(b1[m].value() * sc);
+    for (int m = 0; m < Q; ++m) part.S1[m] = wave_sum(b1[m].value() * sc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) part.S2[t] = wave_sum(b2[t].value() * sc);
+  }
+}
+
+// log P(V <= h) and, with MOM, E[V | V <= h] = C S1/S0 and
+// E[V V^T | V <= h] = C (S2/S0) C^T from the sums of all N points.
+template <int Q, bool MOM>
+__device__ __forceinline__ void ghk_finish(const GhkPart<Q, MOM>& part,
+                                           const double* __restrict__ C, int N, double* logT,
+                                           double (&m1)[Q], double (&m2)[Q][Q]) {
+  const double S0 = part.S0;
+  *logT = log(S0) + part.R * kLn2 - log((double)N);
+  if (MOM) {
+    double S2[Q][Q];
     int t = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a)
 #pragma unroll
       for (int b = a; b < Q; ++b) {
-        double s2 = wave_sum(b2[t++].value() * sc);
-        S2[a][b] = s2;
-        S2[b][a] = s2;
+        S2[a][b] = part.S2[t];
+        S2[b][a] = part.S2[t];
+        ++t;
       }
-    // E[V] = C S1/S0, E[V V^T] = C (S2/S0) C^T
     const double inv0 = 1.0 / S0;
     double tmp[Q][Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       double t1 = 0.0;
 #pragma unroll
-      for (int l = 0; l <= a; ++l) t1 += C[a * Q + l] * S1[l];
+      for (int l = 0; l <= a; ++l) t1 += C[a * Q + l] * part.S1[l];
       m1[a] = t1 * inv0;
 #pragma unroll
       for (int b = 0; b < Q; ++b) {
@@ -440,6 +466,39 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
         m2[a][b] = t2;
       }
   }
+}
+
+// Sums of several subsets combined in a fixed order (their references
+// aligned to the largest).
+template <int Q, bool MOM>
+__device__ __forceinline__ void ghk_combine(GhkPart<Q, MOM>& acc, const GhkPart<Q, MOM>& x) {
+  constexpr int NT = Q * (Q + 1) / 2;
+  const double R = fmax(acc.R, x.R);
+  const double fa = ldexp(1.0, shift_of(acc.R - R));
+  const double fx = ldexp(1.0, shift_of(x.R - R));
+  acc.R = R;
+  acc.S0 = acc.S0 * fa + x.S0 * fx;
+  if (MOM) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) acc.S1[m] = acc.S1[m] * fa + x.S1[m] * fx;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc.S2[t] = acc.S2[t] * fa + x.S2[t] * fx;
+  }
+}
+
+// One GHK integral on one wave over all N points (section 2: the q-variate
+// t CDF of eq. (2) and, with MOM, the moments of the truncated t).
+template <typename T, int Q, bool MOM>
+__device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][Q],
+                                             const double* __restrict__ C,
+                                             const T* __restrict__ s_tab,
+                                             const T* __restrict__ rs_tab,
+                                             const T* __restrict__ uT, const T* __restrict__ ubT,
+                                             int N, int lane, double* logT, double (&m1)[Q],
+                                             double (&m2)[Q][Q]) {
+  GhkPart<Q, MOM> part;
+  ghk_sums<T, Q, MOM>(ht, Ct, s_tab, rs_tab, uT, ubT, N, 0, 64, lane, part);
+  ghk_finish<Q, MOM>(part, C, N, logT, m1, m2);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,10 +603,57 @@ __host__ __device__ constexpr int record_width() {
 // found from h_A (genz_order), the pair's permuted Cholesky factor is kept in
 // the wave's LDS slot cw[Q*Q] for the moment transform, and the moments are
 // mapped back to the original labelling.
+// PHASE splits the work of one pair over several waves: PHASE 1 computes
+// only the sums of every integral over the points k0 + lane + i kstep and
+// writes them to part[part_width()] (lane 0); PHASE 2 combines the K such
+// records at part in a fixed order and finishes the pair as PHASE 0 does.
 // Returns kOk, kENonFinite if y_j is not finite, or kENotPD if the ordered
 // factorisation meets a non-positive pivot.
 // ---------------------------------------------------------------------------
-template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false>
+// doubles of one partial-sum record: A (R, S0) | B (R, S0, S1[Q], S2[NT]) |
+// the two exact-nu integrals (R, S0) each
+template <int Q, bool MOM, bool EXACT>
+__host__ __device__ constexpr int part_width() {
+  return 2 + (MOM ? 2 + Q + Q * (Q + 1) / 2 : 0) + ((EXACT && MOM) ? 4 : 0);
+}
+
+template <int Q, bool MOM>
+__device__ __forceinline__ void part_store(const GhkPart<Q, MOM>& x, double* o) {
+  o[0] = x.R;
+  o[1] = x.S0;
+  if (MOM) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) o[2 + m] = x.S1[m];
+#pragma unroll
+    for (int t = 0; t < Q * (Q + 1) / 2; ++t) o[2 + Q + t] = x.S2[t];
+  }
+}
+
+template <int Q, bool MOM>
+__device__ __forceinline__ void part_load(const double* __restrict__ o, GhkPart<Q, MOM>& x) {
+  x.R = o[0];
+  x.S0 = o[1];
+  if (MOM) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) x.S1[m] = o[2 + m];
+#pragma unroll
+    for (int t = 0; t < Q * (Q + 1) / 2; ++t) x.S2[t] = o[2 + Q + t];
+  }
+}
+
+// the K records at part combined in order 0, 1, ..., K-1
+template <int Q, bool MOM>
+__device__ __forceinline__ void part_reduce(const double* __restrict__ part, int PW, int off,
+                                            int K, GhkPart<Q, MOM>& acc) {
+  part_load<Q, MOM>(part + off, acc);
+  for (int k = 1; k < K; ++k) {
+    GhkPart<Q, MOM> x;
+    part_load<Q, MOM>(part + (size_t)k * PW + off, x);
+    ghk_combine<Q, MOM>(acc, x);
+  }
+}
+
+template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false, int PHASE = 0>
 __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
                                          const double* __restrict__ mui,
                                          const double* __restrict__ cp,
@@ -556,8 +662,11 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
                                          const T* __restrict__ ubT, int N, int lane,
                                          double* lane_out, const T* __restrict__ sApi = nullptr,
                                          const T* __restrict__ sAmi = nullptr,
-                                         double* cw = nullptr) {
+                                         double* cw = nullptr, double* part = nullptr,
+                                         int k0 = 0, int kstep = 64, int K = 1) {
   constexpr int NT = Q * (Q + 1) / 2;
+  constexpr int PW = part_width<Q, MOM, EXACT>();
+  constexpr int OFF_B = 2, OFF_P = 2 + (MOM ? 2 + Q + NT : 0), OFF_M = OFF_P + 2;
   const CompLayout cl(p, Q);
   const double v = cp[cl.nu];
 
@@ -626,7 +735,7 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
 #pragma unroll
       for (int l = 0; l < Q; ++l) Ct[m][l] = (l < m) ? (T)(Cp[m][l] / cmm) : T(0);
     }
-    if (MOM) {
+    if (MOM && PHASE != 1) {
       // the factor is read again only by the moment transform after the
       // point loops: park it in this wave's LDS slot instead of registers
       if (lane == 0) {
@@ -643,25 +752,66 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
   }
 
   // ---- a5 / a6: the two GHK integrals over this lane's points ----
-  double logTA, logTB = 0.0;
+  // (the exact-nu integrals at bounds h_A sqrt(1 +- kFdRel) with it)
+  double logTA, logTB = 0.0, lp = 0.0, lm = 0.0;
   double m1[Q], m2[Q][Q];
-  ghk_integral<T, Q, false>(htA, Ct, Cm, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
-  if (MOM) ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+  T hp[Q], hm[Q];
+  if (EXACT && MOM) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      hp[m] = (T)(hAd[m] * sqrt(1.0 + kFdRel));
+      hm[m] = (T)(hAd[m] * sqrt(1.0 - kFdRel));
+    }
+  }
+  if constexpr (PHASE == 0) {
+    ghk_integral<T, Q, false>(htA, Ct, Cm, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
+    if (MOM) ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+    if (EXACT && MOM) {
+      ghk_integral<T, Q, false>(hp, Ct, Cm, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
+      ghk_integral<T, Q, false>(hm, Ct, Cm, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
+    }
+  } else if constexpr (PHASE == 1) {
+    GhkPart<Q, false> pa;
+    ghk_sums<T, Q, false>(htA, Ct, sAi, nullptr, uT, ubT, N, k0, kstep, lane, pa);
+    if (lane == 0) part_store<Q, false>(pa, part);
+    if (MOM) {
+      GhkPart<Q, MOM> pb;
+      ghk_sums<T, Q, MOM>(htB, Ct, sBi, rsBi, uT, ubT, N, k0, kstep, lane, pb);
+      if (lane == 0) part_store<Q, MOM>(pb, part + OFF_B);
+    }
+    if (EXACT && MOM) {
+      GhkPart<Q, false> pp, pm;
+      ghk_sums<T, Q, false>(hp, Ct, sApi, nullptr, uT, ubT, N, k0, kstep, lane, pp);
+      ghk_sums<T, Q, false>(hm, Ct, sAmi, nullptr, uT, ubT, N, k0, kstep, lane, pm);
+      if (lane == 0) {
+        part_store<Q, false>(pp, part + OFF_P);
+        part_store<Q, false>(pm, part + OFF_M);
+      }
+    }
+    return kOk;
+  } else {
+    GhkPart<Q, false> pa;
+    part_reduce<Q, false>(part, PW, 0, K, pa);
+    ghk_finish<Q, false>(pa, Cm, N, &logTA, m1, m2);
+    if (MOM) {
+      GhkPart<Q, MOM> pb;
+      part_reduce<Q, MOM>(part, PW, OFF_B, K, pb);
+      ghk_finish<Q, MOM>(pb, Cm, N, &logTB, m1, m2);
+    }
+    if (EXACT && MOM) {
+      GhkPart<Q, false> pp, pm;
+      part_reduce<Q, false>(part, PW, OFF_P, K, pp);
+      part_reduce<Q, false>(part, PW, OFF_M, K, pm);
+      ghk_finish<Q, false>(pp, Cm, N, &lp, m1, m2);
+      ghk_finish<Q, false>(pm, Cm, N, &lm, m1, m2);
+    }
+  }
 
   // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a
   // by a central difference over the same points ----
   double dlogJ = 0.0;
   bool fd_ok = false;
   if (EXACT && MOM) {
-    T hp[Q], hm[Q];
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      hp[m] = (T)(hAd[m] * sqrt(1.0 + kFdRel));
-      hm[m] = (T)(hAd[m] * sqrt(1.0 - kFdRel));
-    }
-    double lp, lm;
-    ghk_integral<T, Q, false>(hp, Ct, Cm, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
-    ghk_integral<T, Q, false>(hm, Ct, Cm, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
     fd_ok = isfinite(lp) && isfinite(lm);
     dlogJ = (lp - lm) / (2.0 * kFdRel * 0.5 * (v + p));
   }
@@ -775,6 +925,70 @@ void pair_kernel(
       sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
       EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr,
       REORDER ? cfac + wv * Q * Q : nullptr);
+  if (rc != kOk) {
+    if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
+    return;
+  }
+  if (lane < RW) pairbuf[pair * W + lane] = out[0];
+  if constexpr (RW > 64) {
+    if (lane + 64 < RW) pairbuf[pair * W + 64 + lane] = out[1];
+  }
+}
+
+// The same pair evaluation split over K waves per pair, for launches with too
+// few pairs to fill the GPU: wave w of the grid takes pair w / K and the
+// points s*64 + lane + i*64K (s = w mod K) of every integral and writes that
+// subset's sums to parts[pair][s]; pair_finish_kernel then combines the K
+// records of a pair in order s = 0..K-1 and assembles the pair record.
+template <typename T, int Q, bool MOM, int OCC = 0, bool EXACT = false, bool REORDER = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+void pair_part_kernel(
+    const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
+    const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
+    const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N, int K,
+    double* __restrict__ parts, int* status, const T* __restrict__ sAp = nullptr,
+    const T* __restrict__ sAm = nullptr) {
+  constexpr int PW = part_width<Q, MOM, EXACT>();
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+  if (w >= n * g * K) return;
+  if (status[0] != kOk) return;
+  const int64_t pair = w / K;
+  const int sub = (int)(w - pair * K);
+  const int64_t j = pair / g;
+  const int i = (int)(pair - j * g);
+  const CompLayout cl(p, Q);
+  double out[1];
+  const int rc = pair_eval<T, Q, MOM, EXACT, REORDER, 1>(
+      y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
+      sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
+      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr, nullptr,
+      parts + (size_t)w * PW, 64 * sub, 64 * K, K);
+  if (rc != kOk && lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
+}
+
+template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false>
+__global__ __launch_bounds__(256) void pair_finish_kernel(
+    const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
+    const double* __restrict__ comp, int N, int K, const double* __restrict__ parts,
+    double* __restrict__ pairbuf, int W, int* status) {
+  constexpr int PW = part_width<Q, MOM, EXACT>();
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
+  if (pair >= n * g) return;
+  if (status[0] != kOk) return;
+  const int64_t j = pair / g;
+  const int i = (int)(pair - j * g);
+  const CompLayout cl(p, Q);
+  __shared__ double cfac[REORDER ? 4 * Q * Q : 1];
+  constexpr int RW = record_width<Q, MOM>();
+  double out[RW > 64 ? 2 : 1];
+  const int rc = pair_eval<T, Q, MOM, EXACT, REORDER, 2>(
+      y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, nullptr, nullptr, nullptr,
+      nullptr, nullptr, N, lane, out, nullptr, nullptr, REORDER ? cfac + wv * Q * Q : nullptr,
+      const_cast<double*>(parts) + (size_t)pair * K * PW, 0, 64, K);
   if (rc != kOk) {
     if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
     return;

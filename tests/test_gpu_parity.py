@@ -276,3 +276,27 @@ def test_deterministic(dev):
     for k in ("tau", "e4", "stats"):
         assert np.array_equal(a[k], b[k]), k
     assert a["loglik"] == b["loglik"]
+
+
+@pytest.mark.parametrize("shape", [(7, 3, 3, 2, 1000), (40, 4, 4, 3, 4096), (90, 2, 2, 2, 515),
+                                   (33, 6, 5, 2, 2048)])
+def test_split_waves_parity(dev, orc, shape):
+    """FP64 launches with few pairs spread each pair's points over K waves
+    (here K = 3, 16, 2 and 16) and combine the partial sums; the E-step, the
+    exact-nu E-step and the log-likelihood still match the oracle."""
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    n, p, q, g, N = shape
+    c = inputs.random_case(201 + n, n, p, q, g, N)
+    y, par, u = c["y"], c["params"], c["u"]
+    for mode, omode in (("osl", orc.NU_OSL), ("exact", orc.NU_EXACT_FD)):
+        ref = orc.estep(y, par, u, nu_mode=omode)
+        print(f"[gpu] split estep n={n} q={q} g={g} N={N} {mode}", flush=True)
+        g_ = native.cfust_estep(T(y, dev), gpu_params(par, dev), T(u, dev), nu_mode=mode)
+        got = {k: v.cpu().numpy() for k, v in g_.items()}
+        got["loglik"] = float(got["loglik"][0])
+        err = parity.estep_errors(got, ref, p, q)
+        assert max(err.values()) <= TOL, (mode, err)
+    ll_ref = orc.loglik(y, par, u)
+    ll = float(native.cfust_loglik(T(y, dev), gpu_params(par, dev), T(u, dev)).cpu()[0])
+    assert abs(ll - ll_ref) <= TOL * abs(ll_ref)

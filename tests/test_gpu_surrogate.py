@@ -222,7 +222,9 @@ def test_pair_features_definition(dev):
 
 def test_out_of_range_pairs_fall_back_to_ghk(dev):
     """With an h box no pair reaches, every pair goes through the GHK kernel
-    and the E-step equals the plain one bit for bit."""
+    and the E-step equals the plain one.  (At this size the plain FP64
+    E-step spreads each pair over several waves, so the two sum the same
+    points in a different order: 1e-13.)"""
     from paper_2005_06848_amd import inputs, native
     c = inputs.config(5, n=500)
     par = {k: T(v, dev) for k, v in c["true"].items()}
@@ -234,7 +236,8 @@ def test_out_of_range_pairs_fall_back_to_ghk(dev):
     got = native.cfust_estep(y, par, u, surrogate=net)
     assert net.fallback_count() == c["n"] * c["g"]
     for k in ("tau", "logf", "e2", "e3", "e4", "stats", "loglik"):
-        assert np.array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy()), k
+        a, b = got[k].cpu().numpy(), ref[k].cpu().numpy()
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b)), k
 
 
 # ---------------------------------------------------------------------------
