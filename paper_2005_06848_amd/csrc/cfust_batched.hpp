@@ -67,8 +67,17 @@ __global__ void bprecompute_kernel(BatchDev b, const double* __restrict__ pi,
   if (i == 0 && !pi_on_simplex(pi + c0, g)) fail_problem(b, k, kEInval, -1);
   if (i >= g) return;
   const int c = c0 + i;
-  int rc = precompute_component(p, q, pi[c], nu[c], mu + (size_t)c * p, Sigma + (size_t)c * p * p,
-                                Delta + (size_t)c * p * q, comp + (size_t)c * cl.stride);
+  // LDS sized by the host for kMaxG components, when it fits
+  extern __shared__ double plds[];
+  int rc;
+  if (precompute_lds_bytes(p, q, kMaxG))
+    rc = precompute_component_lds(p, q, pi[c], nu[c], mu + (size_t)c * p,
+                                  Sigma + (size_t)c * p * p, Delta + (size_t)c * p * q,
+                                  plds + (size_t)i * precompute_lds_doubles(p, q),
+                                  comp + (size_t)c * cl.stride);
+  else
+    rc = precompute_component(p, q, pi[c], nu[c], mu + (size_t)c * p, Sigma + (size_t)c * p * p,
+                              Delta + (size_t)c * p * q, comp + (size_t)c * cl.stride);
   if (rc != kOk) fail_problem(b, k, rc, i);
 }
 
@@ -233,10 +242,13 @@ __global__ void bmstep_kernel(BatchDev b, const double* __restrict__ stats, int 
   const int p = b.p, q = b.q;
   const int64_t n = b.n_off[k + 1] - b.n_off[k];
   int* st = b.status + 2 * k;
+  // LDS sized by the host for the largest g of the batch, when it fits
+  extern __shared__ double mlds[];
+  double* wk = mstep_lds_bytes(p, q, kMaxG) ? mlds : mwork + (size_t)c0 * mstep_work_doubles(p, q);
   mstep_body(stats + (size_t)c0 * b.S, n, p, q, g, mu + (size_t)c0 * p,
              Delta + (size_t)c0 * p * q, nu + c0, nu_fixed, fix_delta_zero, nu_lo, nu_hi,
              pi + c0, mu + (size_t)c0 * p, Sigma + (size_t)c0 * p * p, Delta + (size_t)c0 * p * q,
-             nu + c0, pi_tmp + c0, mwork + (size_t)c0 * mstep_work_doubles(p, q), st);
+             nu + c0, pi_tmp + c0, wk, st);
   __syncthreads();
   if (threadIdx.x == 0 && st[0] != kOk) b.active[k] = 0;
 }

@@ -310,7 +310,8 @@ template <typename T>
 void launch_prepare(const Ws& ws, const Plan& pl, const double* pi, const double* mu,
                     const double* Sigma, const double* Delta, const double* nu, const double* u,
                     bool points) {
-  precompute_kernel<<<1, 64, 0, ws.st>>>(pl.p, pl.q, pl.g, pi, Sigma, Delta, mu, nu,
+  precompute_kernel<<<1, 64, precompute_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
+      pl.p, pl.q, pl.g, pi, Sigma, Delta, mu, nu,
                                          ws.at<double>(pl.o_comp), ws.at<int>(pl.o_status));
   const int q1 = pl.q + 1;
   if (points) {
@@ -615,7 +616,8 @@ void run_mstep(Ws& ws, const Plan& pl, int64_t n, const double* stats, const dou
     fixd = o->fix_delta_zero != 0;
   }
   prof_begin(ws, 3);
-  mstep_kernel<<<1, 64, 0, ws.st>>>(stats, n, pl.p, pl.q, pl.g, mu_old, Delta_old, nu_old,
+  mstep_kernel<<<1, 64, mstep_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
+      stats, n, pl.p, pl.q, pl.g, mu_old, Delta_old, nu_old,
                                     fixed, fixd, lo, hi, pi, mu, Sigma, Delta, nu,
                                     ws.at<double>(pl.o_pitmp), ws.at<double>(pl.o_mwork),
                                     ws.at<int>(pl.o_status));
@@ -1069,7 +1071,8 @@ void launch_bpair_q(const BPlan& pl, const BatchDev& b, char* base, const BArgs&
 template <typename T>
 void launch_bprepare(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a,
                      hipStream_t st) {
-  bprecompute_kernel<<<pl.P, 64, 0, st>>>(b, a.pi, a.Sigma, a.Delta, a.mu, a.nu,
+  bprecompute_kernel<<<pl.P, 64, precompute_lds_bytes(pl.p, pl.q, kMaxG), st>>>(
+      b, a.pi, a.Sigma, a.Delta, a.mu, a.nu,
                                           (double*)(base + pl.o_comp));
   int64_t tot = (int64_t)2 * pl.G * pl.N;
   bchi_kernel<T><<<(unsigned)((tot + 127) / 128), 128, 0, st>>>(
@@ -1091,7 +1094,8 @@ void batched_iteration(const BPlan& pl, const BatchDev& b, char* base, const BAr
                                               (const double*)(base + pl.o_pll),
                                               (double*)(base + pl.o_stats));
   baitken_kernel<<<(pl.P + 63) / 64, 64, 0, st>>>(b, pl.max_iter, a.tol);
-  bmstep_kernel<<<pl.P, 64, 0, st>>>(b, (const double*)(base + pl.o_stats), a.nu_fixed,
+  bmstep_kernel<<<pl.P, 64, mstep_lds_bytes(pl.p, pl.q, kMaxG), st>>>(
+      b, (const double*)(base + pl.o_stats), a.nu_fixed,
                                      a.fix_delta_zero, a.nu_lo, a.nu_hi, a.pi, a.mu, a.Sigma,
                                      a.Delta, a.nu, (double*)(base + pl.o_pitmp),
                                      (double*)(base + pl.o_mwork));
@@ -2111,7 +2115,8 @@ int cfust_surrogate_adapt(cfust_surrogate* s, const double* y, int64_t n, int p,
   clear_status(ws, pl);
   const double* comp = ws.at<double>(pl.o_comp);
   int* status = ws.at<int>(pl.o_status);
-  precompute_kernel<<<1, 64, 0, st>>>(p, q, g, pi, Sigma, Delta, mu, nu,
+  precompute_kernel<<<1, 64, precompute_lds_bytes(p, q, g), st>>>(
+      p, q, g, pi, Sigma, Delta, mu, nu,
                                       ws.at<double>(pl.o_comp), status);
   // uniform sample of pairs (with replacement)
   const int64_t pairs = n * g;
@@ -2223,7 +2228,8 @@ int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const d
   clear_status(ws, pl);
   const double* comp = ws.at<double>(pl.o_comp);
   int* status = ws.at<int>(pl.o_status);
-  precompute_kernel<<<1, 64, 0, ws.st>>>(p, q, g, pi, Sigma, Delta, mu, nu,
+  precompute_kernel<<<1, 64, precompute_lds_bytes(p, q, g), ws.st>>>(
+      p, q, g, pi, Sigma, Delta, mu, nu,
                                          ws.at<double>(pl.o_comp), status);
   const int64_t pairs = n * g;
   const unsigned nb = (unsigned)((pairs + 127) / 128);

@@ -204,17 +204,56 @@ __device__ bool pi_on_simplex(const double* pi, int g) {
   return fabs(s - 1.0) <= 1e-12;
 }
 
+// LDS the precompute kernels take for g components (each: its block plus
+// copies of Sigma_i and Delta_i), or 0 when that does not fit (the blocks
+// are then built in place in device memory)
+constexpr int kPrecompLdsMax = 48 * 1024;
+__host__ __device__ inline int precompute_lds_doubles(int p, int q) {
+  return CompLayout(p, q).stride + p * p + p * q;
+}
+__host__ __device__ inline int precompute_lds_bytes(int p, int q, int g) {
+  const int b = g * precompute_lds_doubles(p, q) * (int)sizeof(double);
+  return b <= kPrecompLdsMax ? b : 0;
+}
+
+// Component i's block in LDS: Sigma_i and Delta_i are copied in first (the
+// copy's loads are independent, so they pipeline; the set-up's inner loops
+// then wait on LDS instead of device memory), then the block is copied out.
+__device__ __forceinline__ int precompute_component_lds(int p, int q, double w, double v,
+                                                        const double* mu_i, const double* Sg,
+                                                        const double* Dl, double* lds,
+                                                        double* out) {
+  const CompLayout cl(p, q);
+  double* sg = lds + cl.stride;
+  double* dl = sg + p * p;
+  for (int x = 0; x < p * p; ++x) sg[x] = Sg[x];
+  for (int x = 0; x < p * q; ++x) dl[x] = Dl[x];
+  const int rc = precompute_component(p, q, w, v, mu_i, sg, dl, lds);
+  for (int x = 0; x < cl.stride; ++x) out[x] = lds[x];
+  return rc;
+}
+
+// lane i builds component i's block (in LDS when it fits, then copied out:
+// the serial O(p^3) set-up runs on LDS latency instead of device memory's)
 __global__ void precompute_kernel(int p, int q, int g, const double* __restrict__ pi,
                                   const double* __restrict__ Sigma,
                                   const double* __restrict__ Delta, const double* __restrict__ mu,
                                   const double* __restrict__ nu, double* __restrict__ comp,
                                   int* status) {
+  extern __shared__ double plds[];
   const int i = threadIdx.x;
   CompLayout cl(p, q);
   if (i == 0 && !pi_on_simplex(pi, g)) set_status(status, kEInval, -1);
   if (i >= g) return;
-  int rc = precompute_component(p, q, pi[i], nu[i], mu + (size_t)i * p, Sigma + (size_t)i * p * p,
-                                Delta + (size_t)i * p * q, comp + (size_t)i * cl.stride);
+  int rc;
+  if (precompute_lds_bytes(p, q, g))
+    rc = precompute_component_lds(p, q, pi[i], nu[i], mu + (size_t)i * p,
+                                  Sigma + (size_t)i * p * p, Delta + (size_t)i * p * q,
+                                  plds + (size_t)i * precompute_lds_doubles(p, q),
+                                  comp + (size_t)i * cl.stride);
+  else
+    rc = precompute_component(p, q, pi[i], nu[i], mu + (size_t)i * p, Sigma + (size_t)i * p * p,
+                              Delta + (size_t)i * p * q, comp + (size_t)i * cl.stride);
   if (rc != kOk) set_status(status, rc, i);
 }
 
@@ -1311,14 +1350,23 @@ __device__ double nu_root(double cst, double lo, double hi, double v0) {
 
 // doubles of M-step work space per component (mstep_body)
 __host__ __device__ inline int mstep_work_doubles(int p, int q) {
-  return 2 * q * q + 2 * p * q + 3 * p * p + 2 * p + 2 * q;
+  return 2 * q * q + 3 * p * q + 3 * p * p + 2 * p + 2 * q;
+}
+
+// LDS the M-step kernels take for g components' work space, or 0 when it
+// does not fit (the work space then stays in device memory)
+constexpr int kMstepLdsMax = 48 * 1024;
+__host__ __device__ inline int mstep_lds_bytes(int p, int q, int g) {
+  const int b = g * mstep_work_doubles(p, q) * (int)sizeof(double);
+  return b <= kMstepLdsMax ? b : 0;
 }
 
 // One problem's M-step on one block, lane i = component i.  Statuses go to
 // status[0..1].  Parameters may alias the old ones: every lane reads its old
 // values before any lane writes.  work holds g * mstep_work_doubles(p, q)
-// doubles of device memory (the per-component matrices; in private memory
-// they would need tens of KB of scratch per lane at the largest p and q).
+// doubles (the per-component matrices; in private memory they would need
+// tens of KB of scratch per lane at the largest p and q): the kernels pass
+// LDS when it fits (mstep_lds_bytes), device memory otherwise.
 __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int64_t n, int p,
                                            int q, int g, const double* mu_old,
                                            const double* Delta_old, const double* nu_old,
@@ -1342,6 +1390,7 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
   double* Sg = s4 + q;
   double* Lc = Sg + p * p;
   double* tmp = Lc + p * p;  // q doubles
+  double* E5 = tmp + q;      // q x p: s5 Delta'^T
   double s1 = 0.0, vnew = 0.0;
   bool ok = true;
   if (i < g) {
@@ -1401,15 +1450,18 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
       }
     }
     if (ok) {
+      // E5 = s5 Delta'^T once, then Sigma' entries in O(q) each
+      for (int k = 0; k < q; ++k)
+        for (int b = 0; b < p; ++b) {
+          double dk = 0.0;
+          for (int l = 0; l < q; ++l) dk += s5[k * q + l] * Dn[b * q + l];
+          E5[k * p + b] = dk;
+        }
       for (int a = 0; a < p; ++a)
         for (int b = 0; b < p; ++b) {
           double t = s7[a * p + b];
           for (int k = 0; k < q; ++k) t -= Dn[a * q + k] * s6[b * q + k] + s6[a * q + k] * Dn[b * q + k];
-          for (int k = 0; k < q; ++k) {
-            double dk = 0.0;
-            for (int l = 0; l < q; ++l) dk += s5[k * q + l] * Dn[b * q + l];
-            t += Dn[a * q + k] * dk;
-          }
+          for (int k = 0; k < q; ++k) t += Dn[a * q + k] * E5[k * p + b];
           Sg[a * p + b] = t / s1;
         }
       for (int a = 0; a < p; ++a)
@@ -1451,8 +1503,9 @@ __global__ void mstep_kernel(const double* __restrict__ stats, int64_t n, int p,
                              double* pi, double* mu, double* Sigma, double* Delta, double* nu,
                              double* __restrict__ pi_tmp, double* __restrict__ work,
                              int* status) {
+  extern __shared__ double mlds[];
   mstep_body(stats, n, p, q, g, mu_old, Delta_old, nu_old, nu_fixed, fix_delta_zero, nu_lo, nu_hi,
-             pi, mu, Sigma, Delta, nu, pi_tmp, work, status);
+             pi, mu, Sigma, Delta, nu, pi_tmp, mstep_lds_bytes(p, q, g) ? mlds : work, status);
 }
 
 // ---------------------------------------------------------------------------
