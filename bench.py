@@ -39,12 +39,12 @@ C_PHI, C_PHIINV, C_ACC = 40, 50, 20
 
 # HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (KiB per dispatch, scaled by the same counters on a plain copy kernel:
-# fetch x 1.99980, write x 0.99998); None when the kernel has changed since
+# fetch x 1.99977, write x 0.99998); None when the kernel has changed since
 # the counters were taken.
-TRAFFIC_BYTES_PER_LAUNCH = 60822566
+TRAFFIC_BYTES_PER_LAUNCH = 43270089
 # executed FP64 flops per launch of the same kernel from the SQ_INSTS_VALU_*_F64
 # counters (64 lanes, FMA = 2)
-EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.594e11
+EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.5937e11
 
 
 def flops_per_pair(p, q, N):
