@@ -219,6 +219,45 @@ def batched_form(args, native, torch, np, inputs, dev):
         ts = time.perf_counter() - t0
         res["sequential_seconds"] = round(ts, 3)
         res["speedup_vs_sequential"] = round(ts / tb, 3)
+    res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
+    return res
+
+
+def batched_small(args, native, torch, np, inputs, dev):
+    """The same recipe at the size the batched form is for: 256 starts with
+    n ~ U{150..500} (the paper's data set has 202 observations), g ~ U{2..6},
+    p = q = 5, N = 1024, FP32 integrand, 50 iterations; batched against one
+    by one."""
+    print("[bench] batched: 256 small starts", file=sys.stderr, flush=True)
+    probs = inputs.batched_problems(256, n_lo=150, n_hi=500, seed_offset=5)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    u = T(inputs.qmc_points(1024, 5))
+    y = T(np.concatenate([c["y"] for c in probs]))
+    par = {k: T(np.concatenate([c["init"][k] for c in probs])) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    n = [c["n"] for c in probs]
+    g = [c["g"] for c in probs]
+    it = 50
+    native.cfust_em_fit_batched(y, n, g, par, u, max_iter=1, tol=1e-6, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(y, n, g, par, u, max_iter=it, tol=1e-6,
+                                                             precision="fp32")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    res = {"workload": "256 starts, n~U{150..500}, g~U{2..6}, p=q=5, N=1024, fp32 integrand",
+           "iterations_cap": it, "seconds": round(tb, 4),
+           "n_iter_mean": round(float(n_iter.mean()), 2), "failed": int((status != 0).sum())}
+    if not args.no_sequential:
+        ys = [T(c["y"]) for c in probs]
+        ps = [{k: T(v) for k, v in c["init"].items()} for c in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(len(probs)):
+            native.cfust_em_fit(ys[k], ps[k], u, max_iter=it, tol=1e-6, precision="fp32")
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        res["sequential_seconds"] = round(ts, 4)
+        res["speedup_vs_sequential"] = round(ts / tb, 2)
     return res
 
 
