@@ -332,9 +332,14 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   int64_t pairs = pl.n * pl.g;
   if (pairs == 0) return;
   unsigned blocks = (unsigned)((pairs + 3) / 4);
-  // FP64 with q <= 4 fits four waves per SIMD with little spilling (2.5%
-  // faster at p=q=4); larger q spill heavily there and keep the default
-  constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4 : 0;
+  // Resident waves per SIMD asked of the compiler.  FP64 q <= 4: four (2.5%
+  // faster at p=q=4, 48 B/lane of spill outside the point loop).  q = 5, 6:
+  // three for FP64 and four for FP32 (3.8% and 2.3% faster at p=q=6 than the
+  // compiler's two and three, despite 192 and 176 B/lane of spill).  Larger
+  // q keep the compiler's choice.
+  constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4
+                      : (Q == 5 || Q == 6)       ? (sizeof(T) == 8 ? 3 : 4)
+                                                 : 0;
   const double* comp = ws.at<double>(pl.o_comp);
   double* pairs_out = ws.at<double>(pl.o_pair);
   int* status = ws.at<int>(pl.o_status);

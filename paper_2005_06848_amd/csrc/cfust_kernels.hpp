@@ -361,13 +361,14 @@ __device__ __forceinline__ int shift_of(double d) { return (int)fmax(d, -1100.0)
 __device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
 
 // ---------------------------------------------------------------------------
-// One GHK integral on one wave (section 2: the q-variate t CDF of eq. (2) and,
-// with MOM, the moments of the truncated t).  V ~ t_Q(0, R, dof), R = C C^T,
-// bound h: ht[m] = h_m / C_mm and Ct[m][l] = C_ml / C_mm (l < m) scale the
-// sequential bounds; s[k] = sqrt(chi2^-1(u_k0; dof)/dof) and rs = 1/s.  Lane
-// t handles points t, t+64, ...; MOM draws all Q coordinates and returns
-// E[V | V <= h] and E[V V^T | V <= h], otherwise the last draw is skipped.
-// Every lane returns log P(V <= h) and the moments.
+// GHK integrals (section 2: the q-variate t CDF of eq. (2) and, with MOM, the
+// moments of the truncated t).  V ~ t_Q(0, R, dof), R = C C^T, bound h:
+// ht[m] = h_m / C_mm and Ct[m][l] = C_ml / C_mm (l < m) scale the sequential
+// bounds; s[k] = sqrt(chi2^-1(u_k0; dof)/dof) and rs = 1/s.  MOM draws all Q
+// coordinates and yields E[V | V <= h] and E[V V^T | V <= h]; otherwise the
+// last draw is skipped.  ghk_sums accumulates a subset of the points on one
+// wave, ghk_combine merges subsets, ghk_finish turns the sums into log
+// P(V <= h) and the moments; ghk_integral is all three over all points.
 // ---------------------------------------------------------------------------
 // Wave-uniform sums of one GHK integral over a subset of the points, scaled
 // by 2^-R: S0 = sum w, S1 = sum w ehat, S2 = sum w ehat ehat^T (upper
