@@ -621,7 +621,7 @@ void run_mstep(Ws& ws, const Plan& pl, int64_t n, const double* stats, const dou
     fixd = o->fix_delta_zero != 0;
   }
   prof_begin(ws, 3);
-  mstep_kernel<<<1, 64, mstep_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
+  mstep_kernel<<<1, 256, mstep_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
       stats, n, pl.p, pl.q, pl.g, mu_old, Delta_old, nu_old,
                                     fixed, fixd, lo, hi, pi, mu, Sigma, Delta, nu,
                                     ws.at<double>(pl.o_pitmp), ws.at<double>(pl.o_mwork),

@@ -1362,12 +1362,16 @@ __host__ __device__ inline int mstep_lds_bytes(int p, int q, int g) {
   return b <= kMstepLdsMax ? b : 0;
 }
 
-// One problem's M-step on one block, lane i = component i.  Statuses go to
-// status[0..1].  Parameters may alias the old ones: every lane reads its old
-// values before any lane writes.  work holds g * mstep_work_doubles(p, q)
-// doubles (the per-component matrices; in private memory they would need
-// tens of KB of scratch per lane at the largest p and q): the kernels pass
-// LDS when it fits (mstep_lds_bytes), device memory otherwise.
+// One problem's M-step on one block.  The per-entry work is spread over the
+// block's threads in phases separated by barriers (unpacking the statistics
+// and mu' | Delta' rows | s5 Delta'^T | Sigma' entries); the two Cholesky
+// factorisations and the nu root run on one thread per component.  Every
+// entry is computed with the same operations in the same order as a serial
+// loop would.  Statuses go to status[0..1]; if any component fails, no
+// parameter is written.  Parameters may alias the old ones: every old value
+// is read before the barrier that precedes the first write.  work holds
+// g * mstep_work_doubles(p, q) doubles (LDS when it fits, see
+// mstep_lds_bytes; device memory otherwise).
 __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int64_t n, int p,
                                            int q, int g, const double* mu_old,
                                            const double* Delta_old, const double* nu_old,
@@ -1375,126 +1379,195 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
                                            double nu_hi, double* pi, double* mu, double* Sigma,
                                            double* Delta, double* nu, double* __restrict__ pi_tmp,
                                            double* __restrict__ work, int* status) {
-  const int i = threadIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const StatLayout sl(p, q);
+  const int MW = mstep_work_doubles(p, q);
   __shared__ int fail;
-  if (i == 0) fail = 0;
+  __shared__ int okc[kMaxG];
+  __shared__ double s1c[kMaxG], s2c[kMaxG], vnc[kMaxG];
+  // component c's work space
+  struct WorkC {
+    double *s5, *L5, *s6, *s7, *Dn, *dmu, *s3, *s4, *Sg, *Lc, *E5;
+  };
+  auto wk = [&](int c) {
+    WorkC w;
+    w.s5 = work + (size_t)c * MW;
+    w.L5 = w.s5 + q * q;
+    w.s6 = w.L5 + q * q;
+    w.s7 = w.s6 + p * q;
+    w.Dn = w.s7 + p * p;
+    w.dmu = w.Dn + p * q;
+    w.s3 = w.dmu + p;
+    w.s4 = w.s3 + p;
+    w.Sg = w.s4 + q;
+    w.Lc = w.Sg + p * p;
+    w.E5 = w.Lc + p * p + q;
+    return w;
+  };
+  if (tid < g) okc[tid] = 1;
+  if (tid == 0) fail = 0;
   __syncthreads();
-  double* s5 = work + (size_t)(i < g ? i : 0) * mstep_work_doubles(p, q);
-  double* L5 = s5 + q * q;
-  double* s6 = L5 + q * q;
-  double* s7 = s6 + p * q;
-  double* Dn = s7 + p * p;
-  double* dmu = Dn + p * q;
-  double* s3 = dmu + p;
-  double* s4 = s3 + p;
-  double* Sg = s4 + q;
-  double* Lc = Sg + p * p;
-  double* tmp = Lc + p * p;  // q doubles
-  double* E5 = tmp + q;      // q x p: s5 Delta'^T
-  double s1 = 0.0, vnew = 0.0;
-  bool ok = true;
-  if (i < g) {
-    const double* st = stats + (size_t)i * sl.S;
-    for (int e = 0; e < sl.S; ++e)
-      if (!isfinite(st[e])) ok = false;
-    if (!ok) {
-      set_status(status, kENonFinite, i);
+  for (int t = tid; t < g * sl.S; t += nt)
+    if (!isfinite(stats[t])) okc[t / sl.S] = 0;
+  __syncthreads();
+  if (tid < g) {
+    const double* st = stats + (size_t)tid * sl.S;
+    if (!okc[tid]) {
+      set_status(status, kENonFinite, tid);
       fail = 1;
     }
-    s1 = st[sl.s1];
-    double s2 = st[sl.s2];
-    if (ok && (!(s1 > 0.0) || !(s2 > 0.0))) {
-      ok = false;
-      set_status(status, kENotPD, i);
+    s1c[tid] = st[sl.s1];
+    s2c[tid] = st[sl.s2];
+    if (okc[tid] && (!(s1c[tid] > 0.0) || !(s2c[tid] > 0.0))) {
+      okc[tid] = 0;
+      set_status(status, kENotPD, tid);
       fail = 1;
     }
-    if (ok) {
-      for (int a = 0; a < p; ++a) s3[a] = st[sl.s3 + a];
-      for (int k = 0; k < q; ++k) s4[k] = st[sl.s4 + k];
-      for (int k = 0; k < q; ++k)
-        for (int l = 0; l < q; ++l) s5[k * q + l] = st[sl.s5 + tri_index(min(k, l), max(k, l), q)];
-      const double* Dold = Delta_old + (size_t)i * p * q;
-      for (int a = 0; a < p; ++a) {
-        double t = s3[a];
-        for (int k = 0; k < q; ++k) t -= Dold[a * q + k] * s4[k];
-        dmu[a] = t / s2;
-      }
-      for (int a = 0; a < p; ++a)
-        for (int k = 0; k < q; ++k) s6[a * q + k] = st[sl.s6 + a * q + k] - dmu[a] * s4[k];
-      for (int a = 0; a < p; ++a)
-        for (int b = 0; b < p; ++b)
-          s7[a * p + b] = st[sl.s7 + tri_index(min(a, b), max(a, b), p)] - s3[a] * dmu[b] -
-                          dmu[a] * s3[b] + s2 * dmu[a] * dmu[b];
-      if (fix_delta_zero) {
-        for (int x = 0; x < p * q; ++x) Dn[x] = 0.0;
-      } else {
-        for (int x = 0; x < q * q; ++x) L5[x] = s5[x];
-        if (!chol_small(L5, q)) {
-          ok = false;
-          set_status(status, kENotPD, i);
-          fail = 1;
-        } else {
-          for (int a = 0; a < p; ++a) {
-            for (int k = 0; k < q; ++k) {
-              double t = s6[a * q + k];
-              for (int l = 0; l < k; ++l) t -= L5[k * q + l] * tmp[l];
-              tmp[k] = t / L5[k * q + k];
-            }
-            for (int k = q - 1; k >= 0; --k) {
-              double t = tmp[k];
-              for (int l = k + 1; l < q; ++l) t -= L5[l * q + k] * Dn[a * q + l];
-              Dn[a * q + k] = t / L5[k * q + k];
-            }
-          }
-        }
-      }
+  }
+  __syncthreads();
+  // s3, s4, s5 (full), dmu = (s3 - Delta s4) / s2
+  for (int t = tid; t < g * p; t += nt) {
+    const int c = t / p, a = t - c * p;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    const double* st = stats + (size_t)c * sl.S;
+    const double* Dold = Delta_old + (size_t)c * p * q;
+    w.s3[a] = st[sl.s3 + a];
+    double tt = st[sl.s3 + a];
+    for (int k = 0; k < q; ++k) tt -= Dold[a * q + k] * st[sl.s4 + k];
+    w.dmu[a] = tt / s2c[c];
+  }
+  for (int t = tid; t < g * q * q; t += nt) {
+    const int c = t / (q * q), x = t - c * q * q, k = x / q, l = x - k * q;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    const double* st = stats + (size_t)c * sl.S;
+    if (l == 0) w.s4[k] = st[sl.s4 + k];
+    w.s5[x] = st[sl.s5 + tri_index(min(k, l), max(k, l), q)];
+    w.L5[x] = w.s5[x];
+  }
+  __syncthreads();
+  // re-centred s6' and s7'
+  for (int t = tid; t < g * p * q; t += nt) {
+    const int c = t / (p * q), x = t - c * p * q, a = x / q, k = x - a * q;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    w.s6[x] = stats[(size_t)c * sl.S + sl.s6 + x] - w.dmu[a] * w.s4[k];
+  }
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p), x = t - c * p * p, a = x / p, b = x - a * p;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    const double s2 = s2c[c];
+    w.s7[x] = stats[(size_t)c * sl.S + sl.s7 + tri_index(min(a, b), max(a, b), p)] -
+              w.s3[a] * w.dmu[b] - w.dmu[a] * w.s3[b] + s2 * w.dmu[a] * w.dmu[b];
+  }
+  // Cholesky factor of s5 (one thread per component)
+  if (tid < g && okc[tid] && !fix_delta_zero) {
+    if (!chol_small(wk(tid).L5, q)) {
+      okc[tid] = 0;
+      set_status(status, kENotPD, tid);
+      fail = 1;
     }
-    if (ok) {
-      // E5 = s5 Delta'^T once, then Sigma' entries in O(q) each
-      for (int k = 0; k < q; ++k)
-        for (int b = 0; b < p; ++b) {
-          double dk = 0.0;
-          for (int l = 0; l < q; ++l) dk += s5[k * q + l] * Dn[b * q + l];
-          E5[k * p + b] = dk;
-        }
-      for (int a = 0; a < p; ++a)
-        for (int b = 0; b < p; ++b) {
-          double t = s7[a * p + b];
-          for (int k = 0; k < q; ++k) t -= Dn[a * q + k] * s6[b * q + k] + s6[a * q + k] * Dn[b * q + k];
-          for (int k = 0; k < q; ++k) t += Dn[a * q + k] * E5[k * p + b];
-          Sg[a * p + b] = t / s1;
-        }
-      for (int a = 0; a < p; ++a)
-        for (int b = 0; b < a; ++b) {
-          double t = 0.5 * (Sg[a * p + b] + Sg[b * p + a]);
-          Sg[a * p + b] = t;
-          Sg[b * p + a] = t;
-        }
-      for (int x = 0; x < p * p; ++x) Lc[x] = Sg[x];
-      if (!chol_small(Lc, p)) {
-        ok = false;
-        set_status(status, kENotPD, i);
+  }
+  __syncthreads();
+  // Delta' rows: s6'_a s5^{-1} by forward then backward substitution in place
+  for (int t = tid; t < g * p; t += nt) {
+    const int c = t / p, a = t - c * p;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    double* Dr = w.Dn + a * q;
+    if (fix_delta_zero) {
+      for (int k = 0; k < q; ++k) Dr[k] = 0.0;
+      continue;
+    }
+    const double* L5 = w.L5;
+    for (int k = 0; k < q; ++k) {
+      double tt = w.s6[a * q + k];
+      for (int l = 0; l < k; ++l) tt -= L5[k * q + l] * Dr[l];
+      Dr[k] = tt / L5[k * q + k];
+    }
+    for (int k = q - 1; k >= 0; --k) {
+      double tt = Dr[k];
+      for (int l = k + 1; l < q; ++l) tt -= L5[l * q + k] * Dr[l];
+      Dr[k] = tt / L5[k * q + k];
+    }
+  }
+  __syncthreads();
+  // E5 = s5 Delta'^T
+  for (int t = tid; t < g * q * p; t += nt) {
+    const int c = t / (q * p), x = t - c * q * p, k = x / p, b = x - k * p;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    double dk = 0.0;
+    for (int l = 0; l < q; ++l) dk += w.s5[k * q + l] * w.Dn[b * q + l];
+    w.E5[x] = dk;
+  }
+  __syncthreads();
+  // Sigma' = (s7' - Delta' s6'^T - s6' Delta'^T + Delta' s5 Delta'^T) / s1
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p), x = t - c * p * p, a = x / p, b = x - a * p;
+    if (!okc[c]) continue;
+    const WorkC w = wk(c);
+    double tt = w.s7[x];
+    for (int k = 0; k < q; ++k)
+      tt -= w.Dn[a * q + k] * w.s6[b * q + k] + w.s6[a * q + k] * w.Dn[b * q + k];
+    for (int k = 0; k < q; ++k) tt += w.Dn[a * q + k] * w.E5[k * p + b];
+    w.Sg[x] = tt / s1c[c];
+  }
+  __syncthreads();
+  // symmetrise; the copy Lc is factored to check definiteness
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p), x = t - c * p * p, a = x / p, b = x - a * p;
+    if (!okc[c] || b > a) continue;
+    const WorkC w = wk(c);
+    if (a == b) {
+      w.Lc[x] = w.Sg[x];
+    } else {
+      const double tt = 0.5 * (w.Sg[a * p + b] + w.Sg[b * p + a]);
+      w.Sg[a * p + b] = tt;
+      w.Sg[b * p + a] = tt;
+      w.Lc[a * p + b] = tt;
+      w.Lc[b * p + a] = tt;
+    }
+  }
+  __syncthreads();
+  if (tid < g) {
+    double vnew = nu_old[tid];
+    if (okc[tid]) {
+      if (!chol_small(wk(tid).Lc, p)) {
+        okc[tid] = 0;
+        set_status(status, kENotPD, tid);
         fail = 1;
+      } else if (!nu_fixed) {
+        vnew = nu_root(stats[(size_t)tid * sl.S + sl.s8] / s1c[tid], nu_lo, nu_hi, nu_old[tid]);
       }
     }
-    vnew = nu_old[i];
-    if (ok && !nu_fixed) vnew = nu_root(st[sl.s8] / s1, nu_lo, nu_hi, nu_old[i]);
+    vnc[tid] = vnew;
   }
-  __syncthreads();  // every lane has read its old parameters before any write
+  __syncthreads();  // every old parameter has been read before any write
   if (fail) return;
-  if (i < g) {
-    pi_tmp[i] = s1 / (double)n;
-    for (int a = 0; a < p; ++a) mu[i * p + a] = mu_old[i * p + a] + dmu[a];
-    for (int x = 0; x < p * q; ++x) Delta[(size_t)i * p * q + x] = Dn[x];
-    for (int x = 0; x < p * p; ++x) Sigma[(size_t)i * p * p + x] = Sg[x];
-    nu[i] = vnew;
+  for (int t = tid; t < g * p; t += nt) {
+    const int c = t / p, a = t - c * p;
+    mu[(size_t)c * p + a] = mu_old[(size_t)c * p + a] + wk(c).dmu[a];
+  }
+  for (int t = tid; t < g * p * q; t += nt) {
+    const int c = t / (p * q), x = t - c * p * q;
+    Delta[(size_t)c * p * q + x] = wk(c).Dn[x];
+  }
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p), x = t - c * p * p;
+    Sigma[(size_t)c * p * p + x] = wk(c).Sg[x];
+  }
+  if (tid < g) {
+    pi_tmp[tid] = s1c[tid] / (double)n;
+    nu[tid] = vnc[tid];
   }
   __syncthreads();
-  if (i < g) {
+  if (tid < g) {
     double ps = 0.0;
     for (int k = 0; k < g; ++k) ps += pi_tmp[k];
-    pi[i] = pi_tmp[i] / ps;
+    pi[tid] = pi_tmp[tid] / ps;
   }
 }
 

@@ -465,3 +465,28 @@ def test_surrogate_check_in_em(dev):
           f"GHK l {ts[sw]:.6f}, final {ts[-1]:.6f}")
     assert sw > 0
     assert abs(ts[sw - 1] / ts[sw] - 1) < 1e-5
+
+
+def test_surrogate_check_with_caller_workspace(dev):
+    """cfust_workspace_size_opts counts the check's buffers: a workspace of
+    exactly that size works and gives the library-allocated result; one byte
+    less is refused with ENOMEM."""
+    import torch
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=2000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    net = _shipped()
+    m = 512
+    nb = native.workspace_size_opts(2000, 6, 6, 4, c["u"].shape[0], surrogate=net,
+                                    surrogate_check=m)
+    assert nb > native.workspace_size(2000, 6, 6, 4, c["u"].shape[0])
+    ref = native.cfust_estep(y, par, u, want=(), surrogate=net, surrogate_check=m)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    got = native.cfust_estep(y, par, u, want=(), surrogate=net, surrogate_check=m, workspace=ws)
+    assert np.array_equal(got["stats"].cpu().numpy(), ref["stats"].cpu().numpy())
+    assert got["loglik"].item() == ref["loglik"].item()
+    with pytest.raises(native.CfustError) as e:
+        native.cfust_estep(y, par, u, want=(), surrogate=net, surrogate_check=m,
+                           workspace=ws[:nb - 1])
+    assert e.value.code == native.ENOMEM
