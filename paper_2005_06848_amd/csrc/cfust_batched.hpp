@@ -52,33 +52,29 @@ __device__ __forceinline__ void fail_problem(const BatchDev& b, int k, int code,
   b.active[k] = 0;
 }
 
-// one block per problem, lane i = component i
+// one block per problem: its components' blocks (precompute_block)
 __global__ void bprecompute_kernel(BatchDev b, const double* __restrict__ pi,
                                    const double* __restrict__ Sigma,
                                    const double* __restrict__ Delta,
                                    const double* __restrict__ mu, const double* __restrict__ nu,
                                    double* __restrict__ comp) {
   const int k = blockIdx.x;
-  if (!b.active[k]) return;
+  // every thread reads the flag before any thread may clear it
+  const int live = b.active[k];
+  __syncthreads();
+  if (!live) return;
   const int c0 = b.g_off[k], g = b.g_off[k + 1] - c0;
   const int i = threadIdx.x;
   const int p = b.p, q = b.q;
-  CompLayout cl(p, q);
+  const CompLayout cl(p, q);
   if (i == 0 && !pi_on_simplex(pi + c0, g)) fail_problem(b, k, kEInval, -1);
-  if (i >= g) return;
-  const int c = c0 + i;
   // LDS sized by the host for kMaxG components, when it fits
   extern __shared__ double plds[];
-  int rc;
-  if (precompute_lds_bytes(p, q, kMaxG))
-    rc = precompute_component_lds(p, q, pi[c], nu[c], mu + (size_t)c * p,
-                                  Sigma + (size_t)c * p * p, Delta + (size_t)c * p * q,
-                                  plds + (size_t)i * precompute_lds_doubles(p, q),
-                                  comp + (size_t)c * cl.stride);
-  else
-    rc = precompute_component(p, q, pi[c], nu[c], mu + (size_t)c * p, Sigma + (size_t)c * p * p,
-                              Delta + (size_t)c * p * q, comp + (size_t)c * cl.stride);
-  if (rc != kOk) fail_problem(b, k, rc, i);
+  const int rc = precompute_block(p, q, g, pi + c0, nu + c0, mu + (size_t)c0 * p,
+                                  Sigma + (size_t)c0 * p * p, Delta + (size_t)c0 * p * q,
+                                  comp + (size_t)c0 * cl.stride,
+                                  precompute_lds_bytes(p, q, kMaxG) ? plds : nullptr);
+  if (i < g && rc != kOk) fail_problem(b, k, rc, i);
 }
 
 template <typename T>

@@ -310,7 +310,7 @@ template <typename T>
 void launch_prepare(const Ws& ws, const Plan& pl, const double* pi, const double* mu,
                     const double* Sigma, const double* Delta, const double* nu, const double* u,
                     bool points) {
-  precompute_kernel<<<1, 64, precompute_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
+  precompute_kernel<<<1, kPrecompThreads, precompute_lds_bytes(pl.p, pl.q, pl.g), ws.st>>>(
       pl.p, pl.q, pl.g, pi, Sigma, Delta, mu, nu,
                                          ws.at<double>(pl.o_comp), ws.at<int>(pl.o_status));
   const int q1 = pl.q + 1;
@@ -1076,7 +1076,7 @@ void launch_bpair_q(const BPlan& pl, const BatchDev& b, char* base, const BArgs&
 template <typename T>
 void launch_bprepare(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a,
                      hipStream_t st) {
-  bprecompute_kernel<<<pl.P, 64, precompute_lds_bytes(pl.p, pl.q, kMaxG), st>>>(
+  bprecompute_kernel<<<pl.P, kPrecompThreads, precompute_lds_bytes(pl.p, pl.q, kMaxG), st>>>(
       b, a.pi, a.Sigma, a.Delta, a.mu, a.nu,
                                           (double*)(base + pl.o_comp));
   int64_t tot = (int64_t)2 * pl.G * pl.N;
@@ -2120,7 +2120,7 @@ int cfust_surrogate_adapt(cfust_surrogate* s, const double* y, int64_t n, int p,
   clear_status(ws, pl);
   const double* comp = ws.at<double>(pl.o_comp);
   int* status = ws.at<int>(pl.o_status);
-  precompute_kernel<<<1, 64, precompute_lds_bytes(p, q, g), st>>>(
+  precompute_kernel<<<1, kPrecompThreads, precompute_lds_bytes(p, q, g), st>>>(
       p, q, g, pi, Sigma, Delta, mu, nu,
                                       ws.at<double>(pl.o_comp), status);
   // uniform sample of pairs (with replacement)
@@ -2233,7 +2233,7 @@ int cfust_pair_features(const double* y, int64_t n, int p, int q, int g, const d
   clear_status(ws, pl);
   const double* comp = ws.at<double>(pl.o_comp);
   int* status = ws.at<int>(pl.o_status);
-  precompute_kernel<<<1, 64, precompute_lds_bytes(p, q, g), ws.st>>>(
+  precompute_kernel<<<1, kPrecompThreads, precompute_lds_bytes(p, q, g), ws.st>>>(
       p, q, g, pi, Sigma, Delta, mu, nu,
                                          ws.at<double>(pl.o_comp), status);
   const int64_t pairs = n * g;

@@ -1,9 +1,10 @@
 // HIP kernels of the CFUST mixture E-step / M-step for CDNA4 (gfx950).
 //
 // Data path of one E-step (section 3.2, Algorithm 2, one wave per pair):
-//   precompute_kernel  per component: Omega = Sigma + Delta Delta^T, its
-//                      Cholesky factor, B = Omega^-1 Delta, Lambda, R and its
-//                      Cholesky factor, the log normaliser (eq. (2))
+//   precompute_kernel  per component (one block, phased over entries):
+//                      Omega = Sigma + Delta Delta^T, its Cholesky factor,
+//                      B = Omega^-1 Delta, Lambda, R and its Cholesky factor,
+//                      the log normaliser (eq. (2))
 //   points_kernel      transposes the QMC points into column tables
 //   chi_kernel         chi scale tables s = sqrt(chi2^-1(u_0)/dof) for the
 //                      two integrals of every component
@@ -13,8 +14,8 @@
 //                      expectations (eq. (2)-(4) and the hidden-variable model)
 //   stats_kernel       responsibilities and the eight partial sums per block
 //   reduce_kernel      fixed-order sum of the block partials
-// and of one M-step (section 3.3, Algorithm 3): mstep_kernel, one lane per
-// component.
+// and of one M-step (section 3.3, Algorithm 3): mstep_kernel, one block
+// phased over the entries of all components.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -96,108 +97,8 @@ __global__ void fill_int_kernel(int* p, int n, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// per-component precompute (eq. (2)): one lane per component
+// per-component precompute (eq. (2)): one block for all components
 // ---------------------------------------------------------------------------
-// Component i's block: returns kOk or a status code (the block is then
-// incomplete).  w = pi_i, v = nu_i, mu_i, Sg = Sigma_i, Dl = Delta_i.
-__device__ int precompute_component(int p, int q, double w, double v, const double* mu_i,
-                                    const double* Sg, const double* Dl, double* out) {
-  CompLayout cl(p, q);
-  if (!isfinite(v) || !isfinite(w)) return kENonFinite;
-  if (!(v > 0.0) || !(w > 0.0)) return kEInval;
-  for (int a = 0; a < p; ++a)
-    if (!isfinite(mu_i[a])) return kENonFinite;
-  for (int a = 0; a < p * p; ++a)
-    if (!isfinite(Sg[a])) return kENonFinite;
-  for (int a = 0; a < p * q; ++a)
-    if (!isfinite(Dl[a])) return kENonFinite;
-  double* L = out + cl.L;
-  // Omega = Sigma + Delta Delta^T, Cholesky in place (lower, row-major)
-  for (int a = 0; a < p; ++a)
-    for (int b = 0; b <= a; ++b) {
-      double t = Sg[a * p + b];
-      for (int k = 0; k < q; ++k) t = fma(Dl[a * q + k], Dl[b * q + k], t);
-      L[a * p + b] = t;
-    }
-  for (int j = 0; j < p; ++j) {
-    double s = L[j * p + j];
-    for (int k = 0; k < j; ++k) s -= L[j * p + k] * L[j * p + k];
-    if (!(s > 0.0)) return kENotPD;
-    double ljj = sqrt(s);
-    L[j * p + j] = ljj;
-    for (int r = j + 1; r < p; ++r) {
-      double t = L[r * p + j];
-      for (int k = 0; k < j; ++k) t -= L[r * p + k] * L[j * p + k];
-      L[r * p + j] = t / ljj;
-    }
-    for (int c = j + 1; c < p; ++c) L[j * p + c] = 0.0;
-  }
-  double logdet = 0.0;
-  for (int a = 0; a < p; ++a) logdet += log(L[a * p + a]);
-  logdet *= 2.0;
-  // B = Omega^{-1} Delta by two triangular solves per column, in place in
-  // B's column (the forward solve leaves L^{-1} Delta there)
-  double* B = out + cl.B;
-  for (int k = 0; k < q; ++k) {
-    for (int a = 0; a < p; ++a) {
-      double t = Dl[a * q + k];
-      for (int b = 0; b < a; ++b) t -= L[a * p + b] * B[b * q + k];
-      B[a * q + k] = t / L[a * p + a];
-    }
-    for (int a = p - 1; a >= 0; --a) {
-      double t = B[a * q + k];
-      for (int b = a + 1; b < p; ++b) t -= L[b * p + a] * B[b * q + k];
-      B[a * q + k] = t / L[a * p + a];
-    }
-  }
-  // Lambda = I - Delta^T B (symmetrised), D = sqrt(diag), R = D^-1 Lambda D^-1;
-  // Lambda is built in R's slot and scaled there in place
-  double* lam = out + cl.Rm;
-  for (int k = 0; k < q; ++k)
-    for (int l = 0; l < q; ++l) {
-      double t = (k == l) ? 1.0 : 0.0;
-      for (int a = 0; a < p; ++a) t -= Dl[a * q + k] * B[a * q + l];
-      lam[k * q + l] = t;
-    }
-  for (int k = 0; k < q; ++k)
-    for (int l = 0; l < k; ++l) {
-      double t = 0.5 * (lam[k * q + l] + lam[l * q + k]);
-      lam[k * q + l] = t;
-      lam[l * q + k] = t;
-    }
-  double* D = out + cl.D;
-  double* Dinv = out + cl.Dinv;
-  for (int k = 0; k < q; ++k) {
-    if (!(lam[k * q + k] > 0.0)) return kENotPD;
-    D[k] = sqrt(lam[k * q + k]);
-    Dinv[k] = 1.0 / D[k];
-  }
-  double* C = out + cl.C;
-  double* Rm = out + cl.Rm;
-  for (int k = 0; k < q; ++k)
-    for (int l = 0; l < q; ++l) C[k * q + l] = (l <= k) ? lam[k * q + l] / (D[k] * D[l]) : 0.0;
-  for (int k = 0; k < q; ++k)
-    for (int l = 0; l < q; ++l) Rm[k * q + l] = (k == l) ? 1.0 : lam[k * q + l] / (D[k] * D[l]);
-  for (int j = 0; j < q; ++j) {
-    double s = C[j * q + j];
-    for (int k = 0; k < j; ++k) s -= C[j * q + k] * C[j * q + k];
-    if (!(s > 0.0)) return kENotPD;
-    double cjj = sqrt(s);
-    C[j * q + j] = cjj;
-    for (int r = j + 1; r < q; ++r) {
-      double t = C[r * q + j];
-      for (int k = 0; k < j; ++k) t -= C[r * q + k] * C[j * q + k];
-      C[r * q + j] = t / cjj;
-    }
-  }
-  const double a_ = 0.5 * (v + p);
-  out[cl.kappa] = log(w) + q * kLn2 + lgamma(a_) - lgamma(0.5 * v) - 0.5 * p * (log(v) + kLogPi) -
-                  0.5 * logdet;
-  out[cl.nu] = v;
-  out[cl.psi_a] = digamma_(a_);
-  return kOk;
-}
-
 __device__ bool pi_on_simplex(const double* pi, int g) {
   double s = 0.0;
   for (int k = 0; k < g; ++k) s += pi[k];
@@ -208,6 +109,7 @@ __device__ bool pi_on_simplex(const double* pi, int g) {
 // copies of Sigma_i and Delta_i), or 0 when that does not fit (the blocks
 // are then built in place in device memory)
 constexpr int kPrecompLdsMax = 48 * 1024;
+constexpr int kPrecompThreads = 256;  // block size of the precompute kernels
 __host__ __device__ inline int precompute_lds_doubles(int p, int q) {
   return CompLayout(p, q).stride + p * p + p * q;
 }
@@ -216,25 +118,212 @@ __host__ __device__ inline int precompute_lds_bytes(int p, int q, int g) {
   return b <= kPrecompLdsMax ? b : 0;
 }
 
-// Component i's block in LDS: Sigma_i and Delta_i are copied in first (the
-// copy's loads are independent, so they pipeline; the set-up's inner loops
-// then wait on LDS instead of device memory), then the block is copied out.
-__device__ __forceinline__ int precompute_component_lds(int p, int q, double w, double v,
-                                                        const double* mu_i, const double* Sg,
-                                                        const double* Dl, double* lds,
-                                                        double* out) {
-  const CompLayout cl(p, q);
-  double* sg = lds + cl.stride;
-  double* dl = sg + p * p;
-  for (int x = 0; x < p * p; ++x) sg[x] = Sg[x];
-  for (int x = 0; x < p * q; ++x) dl[x] = Dl[x];
-  const int rc = precompute_component(p, q, w, v, mu_i, sg, dl, lds);
-  for (int x = 0; x < cl.stride; ++x) out[x] = lds[x];
-  return rc;
+// Column-by-column Cholesky factor, in place, of the m x m lower triangle at
+// offset `off` of every live component's block (upper triangle already zero).
+// Column j takes two phases: every entry r >= j subtracts its j-term dot
+// product (the diagonal's result goes to piv[c]), then the column is divided
+// by the square root of the pivot.  A non-positive pivot marks the component
+// kENotPD.
+__device__ __forceinline__ void chol_columns(int m, int g, int off, double* base, int W,
+                                             int* rcs, double* piv) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < m; ++j) {
+    const int h = m - j;
+    for (int t = tid; t < g * h; t += nt) {
+      const int c = t / h, r = j + (t - c * h);
+      if (rcs[c] != kOk) continue;
+      double* L = base + (size_t)c * W + off;
+      double s = L[r * m + j];
+      for (int k = 0; k < j; ++k) s -= L[r * m + k] * L[j * m + k];
+      if (r == j)
+        piv[c] = s;
+      else
+        L[r * m + j] = s;
+    }
+    __syncthreads();
+    for (int t = tid; t < g * h; t += nt) {
+      const int c = t / h, r = j + (t - c * h);
+      if (rcs[c] != kOk) continue;
+      const double s = piv[c];
+      if (!(s > 0.0)) {
+        if (r == j) rcs[c] = kENotPD;
+        continue;
+      }
+      double* L = base + (size_t)c * W + off;
+      const double ljj = sqrt(s);
+      if (r == j)
+        L[j * m + j] = ljj;
+      else
+        L[r * m + j] = L[r * m + j] / ljj;
+    }
+    __syncthreads();
+  }
 }
 
-// lane i builds component i's block (in LDS when it fits, then copied out:
-// the serial O(p^3) set-up runs on LDS latency instead of device memory's)
+// The blocks of g components (pi, nu, mu, Sigma, Delta of component 0 at
+// the pointers given) on one block of threads.  The per-entry work runs in
+// phases separated by barriers: finiteness checks (and the copies of
+// Sigma_i, Delta_i into LDS) | Omega = Sigma + Delta Delta^T | its Cholesky
+// factor, column by column | the columns of B = Omega^{-1} Delta, two
+// triangular solves each, in place | Lambda = I - Delta^T B | its symmetric
+// part | D | C and R = D^{-1} Lambda D^{-1} | R's Cholesky factor | the
+// log normaliser.  Every entry is computed with the same operations in the
+// same order as a serial loop would.  lds holds g * precompute_lds_doubles
+// doubles, or is null: the blocks are then built in place in comp.  Returns,
+// on threads tid < g, component tid's status (kOk, or a code: its block is
+// then incomplete).
+__device__ int precompute_block(int p, int q, int g, const double* pi, const double* nu,
+                                const double* mu, const double* Sigma, const double* Delta,
+                                double* comp, double* lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const CompLayout cl(p, q);
+  const int W = lds ? precompute_lds_doubles(p, q) : cl.stride;
+  double* base = lds ? lds : comp;
+  __shared__ int rcs[kMaxG];
+  __shared__ int bad[kMaxG];
+  __shared__ double piv[kMaxG];
+  auto sg_of = [&](int c) -> const double* {
+    return lds ? lds + (size_t)c * W + cl.stride : Sigma + (size_t)c * p * p;
+  };
+  auto dl_of = [&](int c) -> const double* {
+    return lds ? lds + (size_t)c * W + cl.stride + p * p : Delta + (size_t)c * p * q;
+  };
+  if (tid < g) bad[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < g * p; t += nt)
+    if (!isfinite(mu[t])) bad[t / p] = 1;
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p);
+    const double v = Sigma[t];
+    if (!isfinite(v)) bad[c] = 1;
+    if (lds) lds[(size_t)c * W + cl.stride + (t - c * p * p)] = v;
+  }
+  for (int t = tid; t < g * p * q; t += nt) {
+    const int c = t / (p * q);
+    const double v = Delta[t];
+    if (!isfinite(v)) bad[c] = 1;
+    if (lds) lds[(size_t)c * W + cl.stride + p * p + (t - c * p * q)] = v;
+  }
+  __syncthreads();
+  if (tid < g) {
+    const double w = pi[tid], v = nu[tid];
+    int r = kOk;
+    if (!isfinite(v) || !isfinite(w))
+      r = kENonFinite;
+    else if (!(v > 0.0) || !(w > 0.0))
+      r = kEInval;
+    else if (bad[tid])
+      r = kENonFinite;
+    rcs[tid] = r;
+  }
+  __syncthreads();
+  // Omega's lower triangle (upper set to zero)
+  for (int t = tid; t < g * p * p; t += nt) {
+    const int c = t / (p * p), x = t - c * p * p, a = x / p, b = x - a * p;
+    if (rcs[c] != kOk) continue;
+    double* L = base + (size_t)c * W + cl.L;
+    if (b > a) {
+      L[x] = 0.0;
+      continue;
+    }
+    const double* Sg = sg_of(c);
+    const double* Dl = dl_of(c);
+    double s = Sg[a * p + b];
+    for (int k = 0; k < q; ++k) s = fma(Dl[a * q + k], Dl[b * q + k], s);
+    L[x] = s;
+  }
+  __syncthreads();
+  chol_columns(p, g, cl.L, base, W, rcs, piv);
+  // B = Omega^{-1} Delta, one column per thread: the forward solve leaves
+  // L^{-1} Delta in the column, the backward solve overwrites it
+  for (int t = tid; t < g * q; t += nt) {
+    const int c = t / q, k = t - c * q;
+    if (rcs[c] != kOk) continue;
+    const double* L = base + (size_t)c * W + cl.L;
+    double* B = base + (size_t)c * W + cl.B;
+    const double* Dl = dl_of(c);
+    for (int a = 0; a < p; ++a) {
+      double s = Dl[a * q + k];
+      for (int b = 0; b < a; ++b) s -= L[a * p + b] * B[b * q + k];
+      B[a * q + k] = s / L[a * p + a];
+    }
+    for (int a = p - 1; a >= 0; --a) {
+      double s = B[a * q + k];
+      for (int b = a + 1; b < p; ++b) s -= L[b * p + a] * B[b * q + k];
+      B[a * q + k] = s / L[a * p + a];
+    }
+  }
+  __syncthreads();
+  // Lambda = I - Delta^T B, built in R's slot
+  for (int t = tid; t < g * q * q; t += nt) {
+    const int c = t / (q * q), x = t - c * q * q, k = x / q, l = x - k * q;
+    if (rcs[c] != kOk) continue;
+    const double* B = base + (size_t)c * W + cl.B;
+    const double* Dl = dl_of(c);
+    double s = (k == l) ? 1.0 : 0.0;
+    for (int a = 0; a < p; ++a) s -= Dl[a * q + k] * B[a * q + l];
+    base[(size_t)c * W + cl.Rm + x] = s;
+  }
+  __syncthreads();
+  // symmetric part: the thread of (k, l), l < k, writes both entries
+  for (int t = tid; t < g * q * q; t += nt) {
+    const int c = t / (q * q), x = t - c * q * q, k = x / q, l = x - k * q;
+    if (rcs[c] != kOk || l >= k) continue;
+    double* lam = base + (size_t)c * W + cl.Rm;
+    const double s = 0.5 * (lam[k * q + l] + lam[l * q + k]);
+    lam[k * q + l] = s;
+    lam[l * q + k] = s;
+  }
+  __syncthreads();
+  // D = sqrt(diag Lambda)
+  for (int t = tid; t < g * q; t += nt) {
+    const int c = t / q, k = t - c * q;
+    if (rcs[c] != kOk) continue;
+    double* blk = base + (size_t)c * W;
+    const double d = blk[cl.Rm + k * q + k];
+    if (!(d > 0.0)) {
+      rcs[c] = kENotPD;
+      continue;
+    }
+    blk[cl.D + k] = sqrt(d);
+    blk[cl.Dinv + k] = 1.0 / blk[cl.D + k];
+  }
+  __syncthreads();
+  // C = lower triangle of D^{-1} Lambda D^{-1} (factored next), R in place
+  // over Lambda with a unit diagonal
+  for (int t = tid; t < g * q * q; t += nt) {
+    const int c = t / (q * q), x = t - c * q * q, k = x / q, l = x - k * q;
+    if (rcs[c] != kOk) continue;
+    double* blk = base + (size_t)c * W;
+    const double* D = blk + cl.D;
+    const double lv = blk[cl.Rm + x];
+    blk[cl.C + x] = (l <= k) ? lv / (D[k] * D[l]) : 0.0;
+    blk[cl.Rm + x] = (k == l) ? 1.0 : lv / (D[k] * D[l]);
+  }
+  __syncthreads();
+  chol_columns(q, g, cl.C, base, W, rcs, piv);
+  if (tid < g && rcs[tid] == kOk) {
+    double* blk = base + (size_t)tid * W;
+    double logdet = 0.0;
+    for (int a = 0; a < p; ++a) logdet += log(blk[cl.L + a * p + a]);
+    logdet *= 2.0;
+    const double w = pi[tid], v = nu[tid];
+    const double a_ = 0.5 * (v + p);
+    blk[cl.kappa] = log(w) + q * kLn2 + lgamma(a_) - lgamma(0.5 * v) -
+                    0.5 * p * (log(v) + kLogPi) - 0.5 * logdet;
+    blk[cl.nu] = v;
+    blk[cl.psi_a] = digamma_(a_);
+  }
+  __syncthreads();
+  if (lds)
+    for (int t = tid; t < g * cl.stride; t += nt) {
+      const int c = t / cl.stride, x = t - c * cl.stride;
+      comp[t] = lds[(size_t)c * W + x];
+    }
+  return tid < g ? rcs[tid] : kOk;
+}
+
+// all components' blocks on one block (in LDS when they fit, then copied out)
 __global__ void precompute_kernel(int p, int q, int g, const double* __restrict__ pi,
                                   const double* __restrict__ Sigma,
                                   const double* __restrict__ Delta, const double* __restrict__ mu,
@@ -242,19 +331,10 @@ __global__ void precompute_kernel(int p, int q, int g, const double* __restrict_
                                   int* status) {
   extern __shared__ double plds[];
   const int i = threadIdx.x;
-  CompLayout cl(p, q);
   if (i == 0 && !pi_on_simplex(pi, g)) set_status(status, kEInval, -1);
-  if (i >= g) return;
-  int rc;
-  if (precompute_lds_bytes(p, q, g))
-    rc = precompute_component_lds(p, q, pi[i], nu[i], mu + (size_t)i * p,
-                                  Sigma + (size_t)i * p * p, Delta + (size_t)i * p * q,
-                                  plds + (size_t)i * precompute_lds_doubles(p, q),
-                                  comp + (size_t)i * cl.stride);
-  else
-    rc = precompute_component(p, q, pi[i], nu[i], mu + (size_t)i * p, Sigma + (size_t)i * p * p,
-                              Delta + (size_t)i * p * q, comp + (size_t)i * cl.stride);
-  if (rc != kOk) set_status(status, rc, i);
+  const int rc = precompute_block(p, q, g, pi, nu, mu, Sigma, Delta, comp,
+                                  precompute_lds_bytes(p, q, g) ? plds : nullptr);
+  if (i < g && rc != kOk) set_status(status, rc, i);
 }
 
 // ---------------------------------------------------------------------------
