@@ -91,15 +91,15 @@ int64_t stats_per_block(int64_t n, int tile) {
 }
 
 // A launch of fewer than kSplitWaves pairs spreads each pair's points over
-// up to kSplitMax waves (FP64 form; each wave keeps at least 4 points per
-// lane).  The FP32 form keeps one wave per pair, so that the single-problem
-// path sums in the same order as the batched form (which serves many small
-// problems).
+// up to kSplitMax waves (each wave keeps at least 4 points per lane).  The
+// batched form keeps one wave per pair (its problems fill the chip
+// together), so a single-problem call sums in the batched form's order only
+// where it does not split: N < 512 or at least kSplitWaves pairs.
 constexpr int64_t kSplitWaves = 4096;
 constexpr int kSplitMax = 16;
 
-int split_of(int64_t pairs, int N, int prec) {
-  if (prec != CFUST_FP64 || pairs < 1 || pairs >= kSplitWaves) return 1;
+int split_of(int64_t pairs, int N) {
+  if (pairs < 1 || pairs >= kSplitWaves) return 1;
   int64_t K = (kSplitWaves + pairs - 1) / pairs;
   K = std::min<int64_t>(K, kSplitMax);
   K = std::min<int64_t>(K, N / 256);
@@ -150,7 +150,7 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m 
   off = align_up(off + (size_t)g * N * es);
   pl.o_pair = off;
   off = align_up(off + (size_t)(n > 0 ? n : 1) * g * pl.W * sizeof(double));
-  pl.split = split_of(n * g, N, prec);
+  pl.split = split_of(n * g, N);
   if (pl.split > 1) {
     // widest record: B with moments plus the two exact-nu integrals
     const size_t pw = 2 + 2 + q + (size_t)q * (q + 1) / 2 + 4;
@@ -349,27 +349,25 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   // keep the default occupancy (the ordering adds registers).  Above
   // kMaxQFull only the natural-order kernel exists (the entry points reject
   // the other forms there).
-  if constexpr (sizeof(T) == 8) {
-    if (pl.split > 1 && !pl.reorder) {
-      const int K = pl.split;
-      double* parts = ws.at<double>(pl.o_parts);
-      const unsigned pblocks = (unsigned)((pairs * K + 3) / 4);
-      if constexpr (MOM && Q <= kMaxQFull) {
-        if (pl.exact) {
-          pair_part_kernel<T, Q, MOM, OCC, true><<<pblocks, 256, 0, ws.st>>>(
-              y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status,
-              ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
-          pair_finish_kernel<T, Q, MOM, true><<<blocks, 256, 0, ws.st>>>(
-              y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
-          return;
-        }
+  if (pl.split > 1 && !pl.reorder) {
+    const int K = pl.split;
+    double* parts = ws.at<double>(pl.o_parts);
+    const unsigned pblocks = (unsigned)((pairs * K + 3) / 4);
+    if constexpr (MOM && Q <= kMaxQFull) {
+      if (pl.exact) {
+        pair_part_kernel<T, Q, MOM, OCC, true><<<pblocks, 256, 0, ws.st>>>(
+            y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status,
+            ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
+        pair_finish_kernel<T, Q, MOM, true><<<blocks, 256, 0, ws.st>>>(
+            y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
+        return;
       }
-      pair_part_kernel<T, Q, MOM, OCC><<<pblocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status);
-      pair_finish_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
-      return;
     }
+    pair_part_kernel<T, Q, MOM, OCC><<<pblocks, 256, 0, ws.st>>>(
+        y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status);
+    pair_finish_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
+        y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
+    return;
   }
   if constexpr (Q > kMaxQFull) {
     pair_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(

@@ -70,8 +70,12 @@ def test_batched_matches_oracle_fp64(dev, orc):
 
 
 def test_batched_graph_equals_eager_and_single(dev):
+    """Graph and eager batched runs agree bit for bit.  At N = 256 a
+    single-problem call keeps one wave per pair, as the batched form does,
+    so the two sum in the same order; at N = 1024 a single call spreads each
+    pair over several waves and agrees to FP32 rounding."""
     from paper_2005_06848_amd import native
-    probs, u = small_batch(7, 2, n_lo=200, n_hi=700, N=512)
+    probs, u = small_batch(7, 2, n_lo=200, n_hi=700, N=256)
     y, par, n, g = concat(probs)
     P = {k: T(v, dev) for k, v in par.items()}
     print("[gpu] batched fp32 graph vs eager", flush=True)
@@ -90,6 +94,17 @@ def test_batched_graph_equals_eager_and_single(dev):
                                      T(u, dev), max_iter=12, tol=1e-6, precision="fp32")
         assert single["n_iter"] == ng[k]
         np.testing.assert_allclose(tg[k, :ng[k] + 1], single["trace"], rtol=1e-12)
+    probs, u = small_batch(4, 5, n_lo=200, n_hi=700, N=1024)
+    y, par, n, g = concat(probs)
+    P = {k: T(v, dev) for k, v in par.items()}
+    print("[gpu] batched fp32 vs split single calls", flush=True)
+    fb, tb, nb_, sb = native.cfust_em_fit_batched(T(y, dev), n, g, P, T(u, dev), max_iter=6,
+                                                  tol=0.0, precision="fp32")
+    assert np.all(sb == 0) and np.all(nb_ == 6)
+    for k, c in enumerate(probs):
+        single = native.cfust_em_fit(T(c["y"], dev), {kk: T(v, dev) for kk, v in c["params"].items()},
+                                     T(u, dev), max_iter=6, tol=0.0, precision="fp32")
+        np.testing.assert_allclose(tb[k, :7], single["trace"], rtol=1e-6)
     cfg = native.cfust_batched_config()
     assert cfg["n_candidates"] >= 4 and cfg["waves_per_block"] in (1, 2, 4)
 

@@ -90,6 +90,8 @@ def test_fp32_full_config3_stats_vs_fp64(dev):
 
 
 def test_fp32_small_shapes(dev, orc):
+    """Launches of fewer than 4096 pairs: each pair's points are spread over
+    K = 2, 4 and 2 waves and the partial sums combined."""
     from paper_2005_06848_amd import inputs
     for shape in [(50, 2, 2, 2, 512), (40, 4, 4, 3, 1024), (30, 5, 5, 2, 700)]:
         n, p, q, g, N = shape
