@@ -7,9 +7,11 @@ conditional expectations), responsibilities, log-likelihood, the eight
 partial sums, and the M-step.  The metric is E-step (observation x component)
 evaluations per second.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build targets one
+Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on one
 GPU (the path would shard by observations with one all-reduce of the partial
-sums per iteration).
+sums per iteration).  The CPU baseline is the FP64 oracle on the machine's host
+cores, one thread per block of observations, with the single-thread rate
+beside it.
 """
 from __future__ import annotations
 
@@ -39,9 +41,9 @@ C_PHI, C_PHIINV, C_ACC = 40, 50, 20
 
 # HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (KiB per dispatch, scaled by the same counters on a plain copy kernel:
-# fetch x 1.99977, write x 0.99998); None when the kernel has changed since
+# fetch x 1.99978, write x 0.99999); None when the kernel has changed since
 # the counters were taken.
-TRAFFIC_BYTES_PER_LAUNCH = 43270089
+TRAFFIC_BYTES_PER_LAUNCH = 43747657
 # executed FP64 flops per launch of the same kernel from the SQ_INSTS_VALU_*_F64
 # counters (64 lanes, FMA = 2)
 EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.5937e11
@@ -299,6 +301,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-obs-per-thread", type=int, default=100,
+                    help="observations per thread of the all-cores oracle timing")
     ap.add_argument("--cpu-obs", type=int, default=500,
                     help="observations of the workload timed on the CPU oracle")
     ap.add_argument("--no-forms", action="store_true",
@@ -321,7 +325,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; use --gpus 1"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -425,9 +429,26 @@ def main():
         tc0 = time.perf_counter()
         oracle.estep(c["y"][:m], c["init"], c["u"], want=())
         tc = time.perf_counter() - tc0
-        cpu = {"value": round(m * g / tc, 3), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} observations of the workload ({m * g} pairs), full N={N}, "
-                         f"E-step incl. tau and partial sums, single thread, {tc:.1f} s"}
+        # all host cores: one thread per block of observations (the paper's
+        # J_l blocks); the oracle's C calls release the GIL
+        from concurrent.futures import ThreadPoolExecutor
+        nt = max(1, min(16, len(os.sched_getaffinity(0))))
+        per = max(1, min(args.cpu_obs_per_thread, (n - m) // nt))
+        blocks = [c["y"][m + t * per:m + (t + 1) * per] for t in range(nt)]
+        print(f"[bench] cpu baseline: oracle E-step on {nt} threads x {per} observations",
+              file=sys.stderr, flush=True)
+        with ThreadPoolExecutor(nt) as ex:
+            tm0 = time.perf_counter()
+            list(ex.map(lambda yb: oracle.estep(yb, c["init"], c["u"], want=()), blocks))
+            tm = time.perf_counter() - tm0
+        cpu = {"value": round(nt * per * g / tm, 3), "unit": "pairs/s", "cores": nt,
+               "kind": "oracle",
+               "sample": f"observations {m}..{m + nt * per - 1} of the workload "
+                         f"({nt * per * g} pairs), full N={N}, E-step incl. tau and partial "
+                         f"sums, {nt} threads of {per} observations each, {tm:.1f} s",
+               "single_thread": {"value": round(m * g / tc, 3), "cores": 1,
+                                 "sample": f"first {m} observations ({m * g} pairs), "
+                                           f"{tc:.1f} s"}}
 
     line = {
         "metric": "E-step (obs x comp) evals/sec at stated tol; FP32/surrogate vs FP64 QMC speedup",
