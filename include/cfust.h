@@ -57,8 +57,8 @@ extern "C" {
 #define CFUST_ENOMEM 5      /* workspace too small or allocation failed */
 
 #define CFUST_FP64 0        /* GHK integrand in float64 */
-#define CFUST_FP32 1        /* GHK integrand in float32 with compensated sums;
-                               everything else stays float64 */
+#define CFUST_FP32 1        /* GHK integrand in float32, its weight and moment
+                               sums in float64; everything else stays float64 */
 
 #define CFUST_NU_OSL 0      /* nu update with the one-step-late E[log W | y] */
 #define CFUST_NU_EXACT_FD 1 /* nu update with the exact E[log W | y] = psi(a) - log b

@@ -395,7 +395,11 @@ __global__ void chi_kernel(const double* __restrict__ comp, int comp_stride, int
 // ---------------------------------------------------------------------------
 // accumulators of GHK weights carried with a per-lane power-of-two reference
 // ---------------------------------------------------------------------------
-// FP64: plain sums.  FP32: Neumaier-compensated sums.
+// FP64: plain sums.  FP32: the sums are kept in FP64.  The product of two
+// floats is exact in double, so a moment term costs one FP64 fma, which
+// issues at the rate of an FP32 fma; the only rounding is the FP64 sum's
+// (a Neumaier-compensated FP32 sum takes about seven instructions per term
+// and is less accurate).
 template <typename T>
 struct Acc;
 
@@ -404,29 +408,19 @@ struct Acc<double> {
   double s;
   __device__ __forceinline__ void zero() { s = 0.0; }
   __device__ __forceinline__ void add(double x) { s += x; }
+  __device__ __forceinline__ void add_prod(double a, double b) { s += a * b; }
   __device__ __forceinline__ void scale(double f) { s *= f; }
   __device__ __forceinline__ double value() const { return s; }
 };
 
 template <>
 struct Acc<float> {
-  float s, c;
-  __device__ __forceinline__ void zero() {
-    s = 0.0f;
-    c = 0.0f;
-  }
-  __device__ __forceinline__ void add(float x) {
-    float t = s + x;
-    float big = fabsf(s) >= fabsf(x) ? s : x;
-    float small = fabsf(s) >= fabsf(x) ? x : s;
-    c += (big - t) + small;
-    s = t;
-  }
-  __device__ __forceinline__ void scale(float f) {
-    s *= f;
-    c *= f;
-  }
-  __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(float x) { s += (double)x; }
+  __device__ __forceinline__ void add_prod(float a, float b) { s = fma((double)a, (double)b, s); }
+  __device__ __forceinline__ void scale(float f) { s *= (double)f; }
+  __device__ __forceinline__ double value() const { return s; }
 };
 
 // lowest reference exponent (no point seen yet) and the power-of-two shift of
@@ -518,13 +512,13 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
 #pragma unroll
       for (int m = 0; m < Q; ++m) eh[m] = eps[m] * rs;
 #pragma unroll
-      for (int m = 0; m < Q; ++m) b1[m].add(wgt * eh[m]);
+      for (int m = 0; m < Q; ++m) b1[m].add_prod(wgt, eh[m]);
       int t = 0;
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         T wa = wgt * eh[a];
 #pragma unroll
-        for (int b = a; b < Q; ++b) b2[t++].add(wa * eh[b]);
+        for (int b = a; b < Q; ++b) b2[t++].add_prod(wa, eh[b]);
       }
     }
   }

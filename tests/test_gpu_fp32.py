@@ -1,5 +1,5 @@
-"""FP32 form: GHK integrand and moment accumulation in float32 (compensated
-sums), everything else in float64, against the FP64 oracle.
+"""FP32 form: GHK integrand in float32 (its weight and moment sums in
+float64), everything else in float64, against the FP64 oracle.
 
 Bars: 1e-4 on the moments (e2, e3, e4 and the tau-weighted statistics) and
 1e-7 relative on the log-likelihood; tau and log f are reported too."""
