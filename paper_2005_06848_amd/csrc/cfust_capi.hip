@@ -333,13 +333,16 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   if (pairs == 0) return;
   unsigned blocks = (unsigned)((pairs + 3) / 4);
   // Resident waves per SIMD asked of the compiler.  FP64 q <= 4: four (2.5%
-  // faster at p=q=4, 48 B/lane of spill outside the point loop).  q = 5, 6:
-  // three for FP64 and four for FP32 (3.8% and 2.3% faster at p=q=6 than the
-  // compiler's two and three, despite 192 and 176 B/lane of spill).  Larger
-  // q keep the compiler's choice.
-  constexpr int OCC = (sizeof(T) == 8 && Q <= 4) ? 4
-                      : (Q == 5 || Q == 6)       ? (sizeof(T) == 8 ? 3 : 4)
-                                                 : 0;
+  // faster at p=q=4, 48 B/lane of spill outside the point loop).  FP64
+  // q = 5, 6: three (3.8% faster at p=q=6 than the compiler's two, despite
+  // 192 B/lane of spill).  FP32 q = 5: four (7.6% faster than the
+  // compiler's choice at p=q=5).  FP32 q = 6 and larger q keep the
+  // compiler's choice (at p=q=6 four waves spill 176 B/lane and are 8%
+  // slower).
+  constexpr int OCC = (sizeof(T) == 8 && Q <= 4)        ? 4
+                      : (sizeof(T) == 8 && (Q == 5 || Q == 6)) ? 3
+                      : (sizeof(T) == 4 && Q == 5)             ? 4
+                                                               : 0;
   const double* comp = ws.at<double>(pl.o_comp);
   double* pairs_out = ws.at<double>(pl.o_pair);
   int* status = ws.at<int>(pl.o_status);
