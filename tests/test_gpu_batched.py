@@ -69,6 +69,27 @@ def test_batched_matches_oracle_fp64(dev, orc):
             assert np.max(np.abs(fitted[k][key] - r)) <= 1e-8 * max(np.max(np.abs(r)), 1e-300), (k, key)
 
 
+
+def test_batched_large_blocks_fp64(dev, orc):
+    """p = q = 8: the batched set-up and M-step size their LDS for 16
+    components (51.7 and 69.6 KB), more than 48 KB, so both build the blocks
+    in device memory; 4 EM iterations of 3 problems against the oracle."""
+    from paper_2005_06848_amd import native
+    probs, u = small_batch(3, 4, p=8, q=8, n_lo=250, n_hi=400, N=128)
+    y, par, n, g = concat(probs)
+    print("[gpu] batched fp64 p=q=8", flush=True)
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(
+        T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()}, T(u, dev), max_iter=4, tol=0.0,
+        precision="fp64")
+    assert np.all(status == 0), status
+    fitted = split({k: v.cpu().numpy() for k, v in fit.items() if k in par}, g)
+    for k, c in enumerate(probs):
+        ref = orc.em_fit(c["y"], c["params"], u, max_iter=4, tol=0.0)
+        np.testing.assert_allclose(trace[k, :5], ref["trace"], rtol=1e-10)
+        for key in ("pi", "mu", "Sigma", "Delta", "nu"):
+            r = ref[key]
+            assert np.max(np.abs(fitted[k][key] - r)) <= 1e-8 * max(np.max(np.abs(r)), 1e-300), (k, key)
+
 def test_batched_graph_equals_eager_and_single(dev):
     """Graph and eager batched runs agree bit for bit.  At N = 256 a
     single-problem call keeps one wave per pair, as the batched form does,

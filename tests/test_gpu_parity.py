@@ -278,6 +278,96 @@ def test_deterministic(dev):
     assert a["loglik"] == b["loglik"]
 
 
+
+def test_setup_error_paths(dev, orc):
+    """Every failure of the per-component set-up reports the oracle's code (and
+    the failing component): non-finite Sigma, Delta or mu (ENONFINITE); pi off the simplex
+    (EINVAL); a non-positive diagonal of Lambda, and an indefinite R with a
+    positive diagonal, which fails in R's Cholesky factor (ENOTPD).  The
+    last two have an indefinite Sigma with Omega = Sigma + Delta Delta^T
+    positive definite.  Each case is set up on the host; the kernels finish
+    and report a status.  The E-step and the M-step-free log-likelihood both
+    take the set-up, and so does the batched form (one poisoned problem)."""
+    from paper_2005_06848_amd import inputs, native
+
+    def put(name, comp, idx, val):
+        def edit(par):
+            par[name][comp][idx] = val
+        return edit
+
+    def lam_diag(par):
+        par["Sigma"][1] = np.diag([-0.5, 1.0])
+        par["Delta"][1] = np.diag([1.0, 0.0])
+
+    def r_indefinite(par):
+        # Lambda = I - Omega^{-1} with Delta = I: [[0.1, -0.3], [-0.3, 0.8]]
+        par["Sigma"][1] = np.linalg.inv(np.array([[0.9, 0.3], [0.3, 0.2]])) - np.eye(2)
+        par["Delta"][1] = np.eye(2)
+
+    def pi_off(par):
+        par["pi"][0] += 1e-6
+
+    c = inputs.random_case(17, 10, 2, 2, 2, 64)
+    cases = [("Sigma NaN", put("Sigma", 1, (0, 1), np.nan), native.ENONFINITE, 1),
+             ("Delta Inf", put("Delta", 0, (1, 0), np.inf), native.ENONFINITE, 0),
+             ("mu NaN", put("mu", 1, 1, np.nan), native.ENONFINITE, 1),
+             ("pi off the simplex", pi_off, native.EINVAL, None),
+             ("Lambda diagonal", lam_diag, native.ENOTPD, 1),
+             ("R indefinite", r_indefinite, native.ENOTPD, 1)]
+    for name, edit, code, bad in cases:
+        par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+        edit(par)
+        with pytest.raises(orc.OracleError) as eo:
+            orc.estep(c["y"], par, c["u"])
+        assert eo.value.code == code, (name, eo.value.code)
+        print(f"[gpu] set-up error path: {name}", flush=True)
+        for call in (native.cfust_estep, native.cfust_loglik):
+            with pytest.raises(native.CfustError) as e:
+                call(T(c["y"], dev), gpu_params(par, dev), T(c["u"], dev))
+            assert e.value.code == code, (name, call.__name__, e.value.code)
+            # cfust_loglik has no bad-component output
+            if bad is not None and call is native.cfust_estep:
+                assert e.value.bad == bad, (name, e.value.bad)
+    # the batched form: one problem with an indefinite R fails alone
+    probs = [inputs.random_case(300 + k, 40, 2, 2, 2, 256) for k in range(3)]
+    r_indefinite(probs[1]["params"])
+    y = np.concatenate([q["y"] for q in probs])
+    P = {k: T(np.concatenate([q["params"][k] for q in probs]), dev)
+         for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    print("[gpu] set-up error path: batched", flush=True)
+    _, _, _, st = native.cfust_em_fit_batched(T(y, dev), [40, 40, 40], [2, 2, 2], P,
+                                              T(probs[0]["u"], dev), max_iter=2, tol=0.0,
+                                              precision="fp64")
+    assert st[1] == native.ENOTPD and st[0] == 0 and st[2] == 0, st
+    # a good call afterwards still works
+    gpu = run_pair(dev, c["y"], c["params"], c["u"])
+    assert np.all(np.isfinite(gpu["tau"]))
+
+
+@pytest.mark.parametrize("shape", [(400, 32, 2, 3, 128), (300, 12, 12, 7, 64), (400, 8, 8, 16, 64)])
+def test_large_blocks_fallback_paths(dev, orc, shape):
+    """Shapes whose component blocks do not fit the set-up's and the M-step's
+    48 KB of LDS (52.6/80.2 KB, 50.0/67.2 KB and 51.7/69.6 KB): both kernels
+    then build them in device memory with the same phases.  E-step,
+    log-likelihood and M-step against the oracle.  The M-step bar is 1e-11:
+    with components of 5-60 units of responsibility in up to 32 dimensions,
+    the oracle's own M-step moves by up to 1e-13 under 1e-15 relative noise
+    in the statistics."""
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    n, p, q, g, N = shape
+    c = inputs.random_case(400 + p + q + g, n, p, q, g, N)
+    ref = orc.estep(c["y"], c["params"], c["u"])
+    gpu = run_pair(dev, c["y"], c["params"], c["u"])
+    check(parity.estep_errors(gpu, ref, p, q))
+    ll = float(native.cfust_loglik(T(c["y"], dev), gpu_params(c["params"], dev), T(c["u"], dev)).cpu()[0])
+    assert ll == pytest.approx(ref["loglik"], rel=TOL)
+    print(f"[gpu] mstep p={p} q={q} g={g}", flush=True)
+    new_ref = orc.mstep(ref["stats"], n, c["params"])
+    new_gpu = native.cfust_mstep(T(ref["stats"], dev), n, gpu_params(c["params"], dev))
+    err = parity.params_rel_err({k: v.cpu().numpy() for k, v in new_gpu.items()}, new_ref)
+    assert max(err.values()) < 1e-11, err
+
 @pytest.mark.parametrize("shape", [(7, 3, 3, 2, 1000), (40, 4, 4, 3, 4096), (90, 2, 2, 2, 515),
                                    (33, 6, 5, 2, 2048)])
 def test_split_waves_parity(dev, orc, shape):
