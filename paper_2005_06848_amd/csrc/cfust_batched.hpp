@@ -227,7 +227,7 @@ __global__ void baitken_kernel(BatchDev b, int max_iter, double tol) {
     b.iter[k] = t + 1;
 }
 
-// one block per problem, lane i = component i
+// one block per problem: its components' M-step (mstep_body)
 __global__ void bmstep_kernel(BatchDev b, const double* __restrict__ stats, int nu_fixed,
                               int fix_delta_zero, double nu_lo, double nu_hi, double* pi,
                               double* mu, double* Sigma, double* Delta, double* nu,

@@ -463,9 +463,13 @@ void mlp_forward(const cfust_surrogate* s, const bf16* X, int64_t rows, bf16* co
   }
 }
 
-// inference: all four layers in one kernel per 64 rows (rows multiple of 64)
+// inference: all four layers in one kernel per 16 kInferRT rows (the last
+// block ragged)
 void mlp_infer(const cfust_surrogate* s, const bf16* X, int64_t rows, float* P, hipStream_t st) {
-  if (rows > 0) mlp_infer_kernel<<<(unsigned)(rows / 64), 256, 0, st>>>(X, s->wb, s->params, P);
+  constexpr int R = 16 * kInferRT;
+  if (rows > 0)
+    mlp_infer_kernel<kInferRT><<<(unsigned)((rows + R - 1) / R), 256, 0, st>>>(X, rows, s->wb,
+                                                                              s->params, P);
 }
 
 template <typename X>

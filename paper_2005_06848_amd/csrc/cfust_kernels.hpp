@@ -1381,7 +1381,8 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// M-step (section 3.3, Algorithm 3): one lane per component.
+// M-step (section 3.3, Algorithm 3): one block, phased over the entries of
+// all components (mstep_body).
 // CM order: mu (old Delta), Delta (new mu), Sigma, then nu and pi.
 // ---------------------------------------------------------------------------
 __device__ bool chol_small(double* A, int m) {

@@ -204,50 +204,56 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const bf16* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: one 256-thread block takes 64 rows through all four
-// layers.  The activations of the block's rows stay in LDS (one 64 x 256 bf16
-// tile, overwritten layer by layer after a barrier); weights are read
+// Fused inference: one 256-thread block takes 16 RT rows through all four
+// layers.  The activations of the block's rows stay in LDS (one 16 RT x 256
+// bf16 tile, overwritten layer by layer after a barrier); weights are read
 // k-contiguous from global memory (L2-resident, [out][in] layout).  Wave w
-// owns output columns [w N/4, (w+1) N/4) of every layer and all 64 rows, as
-// 4 x (N/64) tiles of v_mfma_f32_16x16x32_bf16 (gfx950): lane l supplies
-// A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16] and receives
-// D[4(l/16) + i][l%16], i = 0..3.  HBM traffic is the input rows (bf16) and
-// the fp32 outputs only.  rows must be a multiple of 64.
+// owns output columns [w N/4, (w+1) N/4) of every layer and all the block's
+// rows, as RT x (N/64) tiles of v_mfma_f32_16x16x32_bf16 (gfx950): lane l
+// supplies A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16] and receives
+// D[4(l/16) + i][l%16], i = 0..3.  A wave's weight loads are shared by its
+// RT row tiles, so more rows per block mean fewer L2 bytes per MFMA.  HBM
+// traffic is the input rows (bf16) and the fp32 outputs only.  Rows at or
+// past `rows` are zero on input and never stored.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kFusedLd = kMlpHid + 8;  // LDS row pitch (528 bytes)
+// row tiles per block: 64 rows.  128 rows (half the L2 weight bytes per
+// MFMA, half the blocks per CU) made the n = 1e6 network E-step 13% slower;
+// the kernel is bound by latency, not by L2.
+constexpr int kInferRT = 4;
 
-template <int K, int N, bool LAST>
+template <int K, int N, bool LAST, int RT>
 __device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* __restrict__ W,
                                             const float* __restrict__ b, float* __restrict__ P,
-                                            int64_t row0, int lane, int w) {
+                                            int64_t row0, int64_t rows, int lane, int w) {
   constexpr int CT = N / 64;  // 16-column tiles per wave
   const int colbase = w * (N / 4);
   const int r16 = lane & 15, kg = lane >> 4;
-  float4_t acc[4][CT];
+  float4_t acc[RT][CT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8_t a[4], bw[CT];
+    bf16x8_t a[RT], bw[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j)
       bw[j] = *reinterpret_cast<const bf16x8_t*>(W + (size_t)(colbase + 16 * j + r16) * K + k0 +
                                                  8 * kg);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
       a[i] = *reinterpret_cast<const bf16x8_t*>(Hs + (16 * i + r16) * kFusedLd + k0 + 8 * kg);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < CT; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[j], acc[i][j], 0, 0, 0);
   }
   __syncthreads();  // every wave has read this layer's input
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
       const int col = colbase + 16 * j + r16;
@@ -256,39 +262,50 @@ __device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* _
       for (int t = 0; t < 4; ++t) {
         const int row = 16 * i + 4 * kg + t;
         const float z = acc[i][j][t] + bias;
-        if (LAST)
-          P[(size_t)(row0 + row) * kMlpPad + col] = z;
-        else
+        if (LAST) {
+          if (row0 + row < rows) P[(size_t)(row0 + row) * kMlpPad + col] = z;
+        } else {
           Hs[row * kFusedLd + col] = f2bf(z * sigmoid_f(z));
+        }
       }
     }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void mlp_infer_kernel(const bf16* __restrict__ X,
+template <int RT>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const bf16* __restrict__ X, int64_t rows,
                                                         const bf16* __restrict__ wb,
                                                         const float* __restrict__ params,
                                                         float* __restrict__ P) {
-  __shared__ __attribute__((aligned(16))) bf16 Hs[64 * kFusedLd];
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  constexpr int R = 16 * RT;  // rows per block
+  static_assert(R % 64 == 0, "the input copy moves 64 rows per pass");
+  __shared__ __attribute__((aligned(16))) bf16 Hs[R * kFusedLd];
+  const int64_t row0 = (int64_t)blockIdx.x * R;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  {
-    const int r = tid >> 2, c = (tid & 3) * 16;
-    const uint4* src = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * kMlpPad + c);
+  // the block's input rows, 16 bf16 (one uint4 pair) per thread per pass
+#pragma unroll
+  for (int pass = 0; pass < R / 64; ++pass) {
+    const int r = 64 * pass + (tid >> 2), c = (tid & 3) * 16;
     uint4* dst = reinterpret_cast<uint4*>(Hs + r * kFusedLd + c);
-    dst[0] = src[0];
-    dst[1] = src[1];
+    if (row0 + r < rows) {
+      const uint4* src = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * kMlpPad + c);
+      dst[0] = src[0];
+      dst[1] = src[1];
+    } else {
+      dst[0] = uint4{0u, 0u, 0u, 0u};
+      dst[1] = uint4{0u, 0u, 0u, 0u};
+    }
   }
   __syncthreads();
-  fused_layer<mlp_k(0), mlp_n(0), false>(Hs, wb + MlpOff<0>::wb, params + MlpOff<0>::b, nullptr,
-                                         row0, lane, w);
-  fused_layer<mlp_k(1), mlp_n(1), false>(Hs, wb + MlpOff<1>::wb, params + MlpOff<1>::b, nullptr,
-                                         row0, lane, w);
-  fused_layer<mlp_k(2), mlp_n(2), false>(Hs, wb + MlpOff<2>::wb, params + MlpOff<2>::b, nullptr,
-                                         row0, lane, w);
-  fused_layer<mlp_k(3), mlp_n(3), true>(Hs, wb + MlpOff<3>::wb, params + MlpOff<3>::b, P, row0,
-                                        lane, w);
+  fused_layer<mlp_k(0), mlp_n(0), false, RT>(Hs, wb + MlpOff<0>::wb, params + MlpOff<0>::b,
+                                             nullptr, row0, rows, lane, w);
+  fused_layer<mlp_k(1), mlp_n(1), false, RT>(Hs, wb + MlpOff<1>::wb, params + MlpOff<1>::b,
+                                             nullptr, row0, rows, lane, w);
+  fused_layer<mlp_k(2), mlp_n(2), false, RT>(Hs, wb + MlpOff<2>::wb, params + MlpOff<2>::b,
+                                             nullptr, row0, rows, lane, w);
+  fused_layer<mlp_k(3), mlp_n(3), true, RT>(Hs, wb + MlpOff<3>::wb, params + MlpOff<3>::b, P,
+                                            row0, rows, lane, w);
 }
 
 // out[i] = sum_s part[s * n + i] (fixed order)
