@@ -263,6 +263,33 @@ def batched_small(args, native, torch, np, inputs, dev):
     return res
 
 
+def em_fit_form(args, native, torch, np, inputs, dev):
+    """The 50-iteration EM fit of the benchmark workload (n=20000, p=q=4,
+    g=3, N=4096) from its k-means start, tolerance 1e-6 on the Aitken
+    limit, through cfust_em_fit (graph-captured iterations), FP64 and FP32
+    integrands: wall time, iterations, time per iteration and the final l."""
+    c = inputs.config(2)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y, u = T(c["y"]), T(c["u"])
+    res = {"workload": "cfust-em n=20000 p=4 q=4 g=3 N=4096 (k-means start), max 50 iterations, "
+                       "tol 1e-6"}
+    for prec in ("fp64", "fp32"):
+        print(f"[bench] em fit: workload 2 {prec}", file=sys.stderr, flush=True)
+        par = {k: T(v) for k, v in c["init"].items()}
+        native.cfust_em_fit(y, par, u, max_iter=1, tol=1e-6, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fit = native.cfust_em_fit(y, par, u, max_iter=50, tol=1e-6, precision=prec)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        it = int(fit["n_iter"])
+        tr = np.asarray(fit["trace"])
+        res[prec] = {"seconds": round(ts, 4), "iterations": it,
+                     "ms_per_iteration": round(1e3 * ts / max(it, 1), 3),
+                     "loglik_start": float(tr[0]), "loglik_final": float(tr[it])}
+    return res
+
+
 def high_q_form(args, native, torch, np, inputs, dev):
     """High-q stress case (workload 6: n=202, p=q=11, g=2, N=8192): 100 EM
     iterations from the k-means start, FP64 and FP32 integrands.  From this
@@ -313,6 +340,8 @@ def parse():
     ap.add_argument("--batched-iters", type=int, default=50)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-form leg (n=1000000, p=q=6, g=4, N=8192)")
+    ap.add_argument("--no-fit", action="store_true",
+                    help="skip the 50-iteration EM fit of the benchmark workload")
     ap.add_argument("--no-high-q", action="store_true",
                     help="skip the high-q stress leg (100 EM iterations, n=202, p=q=11, g=2, N=8192)")
     ap.add_argument("--no-sequential", action="store_true",
@@ -419,6 +448,9 @@ def main():
     if not args.no_high_q:
         forms = forms or {}
         forms["high_q"] = high_q_form(args, native, torch, np, inputs, dev)
+    if not args.no_fit:
+        forms = forms or {}
+        forms["em_fit"] = em_fit_form(args, native, torch, np, inputs, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
