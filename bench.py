@@ -9,7 +9,7 @@ evaluations per second.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: the library runs on one
 GPU (the path would shard by observations with one all-reduce of the partial
-sums per iteration).  The CPU baseline is the FP64 oracle on the machine's host
+sums per iteration).  The CPU baseline is the FP64 oracle on the host's
 cores, one thread per block of observations, with the single-thread rate
 beside it.
 """

@@ -242,7 +242,7 @@ def test_out_of_range_pairs_fall_back_to_ghk(dev):
 
 # ---------------------------------------------------------------------------
 # the trained network shipped with the package (trained on the GPU by
-# ``python -m paper_2005_06848_amd.surrogate``), judged by the GHK kernel
+# ``python -m paper_2005_06848_amd.surrogate``), checked against the GHK kernel
 # ---------------------------------------------------------------------------
 def _shipped():
     from paper_2005_06848_amd import native, surrogate
