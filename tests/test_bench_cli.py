@@ -1,0 +1,35 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal and the algorithmic
+flop model behind the roofline line."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2, (r.returncode, r.stderr[-500:])
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_flop_model_per_pair():
+    """F_pair = N (F_A + F_B) + 2p^2 + 2pq + 40 with the nominal costs of the
+    special functions (Phi 40, Phi^-1 50, scaled accumulation 20 flops):
+    integral A draws q - 1 coordinates, integral B all q and adds the moment
+    sums q(q+1) + 4q.  At p = q = 4, N = 4096 that is 3,219,560 flops."""
+    import bench
+    assert (bench.C_PHI, bench.C_PHIINV, bench.C_ACC) == (40, 50, 20)
+    assert bench.flops_per_pair(4, 4, 4096) == 3219560
+    # by hand for p = q = 1, N = 1: A = 1+1+40+0+20, B = 1+1+40+50+2+4+20
+    assert bench.flops_per_pair(1, 1, 1) == 62 + 118 + 2 + 2 + 40
+    # linear in N with slope F_A + F_B
+    d = bench.flops_per_pair(6, 6, 2) - bench.flops_per_pair(6, 6, 1)
+    q = 6
+    fa = q * q + q + 40 * q + 50 * (q - 1) + 20
+    fb = q * q + q + 40 * q + 50 * q + q * (q + 1) + 4 * q + 20
+    assert d == fa + fb
