@@ -186,6 +186,8 @@ def batched_form(args, native, torch, np, inputs, dev):
     N=4096, FP32 integrand), one device-driven loop with hipGraph-captured
     iterations and autotuned launch shape; compared with fitting the same
     starts one after another through the single-problem entry point."""
+    if args.no_batched_large:
+        return {"small_problems": batched_small(args, native, torch, np, inputs, dev)}
     print("[bench] batched: generating 64 starts", file=sys.stderr, flush=True)
     probs = inputs.batched_problems(64)
     u = inputs.qmc_points(4096, 5)
@@ -340,6 +342,8 @@ def parse():
     ap.add_argument("--batched-iters", type=int, default=50)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-form leg (n=1000000, p=q=6, g=4, N=8192)")
+    ap.add_argument("--no-batched-large", action="store_true",
+                    help="batched leg: only the 256 small problems, not the 64 starts")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the 50-iteration EM fit of the benchmark workload")
     ap.add_argument("--no-high-q", action="store_true",
