@@ -91,9 +91,12 @@ def test_fp32_full_config3_stats_vs_fp64(dev):
 
 def test_fp32_small_shapes(dev, orc):
     """Launches of fewer than 4096 pairs: each pair's points are spread over
-    K = 2, 4 and 2 waves and the partial sums combined."""
+    K = 2, 4 and 2 waves and the partial sums combined; with N < 512 (the
+    last two shapes) each pair keeps one wave, which at q = 5 is the
+    four-wave kernel."""
     from paper_2005_06848_amd import inputs
-    for shape in [(50, 2, 2, 2, 512), (40, 4, 4, 3, 1024), (30, 5, 5, 2, 700)]:
+    for shape in [(50, 2, 2, 2, 512), (40, 4, 4, 3, 1024), (30, 5, 5, 2, 700),
+                  (40, 5, 5, 3, 256), (40, 6, 6, 2, 300)]:
         n, p, q, g, N = shape
         cc = inputs.random_case(500 + n, n, p, q, g, N)
         g32 = run(dev, cc["y"], cc["params"], cc["u"], "fp32")
