@@ -88,11 +88,20 @@ def test_exact_fp32_form(dev, orc):
     1e-4 relative like the other moments."""
     from paper_2005_06848_amd import inputs
     import parity
-    c = inputs.random_case(41, 200, 4, 3, 2, 2048)
-    ref = orc.estep(c["y"], c["params"], c["u"], nu_mode=orc.NU_EXACT_FD)
-    got = gpu_estep(dev, c["y"], c["params"], c["u"], precision="fp32")
-    err = parity.estep_errors(got, ref, 4, 3)
-    assert err["e1"] < 1e-4 and err["stats"] < 1e-4 and err["loglik"] < 1e-7, err
+    # (200, 4, 3, 2, 2048): 400 pairs over 8 waves each; (100, 5, 5, 2, 1024):
+    # 200 pairs over 4 waves each, the q = 5 four-wave split kernel.  e1's
+    # central difference divides the FP32-level difference of the two log
+    # integrals (about 1e-7 per coordinate) by 2 delta = 2e-3 a, so its error
+    # grows with q: the bar is 1e-4 at q = 3 and 3e-4 at q = 5 (measured
+    # 1.3e-4; e2..e4 stay near 2e-6).  The moment and l bars are the form's.
+    for seed, (n, p, q, g, N), e1_bar in ((41, (200, 4, 3, 2, 2048), 1e-4),
+                                          (43, (100, 5, 5, 2, 1024), 3e-4)):
+        c = inputs.random_case(seed, n, p, q, g, N)
+        ref = orc.estep(c["y"], c["params"], c["u"], nu_mode=orc.NU_EXACT_FD)
+        got = gpu_estep(dev, c["y"], c["params"], c["u"], precision="fp32")
+        err = parity.estep_errors(got, ref, p, q)
+        assert err["e1"] < e1_bar and err["stats"] < 1e-4 and err["loglik"] < 1e-7, (q, err)
+        assert max(err["e2"], err["e3"], err["e4"]) < 1e-4, (q, err)
 
 
 def test_exact_em_is_monotone(dev):
