@@ -219,3 +219,44 @@ def test_multistart_algorithm1_matches_oracle(dev):
     np.testing.assert_allclose(fit["trace"], ref["trace"], rtol=1e-9)
     err = parity.params_rel_err({k: fit[k].cpu().numpy() for k in ("pi", "mu", "Sigma", "Delta", "nu")}, ref)
     assert max(err.values()) < 1e-9, err
+
+
+@pytest.mark.timeout(600)
+def test_batched_workload4_two_full_size_starts_vs_oracle(dev):
+    """Two full-size starts of the 64-start workload (the two with the
+    fewest pairs: n = 10022, g = 2 and n = 8527, g = 3; p = q = 5, N = 4096)
+    in one batched FP64 launch sequence, 2 EM iterations, against the same
+    iterations composed from the oracle's E-step (over all observations) and
+    M-step: the l trace and the parameters.  The paper's criterion for the
+    parallel runs is estimates almost identical to the serial ones with the
+    same final clustering; the MAP labels are compared too."""
+    from paper_2005_06848_amd import inputs, native
+    import oracle_pool
+    import parity
+    probs = inputs.batched_problems(64)
+    pick = sorted(range(64), key=lambda k: probs[k]["n"] * probs[k]["g"])[:2]
+    sel = [probs[k] for k in pick]
+    u = inputs.qmc_points(4096, 5)
+    y = np.concatenate([c["y"] for c in sel])
+    par = {k: np.concatenate([c["init"][k] for c in sel]) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    n = [c["n"] for c in sel]
+    g = [c["g"] for c in sel]
+    print(f"[gpu] batched fp64, workload 4 starts {pick}: n={n} g={g}", flush=True)
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(
+        T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()}, T(u, dev), max_iter=2, tol=0.0,
+        precision="fp64")
+    assert np.all(status == 0), status
+    fitted = split({k: v.cpu().numpy() for k, v in fit.items() if k in par}, g)
+    for k, c in enumerate(sel):
+        print(f"[cpu] oracle, start {pick[k]}: 2 EM iterations over all {c['n']} observations",
+              flush=True)
+        ref = oracle_pool.em_iterations(c["y"], c["init"], u, 2)
+        assert n_iter[k] == 2
+        np.testing.assert_allclose(trace[k, :3], ref["trace"], rtol=1e-10)
+        err = parity.params_rel_err(fitted[k], ref)
+        assert max(err.values()) < 1e-9, (k, err)
+        # MAP labels at the two fitted parameter sets (E-steps on the GPU)
+        lab = [native.cfust_estep(T(c["y"], dev), {kk: T(pp[kk], dev) for kk in par}, T(u, dev),
+                                  want=("tau",))["tau"].cpu().numpy().argmax(1)
+               for pp in (fitted[k], ref)]
+        assert np.array_equal(lab[0], lab[1])

@@ -128,35 +128,21 @@ def test_estep_config2_reduced(dev, orc):
     check(err)
 
 
-def test_estep_config2_full_sampled(dev, orc):
-    """Full config 2 (n=20000) in the benchmark's launch configuration: sampled
-    pairs against the oracle; the statistics and log-likelihood against the
-    tau-weighted sums of the GPU's own per-pair outputs."""
+def test_estep_config2_full_vs_oracle(dev):
+    """Full config 2 (n=20000, 60000 pairs) in the benchmark's launch
+    configuration against the oracle run over all observations: every
+    per-pair output, all partial sums s1..s8 and the log-likelihood at the
+    FP64 bar."""
     from paper_2005_06848_amd import inputs
+    import oracle_pool
     import parity
     c = inputs.config(2)
     gpu = run_pair(dev, c["y"], c["init"], c["u"])
-    rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(c["n"], size=24, replace=False))
-    ref = orc.estep(c["y"][idx], c["init"], c["u"])
-    sub = {k: gpu[k][idx] for k in ("tau", "logf", "e1", "e2", "e3", "e4")}
-    # tau of a sampled observation depends only on its own pairs
-    sub["stats"] = ref["stats"]
-    sub["loglik"] = ref["loglik"]
-    err = parity.estep_errors(sub, ref, 4, 4)
+    print("[cpu] oracle E-step on all 20000 observations", flush=True)
+    ref = oracle_pool.estep_parallel(c["y"], c["init"], c["u"])
+    err = parity.estep_errors(gpu, ref, 4, 4)
+    print(err, flush=True)
     check(err)
-    # property at full size: stats = tau-weighted sums of the pair outputs
-    y, mu = c["y"], c["init"]["mu"]
-    tau, e2 = gpu["tau"], gpu["e2"]
-    for i in range(3):
-        r = y - mu[i]
-        t = tau[:, i]
-        assert gpu["stats"][i, 0] == pytest.approx(t.sum(), rel=1e-12)
-        assert gpu["stats"][i, 1] == pytest.approx((t * e2[:, i]).sum(), rel=1e-12)
-        np.testing.assert_allclose(gpu["stats"][i, 2:6], (t * e2[:, i]) @ r, rtol=1e-11, atol=1e-9)
-        np.testing.assert_allclose(gpu["stats"][i, 6:10], t @ gpu["e3"][:, i], rtol=1e-11)
-    lse = np.logaddexp.reduce(gpu["logf"], axis=1)
-    assert gpu["loglik"] == pytest.approx(lse.sum(), rel=1e-12)
     np.testing.assert_allclose(gpu["tau"].sum(1), 1.0, rtol=1e-13)
 
 
@@ -240,7 +226,17 @@ def test_edge_cases(dev, orc):
     gpu = run_pair(dev, y, c["params"], c["u"])
     assert np.all(np.isfinite(gpu["logf"])) and np.all(np.isfinite(gpu["tau"]))
     err = __import__("parity").estep_errors(gpu, ref, 2, 2)
-    assert err["logf"] < 1e-9 and err["tau"] < 1e-10, err
+    print("deep tail", err, flush=True)
+    check(err)
+    # the far observation's own pairs (tau 1 - 5e-8 and 5e-8), each
+    # quantity by the measure of tests/parity.py: log f absolute, e1
+    # relative to max(|e1|, 1), e2..e4 normwise relative
+    assert np.max(np.abs(gpu["logf"][0] - ref["logf"][0])) <= TOL
+    for i in range(2):
+        assert abs(gpu["e1"][0, i] - ref["e1"][0, i]) <= TOL * max(abs(ref["e1"][0, i]), 1.0)
+        for k in ("e2", "e3", "e4"):
+            a, r = gpu[k][0, i], ref[k][0, i]
+            assert np.max(np.abs(a - r)) <= TOL * np.max(np.abs(r)), (k, i, a, r)
     # error paths
     c = inputs.random_case(17, 10, 2, 2, 2, 64)
     bad = {k: np.array(v, copy=True) for k, v in c["params"].items()}
@@ -269,14 +265,40 @@ def test_edge_cases(dev, orc):
 
 
 def test_deterministic(dev):
-    from paper_2005_06848_amd import inputs, native
-    c = inputs.random_case(41, 2000, 4, 4, 3, 512)
-    a = run_pair(dev, c["y"], c["params"], c["u"])
-    b = run_pair(dev, c["y"], c["params"], c["u"])
-    for k in ("tau", "e4", "stats"):
-        assert np.array_equal(a[k], b[k]), k
-    assert a["loglik"] == b["loglik"]
+    """Ten E-steps of the full config-2 workload (n=20000, p=q=4, g=3,
+    N=4096) in the benchmark's launch configuration give bit-identical
+    per-pair outputs, partial sums and log-likelihood (fixed-order
+    reductions, no atomics in any sum)."""
+    from paper_2005_06848_amd import inputs
+    c = inputs.config(2)
+    first = run_pair(dev, c["y"], c["init"], c["u"])
+    for r in range(9):
+        again = run_pair(dev, c["y"], c["init"], c["u"])
+        for k in ("tau", "logf", "e1", "e2", "e3", "e4", "stats"):
+            assert np.array_equal(first[k], again[k]), (r, k)
+        assert first["loglik"] == again["loglik"], r
 
+
+def test_em_fit_resume_is_bitwise(dev):
+    """cfust_em_fit for k1 iterations, then again from its output for k2,
+    equals one run of k1 + k2 iterations bit for bit (trace and parameters):
+    the fit keeps no hidden state between calls."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(1)
+    keys = ("pi", "mu", "Sigma", "Delta", "nu")
+    for graph in (True, False):
+        print(f"[gpu] resume test graph={graph}", flush=True)
+        full = native.cfust_em_fit(T(c["y"], dev), gpu_params(c["init"], dev), T(c["u"], dev),
+                                   max_iter=7, tol=0.0, graph=graph)
+        a = native.cfust_em_fit(T(c["y"], dev), gpu_params(c["init"], dev), T(c["u"], dev),
+                                max_iter=3, tol=0.0, graph=graph)
+        b = native.cfust_em_fit(T(c["y"], dev), {k: a[k].clone() for k in keys}, T(c["u"], dev),
+                                max_iter=4, tol=0.0, graph=graph)
+        assert full["n_iter"] == 7 and a["n_iter"] == 3 and b["n_iter"] == 4
+        np.testing.assert_array_equal(np.asarray(a["trace"]), np.asarray(full["trace"])[:4])
+        np.testing.assert_array_equal(np.asarray(b["trace"]), np.asarray(full["trace"])[3:])
+        for k in keys:
+            np.testing.assert_array_equal(b[k].cpu().numpy(), full[k].cpu().numpy())
 
 
 def test_setup_error_paths(dev, orc):

@@ -351,3 +351,47 @@ def test_multistart_picks_the_largest_loglik():
     run = orc.em_fit(c["y"], starts[fit["best"]], c["u"], max_iter=1, tol=0.0)
     ref = orc.em_fit(c["y"], run, c["u"], max_iter=3, tol=0.0)
     np.testing.assert_array_equal(fit["trace"], ref["trace"])
+
+
+def _stats_from_pairs(y, mu, tau, e1, e2, e3, e4):
+    """s1..s8 of every component written out from their definitions (the
+    tau-weighted sums of the per-pair conditional expectations, centred at
+    mu_i), packed s1 | s2 | s3[p] | s4[q] | s5 upper triangle | s6[p][q] |
+    s7 upper triangle | s8, symmetric blocks row by row."""
+    n, p = y.shape
+    g, q = e3.shape[1], e3.shape[2]
+    iu_q = np.triu_indices(q)
+    iu_p = np.triu_indices(p)
+    rows = []
+    for i in range(g):
+        r = y - mu[i]
+        t = tau[:, i]
+        s1 = t.sum()
+        s2 = (t * e2[:, i]).sum()
+        s3 = np.einsum("j,j,ja->a", t, e2[:, i], r)
+        s4 = np.einsum("j,jk->k", t, e3[:, i])
+        s5 = np.einsum("j,jkl->kl", t, e4[:, i])
+        s6 = np.einsum("j,ja,jk->ak", t, r, e3[:, i])
+        s7 = np.einsum("j,j,ja,jb->ab", t, e2[:, i], r, r)
+        s8 = (t * (e1[:, i] - e2[:, i])).sum()
+        rows.append(np.concatenate([[s1, s2], s3, s4, s5[iu_q], s6.ravel(), s7[iu_p], [s8]]))
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("shape", [(70, 3, 2, 2), (45, 2, 4, 3), (33, 5, 3, 2), (50, 1, 3, 2)])
+def test_stats_assembly_recomputed(orc, shape):
+    """Every partial sum s1..s8 (Algorithm 2's per-component partial sums,
+    reconstructed from the hidden-variable model) equals the tau-weighted
+    sums of the oracle's own per-pair tau, e1..e4 and r = y - mu_i, written
+    out here with numpy.  p != q throughout, so a transposed s6 or a
+    mis-packed triangle changes the layout and fails."""
+    n, p, q, g = shape
+    c = inputs.random_case(500 + n + p, n, p, q, g, 256)
+    for mode in (orc.NU_OSL, orc.NU_EXACT_FD):
+        out = orc.estep(c["y"], c["params"], c["u"], nu_mode=mode)
+        ref = _stats_from_pairs(c["y"], np.asarray(c["params"]["mu"]), out["tau"], out["e1"],
+                                out["e2"], out["e3"], out["e4"])
+        assert out["stats"].shape == ref.shape
+        scale = np.maximum(np.abs(ref).max(1, keepdims=True), 1e-300)
+        err = np.abs(out["stats"] - ref) / scale
+        assert err.max() < 1e-13, (mode, err.max(), np.unravel_index(err.argmax(), err.shape))
