@@ -13,6 +13,9 @@
 #include "cfust_kernels.hpp"
 
 namespace cfust {
+// every kernel, device function and table has internal linkage: each
+// translation unit of the library compiles the ones it uses
+namespace {
 
 // Device view of the batch description and per-problem state.
 struct BatchDev {
@@ -262,8 +265,5 @@ __global__ void binit_state_kernel(BatchDev b, int max_iter) {
   for (int t = 0; t <= max_iter; ++t) tr[t] = NAN;
 }
 
-__global__ void fill_uint_kernel(unsigned int* p, unsigned int v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
-}
-
+}  // namespace
 }  // namespace cfust

@@ -23,6 +23,9 @@
 #include "cfust_math.hpp"
 
 namespace cfust {
+// every kernel, device function and table has internal linkage: each
+// translation unit of the library compiles the ones it uses
+namespace {
 
 constexpr int kMaxP = 32;
 constexpr int kMaxQ = 12;      // E-step, log-likelihood, M-step and EM fit (FP64, FP32)
@@ -94,6 +97,10 @@ __device__ __forceinline__ void set_status(int* status, int code, int comp) {
 __global__ void fill_int_kernel(int* p, int n, int v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+__global__ void fill_uint_kernel(unsigned int* p, unsigned int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1715,4 +1722,5 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
   out[t] = r;
 }
 
+}  // namespace
 }  // namespace cfust

@@ -14,6 +14,9 @@
 #include "cfust_coeffs.hpp"
 
 namespace cfust {
+// every kernel, device function and table has internal linkage: each
+// translation unit of the library compiles the ones it uses
+namespace {
 
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kSqrtHalf = 0.70710678118654752440;
@@ -434,4 +437,5 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+}  // namespace
 }  // namespace cfust

@@ -12,6 +12,9 @@
 #include <stdint.h>
 
 namespace cfust {
+// every kernel, device function and table has internal linkage: each
+// translation unit of the library compiles the ones it uses
+namespace {
 
 using bf16 = unsigned short;
 typedef short short4_t __attribute__((ext_vector_type(4)));
@@ -628,4 +631,5 @@ __global__ void unstd_kernel(const float* __restrict__ P, int64_t B, int OUT, in
   label_row(P + r * kMlpPad, my, sy, q, out + r * OUT);
 }
 
+}  // namespace
 }  // namespace cfust

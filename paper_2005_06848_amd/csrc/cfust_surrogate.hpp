@@ -14,6 +14,9 @@
 #include "cfust_mlp.hpp"
 
 namespace cfust {
+// every kernel, device function and table has internal linkage: each
+// translation unit of the library compiles the ones it uses
+namespace {
 
 // training range and standardisation, by value in kernel arguments
 struct SurrRange {
@@ -439,4 +442,5 @@ __global__ void check_combine_kernel(const double* __restrict__ cst, int GS, int
   if (e == GS) loglik[0] += scale * (cst[2 * GS + 1] - cst[GS]);
 }
 
+}  // namespace
 }  // namespace cfust
