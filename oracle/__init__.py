@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle_cfust.so")
 SOURCES = [os.path.join(_HERE, "cfust_oracle.c")]
 
 OK, EINVAL, ENOTPD, ENONFINITE, ENOMEM = 0, 1, 2, 3, 5
-NU_OSL, NU_EXACT_FD, NU_FIXED = 0, 1, 2
+NU_OSL, NU_EXACT_FD, NU_FIXED, NU_EXACT = 0, 1, 2, 3
 FD_REL = 1e-3
 
 
@@ -44,13 +44,15 @@ def lib():
                      "orc_norm_quantile_log", "orc_digamma"):
             f = getattr(L, name)
             f.restype, f.argtypes = d, [d]
-        for name in ("orc_gamma_p", "orc_gamma_q", "orc_chi2_quantile"):
+        for name in ("orc_gamma_p", "orc_gamma_q", "orc_chi2_quantile", "orc_chi2_quantile_ddof"):
             f = getattr(L, name)
             f.restype, f.argtypes = d, [d, d]
         L.orc_stats_size.restype, L.orc_stats_size.argtypes = i, [i, i]
         L.orc_aitken_linf.restype, L.orc_aitken_linf.argtypes = d, [d, d, d]
         L.orc_ghk.restype = i
         L.orc_ghk.argtypes = [i, P, P, d, P, i, i, P, P, P]
+        L.orc_ghk_tangent.restype = i
+        L.orc_ghk_tangent.argtypes = [i, P, P, d, P, i, P, P]
         L.orc_estep.restype = i
         L.orc_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, i, i,
                                 P, P, P, P, P, P, P, P, P]
@@ -124,6 +126,11 @@ def chi2_quantile(u, dof):
     return lib().orc_chi2_quantile(float(u), float(dof))
 
 
+def chi2_quantile_ddof(u, dof):
+    """d/d(dof) of the chi-square quantile at probability u."""
+    return lib().orc_chi2_quantile_ddof(float(u), float(dof))
+
+
 def ghk(h, C, dof, u, moments=True):
     """GHK estimate: returns (logT, EV, EVV) for V ~ t_q(0, C C^T, dof), V <= h."""
     h = _f64(h)
@@ -138,6 +145,20 @@ def ghk(h, C, dof, u, moments=True):
     if rc:
         raise OracleError(rc)
     return float(logT[0]), EV, EVV
+
+
+def ghk_tangent(h, C, a, u):
+    """log P(V <= h), V ~ t_q(0, C C^T, 2a) (GHK, no moments) and the
+    derivative in a' at a' = a of the same estimate with bound h sqrt(a'/a)
+    and dof 2a'."""
+    h, C, u = _f64(h), _f64(C), _f64(u)
+    q = h.shape[0]
+    lt, dl = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().orc_ghk_tangent(q, _ptr(h), _ptr(C), float(a), _ptr(u), u.shape[0],
+                               ctypes.byref(lt), ctypes.byref(dl))
+    if rc:
+        raise OracleError(rc)
+    return lt.value, dl.value
 
 
 def genz_order(h, R):

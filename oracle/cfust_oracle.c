@@ -198,6 +198,28 @@ double orc_chi2_quantile(double u, double dof) {
   return 2.0 * x;
 }
 
+/* Derivative of the chi-square quantile with respect to the degrees of
+ * freedom.  x = orc_chi2_quantile(u, dof) solves P(a, z) = u with a = dof/2,
+ * z = x/2; differentiating, dz/da = -(dP/da) / (dP/dz), and since x = 2z and
+ * dof = 2a, dx/d(dof) = dz/da.  Here dP/dz = z^(a-1) e^(-z) / Gamma(a) and,
+ * term by term from the series P(a, z) = sum_{k>=0} e^(-z) z^(a+k) / Gamma(a+k+1),
+ *   dP/da = sum_{k>=0} e^(-z) z^(a+k) / Gamma(a+k+1) * (log z - psi(a+k+1)).
+ * Each term is evaluated on its own (log-gamma and digamma per term); the sum
+ * stops once the terms, past their peak at a+k ~ z, fall below 1e-20. */
+double orc_chi2_quantile_ddof(double u, double dof) {
+  const double a = 0.5 * dof;
+  const double z = 0.5 * orc_chi2_quantile(u, dof);
+  const double lz = log(z);
+  double dPda = 0.0;
+  for (int k = 0; k < 100000; ++k) {
+    const double w = exp((a + k) * lz - z - lgamma(a + k + 1.0));
+    dPda += w * (lz - orc_digamma(a + k + 1.0));
+    if (a + k > z && w < 1e-20) break;
+  }
+  const double dPdz = exp((a - 1.0) * lz - z - lgamma(a));
+  return -dPda / dPdz;
+}
+
 /* ------------------------------------------------------------------------- */
 /* small dense linear algebra                                                */
 /* ------------------------------------------------------------------------- */
@@ -369,6 +391,86 @@ static void chi_scale_table(const double* u, int n_qmc, int q, double dof, doubl
   for (int k = 0; k < n_qmc; ++k) s[k] = sqrt(orc_chi2_quantile(u[(size_t)k * (q + 1)], dof) / dof);
 }
 
+/* Tangent of the scale of integral A with respect to a' = dof'/2 at a' = a:
+ * the bounds of J(a') (see orc_estep) are s_k(a') h sqrt(a'/a), with
+ * s_k(a') = sqrt(x_k(2a') / (2a')), so the factor multiplying h has
+ *   t_k = d/da' [s_k(a') sqrt(a'/a)] at a' = a = 2 ds_k/d(dof) + s_k / (2a),
+ *   ds_k/d(dof) = (dx_k/d(dof) / dof - x_k / dof^2) / (2 s_k),  dof = 2a. */
+static void chi_tangent_table(const double* u, int n_qmc, int q, double a, const double* s,
+                              double* t) {
+  const double dof = 2.0 * a;
+  for (int k = 0; k < n_qmc; ++k) {
+    const double uk = u[(size_t)k * (q + 1)];
+    const double x = orc_chi2_quantile(uk, dof);
+    const double dx = orc_chi2_quantile_ddof(uk, dof);
+    const double ds = (dx / dof - x / (dof * dof)) / (2.0 * s[k]);
+    t[k] = 2.0 * ds + s[k] / (2.0 * a);
+  }
+}
+
+/* log P(V <= h) of ghk_core (no moments) and its derivative along a
+ * perturbation of the scale: the same estimator with the factor of h at
+ * point k moving at rate t[k] (chi_tangent_table), differentiated step by
+ * step through the sequential bounds and draws on the same points:
+ *   ub_m' = (t_k h_m - sum_{l<m} C_ml eps_l') / C_mm,
+ *   (log Phi(ub_m))' = phi(ub_m) / Phi(ub_m) * ub_m',
+ *   eps_m' = u_m phi(ub_m) / phi(eps_m) * ub_m'   (from Phi(eps_m) = u_m Phi(ub_m)),
+ *   (log weight_k)' = sum_m (log Phi(ub_m))',
+ *   (log T)' = sum_k weight_k (log weight_k)' / sum_k weight_k.
+ * Ratios of densities are taken in log space. */
+static void ghk_tangent(int q, const double* h, const double* C, const double* s, const double* t,
+                        const double* u, int n_qmc, double* logw, double* dlw, double* logT,
+                        double* dlogT) {
+  double eps[64], deps[64];
+  for (int k = 0; k < n_qmc; ++k) {
+    const double* uk = u + (size_t)k * (q + 1);
+    double lw = 0.0, dl = 0.0;
+    for (int m = 0; m < q; ++m) {
+      double acc = s[k] * h[m], dacc = t[k] * h[m];
+      for (int l = 0; l < m; ++l) {
+        acc -= C[m * q + l] * eps[l];
+        dacc -= C[m * q + l] * deps[l];
+      }
+      const double ub = acc / C[m * q + m];
+      const double dub = dacc / C[m * q + m];
+      const double le = orc_log_norm_cdf(ub);
+      const double lphi_ub = -0.5 * ub * ub - LOG_SQRT_2PI_;
+      lw += le;
+      dl += exp(lphi_ub - le) * dub;
+      if (m < q - 1) {
+        double um = uk[m + 1];
+        double lp = log(um) + le;
+        if (lp <= -LN2_) {
+          eps[m] = orc_norm_quantile_log(lp);
+        } else {
+          double comp = (1.0 - um) + um * orc_norm_cdf(-ub);
+          eps[m] = -orc_norm_quantile_log(log(comp));
+        }
+        const double lphi_eps = -0.5 * eps[m] * eps[m] - LOG_SQRT_2PI_;
+        deps[m] = exp(log(um) + lphi_ub - lphi_eps) * dub;
+      }
+    }
+    logw[k] = lw;
+    dlw[k] = dl;
+  }
+  double M = -INFINITY;
+  for (int k = 0; k < n_qmc; ++k)
+    if (logw[k] > M) M = logw[k];
+  if (!isfinite(M)) {
+    *logT = -INFINITY;
+    *dlogT = 0.0;
+    return;
+  }
+  double S0 = 0.0, S1 = 0.0;
+  for (int k = 0; k < n_qmc; ++k) {
+    const double wk = exp(logw[k] - M);
+    S0 += wk;
+    S1 += wk * dlw[k];
+  }
+  *logT = M + log(S0) - log((double)n_qmc);
+  *dlogT = S1 / S0;
+}
+
 int orc_ghk(int q, const double* h, const double* C, double dof, const double* u, int n_qmc,
             int moments, double* logT, double* EV, double* EVV) {
   if (q < 1 || q > 64 || n_qmc < 1 || !(dof > 0.0)) return ORC_EINVAL;
@@ -387,6 +489,27 @@ int orc_ghk(int q, const double* h, const double* C, double dof, const double* u
   free(logw);
   free(ehat);
   return ORC_OK;
+}
+
+int orc_ghk_tangent(int q, const double* h, const double* C, double a, const double* u,
+                    int n_qmc, double* logT, double* dlogT) {
+  if (q < 1 || q > 64 || n_qmc < 1 || !(a > 0.0)) return ORC_EINVAL;
+  double* s = (double*)malloc(sizeof(double) * n_qmc);
+  double* t = (double*)malloc(sizeof(double) * n_qmc);
+  double* logw = (double*)malloc(sizeof(double) * n_qmc);
+  double* dlw = (double*)malloc(sizeof(double) * n_qmc);
+  int rc = ORC_OK;
+  if (!s || !t || !logw || !dlw) rc = ORC_ENOMEM;
+  if (!rc) {
+    chi_scale_table(u, n_qmc, q, 2.0 * a, s);
+    chi_tangent_table(u, n_qmc, q, a, s, t);
+    ghk_tangent(q, h, C, s, t, u, n_qmc, logw, dlw, logT, dlogT);
+  }
+  free(s);
+  free(t);
+  free(logw);
+  free(dlw);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -511,6 +634,7 @@ typedef struct {
   double* sB;     /* chi scale table, dof nu+p+2, N */
   double* sAp;    /* chi scale tables, dof (nu+p)(1 +- ORC_FD_REL) (exact e1 only) */
   double* sAm;
+  double* tA;     /* tangent of integral A's scale in a = (nu+p)/2 (exact e1 only) */
   double kappa;   /* log pi + q log 2 + log of t_p's normaliser */
   double nu;
 } comp_t;
@@ -550,6 +674,7 @@ static void free_comps(comp_t* cp, int g) {
     free(cp[i].sB);
     free(cp[i].sAp);
     free(cp[i].sAm);
+    free(cp[i].tA);
   }
   free(cp);
 }
@@ -587,8 +712,9 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
       c->sAp = (double*)malloc(sizeof(double) * n_qmc);
       c->sAm = (double*)malloc(sizeof(double) * n_qmc);
     }
+    if (tables == 3) c->tA = (double*)malloc(sizeof(double) * n_qmc);
     if (!c->L || !c->B || !c->D || !c->C || !c->R || (tables && (!c->sA || !c->sB)) ||
-        (tables == 2 && (!c->sAp || !c->sAm))) {
+        (tables == 2 && (!c->sAp || !c->sAm)) || (tables == 3 && !c->tA)) {
       rc = ORC_ENOMEM;
       break;
     }
@@ -652,6 +778,7 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
       chi_scale_table(u, n_qmc, q, (v + p) * (1.0 + ORC_FD_REL), c->sAp);
       chi_scale_table(u, n_qmc, q, (v + p) * (1.0 - ORC_FD_REL), c->sAm);
     }
+    if (tables == 3) chi_tangent_table(u, n_qmc, q, 0.5 * (v + p), c->sA, c->tA);
   }
   free(Om);
   free(Lam);
@@ -684,6 +811,8 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
  *       e1 = psi(a) - log b + d/da log J(a);
  *     nu_mode ORC_NU_OSL uses the one-step-late form d/da log J ~ e2 - a/b,
  *       e1 - e2 = psi(a) - log b - a/b   (exact when Delta = 0);
+ *     nu_mode ORC_NU_EXACT takes the derivative of the estimate of J itself,
+ *       on the same points (ghk_tangent with chi_tangent_table);
  *     nu_mode ORC_NU_EXACT_FD takes the central difference with step
  *       ORC_FD_REL a on the same points: integrals at dof (nu+p)(1 +- eps)
  *       and bounds h_A sqrt(1 +- eps).
@@ -703,15 +832,17 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
   int rc = validate_model(n, p, q, g, pi, mu, Sigma, Delta, nu, y);
   if (rc) return rc;
   const int exact = nu_mode == ORC_NU_EXACT_FD;
+  const int tangent = nu_mode == ORC_NU_EXACT;
   offs_t o = stat_offsets(p, q);
   comp_t* cp = NULL;
-  rc = make_comps(p, q, g, pi, Sigma, Delta, nu, u, n_qmc, exact ? 2 : 1, &cp, &bad);
+  rc = make_comps(p, q, g, pi, Sigma, Delta, nu, u, n_qmc, exact ? 2 : tangent ? 3 : 1, &cp, &bad);
   if (rc) {
     if (bad_component) *bad_component = bad;
     return rc;
   }
   double* logw = (double*)malloc(sizeof(double) * n_qmc);
   double* ehat = (double*)malloc(sizeof(double) * (size_t)n_qmc * q);
+  double* dlw = (double*)malloc(sizeof(double) * n_qmc);
   double* lf = (double*)malloc(sizeof(double) * g);
   double* E2 = (double*)malloc(sizeof(double) * g);
   double* E1m2 = (double*)malloc(sizeof(double) * g);
@@ -719,7 +850,7 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
   double* E4 = (double*)malloc(sizeof(double) * g * q * q);
   double* R = (double*)malloc(sizeof(double) * g * p);
   double* z = (double*)malloc(sizeof(double) * p);
-  if (!logw || !ehat || !lf || !E2 || !E1m2 || !E3 || !E4 || !R || !z) {
+  if (!logw || !ehat || !dlw || !lf || !E2 || !E1m2 || !E3 || !E4 || !R || !z) {
     rc = ORC_ENOMEM;
     goto done;
   }
@@ -776,6 +907,12 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
           ghk_in_order(q, hM, Cu, pm, c->sAm, u, n_qmc, 0, logw, ehat, &lM, NULL, NULL);
           if (isfinite(lP) && isfinite(lM))
             E1m2[i] = orc_digamma(aa) - log(bb) + (lP - lM) / (2.0 * ORC_FD_REL * aa) - e2v;
+        }
+        if (tangent) {
+          double hp[64], lT, dlT;
+          for (int k = 0; k < q; ++k) hp[k] = pm ? hA[pm[k]] : hA[k];
+          ghk_tangent(q, hp, Cu, c->sA, c->tA, u, n_qmc, logw, dlw, &lT, &dlT);
+          E1m2[i] = orc_digamma(aa) - log(bb) + dlT - e2v;
         }
         double sc = sqrt((v + d) / (v + p + 2.0));
         double mx[64];
@@ -834,6 +971,7 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
 done:
   free(logw);
   free(ehat);
+  free(dlw);
   free(lf);
   free(E2);
   free(E1m2);

@@ -27,6 +27,7 @@
 #define ORC_NU_EXACT_FD 1   /* e1 = E[log W | y] with a central difference in a */
 #define ORC_FD_REL 1e-3     /* relative step of that difference */
 #define ORC_NU_FIXED 2
+#define ORC_NU_EXACT 3      /* e1 = E[log W | y] with the derivative of the estimate itself */
 
 #ifdef __cplusplus
 extern "C" {
@@ -41,6 +42,7 @@ double orc_digamma(double x);
 double orc_gamma_p(double a, double x);
 double orc_gamma_q(double a, double x);
 double orc_chi2_quantile(double u, double dof);
+double orc_chi2_quantile_ddof(double u, double dof);
 
 /* GHK estimate of P(V <= h) for V ~ t_q(0, R, dof), R = C C^T (C lower,
  * q*q row-major, positive diagonal).  s[k] = sqrt(chi2_quantile(u[k][0],dof)/dof).
@@ -51,6 +53,12 @@ int orc_ghk(int q, const double* h, const double* C, double dof, const double* u
 /* Genz-Bretz variable ordering of P(Z <= h), Z ~ N(0, R), R with unit
  * diagonal: perm[i] = variable placed at step i, Cp = chol(R[perm][perm]). */
 int orc_genz_order(int q, const double* h, const double* R, int* perm, double* Cp);
+
+/* log T = log P(V <= h), V ~ t_q(0, C C^T, 2a), by orc_ghk without moments,
+ * and d/da' log of the same estimate with bound h sqrt(a'/a) and dof 2a', at
+ * a' = a, on the same points (the derivative of the estimate itself). */
+int orc_ghk_tangent(int q, const double* h, const double* C, double a, const double* u,
+                    int n_qmc, double* logT, double* dlogT);
 
 /* orc_ghk with the variables in the Genz-Bretz order found from h and R
  * (R a correlation matrix); moments in the original labelling; perm[q]

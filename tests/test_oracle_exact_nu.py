@@ -1,4 +1,5 @@
-"""Pins of the oracle's exact e1 = E[log W | y] (nu_mode EXACT_FD).
+"""Pins of the oracle's exact e1 = E[log W | y] (nu_mode EXACT: the derivative
+of the GHK estimate itself; nu_mode EXACT_FD: a central difference).
 
 The hidden-variable model gives W | y a density proportional to
 w^{a-1} e^{-b w} Phi_q(sqrt(w) c; Lambda) (a = (nu+p)/2, b = (nu+d)/2,
@@ -7,9 +8,12 @@ pins compute E[log W | y] straight from that density by one-dimensional
 quadrature over w, with the normal CDF from scipy (q = 1) or the bivariate
 normal CDF as a one-dimensional integral on generalised Gauss-Laguerre nodes
 (q = 2), and check
-the oracle's central-difference value against it.  Delta = 0 reduces both
-modes to psi(a) - log b exactly.
+the oracle's values against it.  Delta = 0 reduces all modes to
+psi(a) - log b exactly.  The derivative of the estimate is pinned on its own
+by a fourth-order difference quotient of the oracle's plain GHK estimate
+(which it differentiates), and its chi-square quantile derivative by mpmath.
 """
+import mpmath
 import numpy as np
 from scipy import integrate, special, stats
 
@@ -43,8 +47,10 @@ def test_delta_zero_modes_agree():
     u = inputs.qmc_points(512, q)
     e_osl = _oracle_e1(y, mu, Sigma, Delta, 6.0, u, orc.NU_OSL)
     e_fd = _oracle_e1(y, mu, Sigma, Delta, 6.0, u, orc.NU_EXACT_FD)
+    e_ex = _oracle_e1(y, mu, Sigma, Delta, 6.0, u, orc.NU_EXACT)
     a, b, _, _ = _pair_quantities(y, mu, Sigma, Delta, 6.0)
     assert e_fd == e_osl
+    assert e_ex == e_osl
     assert abs(e_fd - (special.digamma(a) - np.log(b))) < 1e-14
 
 
@@ -68,8 +74,10 @@ def test_q1_matches_quadrature_of_the_definition():
         den = integrate.quad(lambda w: dens(w, 0), 0, np.inf, limit=400, epsabs=0, epsrel=1e-12)[0]
         ref = num / den
         e_fd = _oracle_e1(y, mu, Sigma, Delta, nu, u, orc.NU_EXACT_FD)
+        e_ex = _oracle_e1(y, mu, Sigma, Delta, nu, u, orc.NU_EXACT)
         e_osl = _oracle_e1(y, mu, Sigma, Delta, nu, u, orc.NU_OSL)
         assert abs(e_fd - ref) < 2e-5 * max(1.0, abs(ref)), (case, e_fd, ref, e_osl)
+        assert abs(e_ex - ref) < 2e-5 * max(1.0, abs(ref)), (case, e_ex, ref, e_osl)
 
 
 def test_q2_matches_quadrature_of_the_definition():
@@ -105,7 +113,52 @@ def test_q2_matches_quadrature_of_the_definition():
         ref_e2 = float(np.sum(wt * ph * w) / np.sum(wt * ph))
         par = dict(pi=np.array([1.0]), mu=mu[None], Sigma=Sigma[None], Delta=Delta[None],
                    nu=np.array([nu]))
-        out = orc.estep(y[None], par, u, nu_mode=orc.NU_EXACT_FD, want=("e1", "e2"))
-        e1, e2 = float(out["e1"][0, 0]), float(out["e2"][0, 0])
-        assert abs(e2 - ref_e2) < 1e-5 * ref_e2, (case, e2, ref_e2)
-        assert abs(e1 - ref_e1) < 1e-4 * max(1.0, abs(ref_e1)), (case, e1, ref_e1)
+        for mode in (orc.NU_EXACT_FD, orc.NU_EXACT):
+            out = orc.estep(y[None], par, u, nu_mode=mode, want=("e1", "e2"))
+            e1, e2 = float(out["e1"][0, 0]), float(out["e2"][0, 0])
+            assert abs(e2 - ref_e2) < 1e-5 * ref_e2, (case, mode, e2, ref_e2)
+            assert abs(e1 - ref_e1) < 1e-4 * max(1.0, abs(ref_e1)), (case, mode, e1, ref_e1)
+
+
+def test_chi2_quantile_derivative_matches_mpmath():
+    """d/d(dof) of the chi-square quantile: implicit differentiation of the
+    regularised incomplete gamma at 40 digits (mpmath) against the oracle's
+    series.  In the far upper tail the series for dP/da cancels to about
+    1/Q, hence the looser bar there."""
+    mpmath.mp.dps = 40
+
+    def quantile(u, dof):
+        f = lambda x: mpmath.gammainc(dof / 2, 0, x / 2, regularized=True) - u
+        return mpmath.findroot(f, orc.chi2_quantile(float(u), float(dof)))
+
+    for u, dof, tol in [(0.3, 7.0, 1e-13), (1e-6, 5.5, 1e-13), (0.5, 30.0, 1e-13),
+                        (0.01, 3.2, 1e-13), (0.9, 140.0, 1e-12), (0.97, 4.1, 1e-12),
+                        (0.999999, 12.3, 1e-9)]:
+        ref = float(mpmath.diff(lambda d: quantile(mpmath.mpf(u), d), mpmath.mpf(dof)))
+        got = orc.chi2_quantile_ddof(u, dof)
+        assert abs(got - ref) <= tol * abs(ref), (u, dof, got, ref)
+
+
+def test_tangent_is_the_derivative_of_the_estimate():
+    """The oracle's tangent of log J(a') (bound h sqrt(a'/a), dof 2a', the
+    same points) against a fourth-order central difference of the plain GHK
+    estimate over a': a dropped term or a wrong sign in the chain rule
+    through the sequential bounds and draws, or in the chi-scale tangent,
+    fails this."""
+    rng = np.random.default_rng(11)
+    for case, q in enumerate((1, 2, 3, 5, 6)):
+        u = inputs.qmc_points(1024, q)
+        A = rng.standard_normal((q, q))
+        R = A @ A.T + q * np.eye(q)
+        dg = np.sqrt(np.diag(R))
+        R = R / np.outer(dg, dg)
+        C = np.linalg.cholesky(R)
+        h = rng.uniform(-1.0, 2.0, size=q)
+        a = rng.uniform(2.5, 9.0)
+        lt, dl = orc.ghk_tangent(h, C, a, u)
+        lt0 = orc.ghk(h, C, 2 * a, u, moments=False)[0]
+        assert lt == lt0
+        f = lambda ap: orc.ghk(h * np.sqrt(ap / a), C, 2 * ap, u, moments=False)[0]
+        dlt = 1e-3 * a
+        fd = (8 * (f(a + dlt) - f(a - dlt)) - (f(a + 2 * dlt) - f(a - 2 * dlt))) / (12 * dlt)
+        assert abs(dl - fd) < 1e-8 * max(abs(fd), 1e-2), (case, q, dl, fd)
