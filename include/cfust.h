@@ -25,9 +25,9 @@
  *  - Functions return CFUST_OK (0) or an error code; they never throw.
  *  - Limits: 1 <= p <= 32, 1 <= q <= 12, 1 <= g <= 16, n_qmc >= 1, n >= 0.
  *    For 9 <= q <= 12 the natural-order E-step, log-likelihood, M-step and
- *    EM fit exist (FP64 and FP32); the exact nu step, the variable ordering,
- *    the surrogate, the batched form, the multistart fit and the GHK label
- *    batch return CFUST_EINVAL there.
+ *    EM fit exist (FP64 and FP32, with every nu_mode); the variable
+ *    ordering, the surrogate, the batched form, the multistart fit and the
+ *    GHK label batch return CFUST_EINVAL there.
  *
  * Sufficient statistics ("partial sums" of Algorithm 2) are stats[g][S] with
  * S = cfust_stats_size(p, q) = 3 + p + q + p q + p(p+1)/2 + q(q+1)/2, per
@@ -61,16 +61,17 @@ extern "C" {
                                sums in float64; everything else stays float64 */
 
 #define CFUST_NU_OSL 0      /* nu update with the one-step-late E[log W | y] */
-#define CFUST_NU_EXACT_FD 1 /* nu update with the exact E[log W | y] = psi(a) - log b
+#define CFUST_NU_EXACT 1    /* nu update with the exact E[log W | y] = psi(a) - log b
                                + d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a, the
-                               derivative a central difference (relative step 1e-3 in
-                               a, two more integrals per pair on the same points);
-                               not with a surrogate nor in cfust_em_fit_batched */
+                               derivative that of the GHK estimate itself on the same
+                               points (a tangent carried through integral A: its
+                               bounds, draws and chi-square scale); not with a
+                               surrogate */
 #define CFUST_NU_FIXED 2    /* nu held fixed */
 
 typedef struct cfust_opts {
   int precision;          /* CFUST_FP64 or CFUST_FP32 */
-  int nu_mode;            /* CFUST_NU_OSL, CFUST_NU_EXACT_FD or CFUST_NU_FIXED */
+  int nu_mode;            /* CFUST_NU_OSL, CFUST_NU_EXACT or CFUST_NU_FIXED */
   int fix_delta_zero;     /* nonzero: Delta held at 0 (t-mixture special case) */
   int max_iter;           /* cfust_em_fit: maximum number of M-steps */
   double tol;             /* cfust_em_fit: Aitken tolerance on |l_inf - l| */
@@ -231,8 +232,8 @@ int cfust_loglik_rqmc(const double* y, int64_t n, int p, int q, int g, const dou
  * l^(0) and `burn_in` EM iterations per start, exactly that many unless a
  * start fails); the start with the largest l after its burn-in continues
  * with cfust_em_fit (opts->max_iter, opts->tol) into pi, mu, Sigma, Delta, nu
- * (device outputs [g]...).  The burn-in uses the one-step-late nu update when
- * opts->nu_mode is CFUST_NU_EXACT_FD.  start_loglik (host [m], may be NULL):
+ * (device outputs [g]...).  The burn-in uses opts->nu_mode as the
+ * continuation does, in the natural variable order.  start_loglik (host [m], may be NULL):
  * l of each start after its burn-in (NaN if the start failed); best (host):
  * the selected start; loglik_trace, n_iter, bad_component as cfust_em_fit.
  * Needs m copies of y in device memory. */
@@ -369,8 +370,9 @@ double cfust_aitken_linf(double l0, double l1, double l2);
 /* Diagnostic: evaluates a device special function elementwise on x[n]
  * (device), writing out[n] (device).  fn: 0 Phi, 1 log Phi, 2 Phi^-1,
  * 3 Phi^-1 from log p, 4 chi-square quantile at (x, x2 = dof), 5 digamma,
- * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32, 9 log, 10 sqrt.  x2 may be NULL unless
- * fn is 4. */
+ * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32, 9 log, 10 sqrt,
+ * 11 d/d(dof) of the chi-square quantile at (x, x2 = dof), 12 phi(x)/Phi(x),
+ * 13 phi(x)/Phi(x) in float32.  x2 may be NULL unless fn is 4 or 11. */
 int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
                        void* stream);
 

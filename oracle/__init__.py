@@ -285,10 +285,9 @@ def em_fit_multistart(y, starts, u, burn_in=0, max_iter=10, tol=1e-6, nu_mode=NU
     start runs burn_in EM iterations (its l^(0) when burn_in = 0), the start
     with the largest l after them is kept (the paper's "smallest" read as the
     largest, i.e. maximum likelihood), and the fit continues from it.  The
-    burn-in uses the one-step-late nu update when nu_mode is exact, and the
-    natural variable order; the continuation uses nu_mode and reorder."""
-    bm = NU_OSL if nu_mode == NU_EXACT_FD else nu_mode
-    runs = [em_fit(y, s, u, max_iter=burn_in, tol=0.0, nu_mode=bm, **kw) for s in starts]
+    burn-in uses nu_mode in the natural variable order; the continuation uses
+    nu_mode and reorder."""
+    runs = [em_fit(y, s, u, max_iter=burn_in, tol=0.0, nu_mode=nu_mode, **kw) for s in starts]
     ll = np.array([r["trace"][-1] for r in runs])
     best = int(np.argmax(ll))
     fit = em_fit(y, runs[best], u, max_iter=max_iter, tol=tol, nu_mode=nu_mode, reorder=reorder,

@@ -49,12 +49,14 @@ struct BPlan {
   // workspace offsets
   size_t o_noff, o_goff, o_poff, o_boff, o_perb, o_partoff, o_roff, o_active, o_status, o_iter,
       o_niter, o_llcur, o_trace, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll,
-      o_stats, o_pitmp, o_mwork, o_counter, o_pstat, total;
+      o_stats, o_pitmp, o_mwork, o_counter, o_pstat, o_tA, total;
+  bool exact = false;  // exact E[log W | y] (tangent table o_tA)
 };
 
 int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, int prec,
-               int max_iter, BPlan* pl) {
+               int max_iter, bool exact, BPlan* pl) {
   pl->P = P;
+  pl->exact = exact;
   pl->p = p;
   pl->q = q;
   pl->N = N;
@@ -137,6 +139,7 @@ int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, i
   pl->o_mwork = take((size_t)pl->G * mstep_work_doubles(p, q) * sizeof(double));
   pl->o_counter = take(64);
   pl->o_pstat = take(4 * sizeof(int));
+  pl->o_tA = take((size_t)pl->G * N * es);  // used with the exact nu step only
   pl->total = off;
   return CFUST_OK;
 }
@@ -172,16 +175,26 @@ struct BArgs {
   double nu_lo, nu_hi, tol;
 };
 
-template <typename T, int Q>
-void launch_bpair(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a, hipStream_t st,
-                  const Shape& sh, unsigned int total, int n_cu) {
+template <typename T, int Q, bool EXACT>
+void launch_bpair_e(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a,
+                    hipStream_t st, const Shape& sh, unsigned int total, int n_cu) {
   int waves = sh.wps * 4 * n_cu;
   int blocks = std::max(1, waves / sh.wpb);
-  bpair_kernel<T, Q><<<blocks, 64 * sh.wpb, 0, st>>>(
+  bpair_kernel<T, Q, EXACT><<<blocks, 64 * sh.wpb, 0, st>>>(
       b, a.y, a.mu, (const double*)(base + pl.o_comp), (const T*)(base + pl.o_sA),
       (const T*)(base + pl.o_sB), (const T*)(base + pl.o_rsB), (const T*)(base + pl.o_uT),
       (const T*)(base + pl.o_ubT), pl.N, (double*)(base + pl.o_pair),
-      (unsigned int*)(base + pl.o_counter), total, sh.chunk);
+      (unsigned int*)(base + pl.o_counter), total, sh.chunk,
+      EXACT ? (const T*)(base + pl.o_tA) : nullptr);
+}
+
+template <typename T, int Q>
+void launch_bpair(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a, hipStream_t st,
+                  const Shape& sh, unsigned int total, int n_cu) {
+  if (pl.exact)
+    launch_bpair_e<T, Q, true>(pl, b, base, a, st, sh, total, n_cu);
+  else
+    launch_bpair_e<T, Q, false>(pl, b, base, a, st, sh, total, n_cu);
 }
 
 template <typename T>
@@ -209,7 +222,8 @@ void launch_bprepare(const BPlan& pl, const BatchDev& b, char* base, const BArgs
   int64_t tot = (int64_t)2 * pl.G * pl.N;
   bchi_kernel<T><<<(unsigned)((tot + 127) / 128), 128, 0, st>>>(
       b, (const double*)(base + pl.o_comp), pl.stride, CompLayout(pl.p, pl.q).nu, pl.G, a.u, pl.N,
-      (T*)(base + pl.o_sA), (T*)(base + pl.o_sB), (T*)(base + pl.o_rsB));
+      (T*)(base + pl.o_sA), (T*)(base + pl.o_sB), (T*)(base + pl.o_rsB),
+      pl.exact ? (T*)(base + pl.o_tA) : nullptr);
 }
 
 // one EM iteration of every active problem; no host synchronisation
@@ -402,9 +416,11 @@ extern "C" int cfust_em_fit_batched(const double* y, int p, int q, int n_problem
   cfust_opts def;
   cfust_default_opts(&def);
   if (!o) o = &def;
-  if (o->max_iter < 0 || o->nu_mode == CFUST_NU_EXACT_FD || o->reorder) return CFUST_EINVAL;
+  if (o->max_iter < 0 || o->reorder) return CFUST_EINVAL;
   BPlan pl;
-  if ((rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, o->precision, o->max_iter, &pl))) return rc;
+  if ((rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, o->precision, o->max_iter,
+                       o->nu_mode == CFUST_NU_EXACT, &pl)))
+    return rc;
   hipStream_t caller = (hipStream_t)o->stream;
   // a library-owned stream (default priority): graph capture is not allowed
   // on the null stream; the caller's earlier work is awaited first
@@ -531,7 +547,6 @@ extern "C" int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q,
     cfust_opts ob = *o;
     ob.max_iter = burn_in;
     ob.tol = 0.0;  // exactly burn_in iterations
-    if (ob.nu_mode == CFUST_NU_EXACT_FD) ob.nu_mode = CFUST_NU_OSL;
     ob.reorder = 0;  // the batched kernels integrate in the natural order
     ob.surrogate = nullptr;
     ob.workspace = nullptr;
@@ -581,7 +596,7 @@ extern "C" int cfust_batched_workspace_size(int p, int q, int n_problems, const 
       n_qmc < 1 || max_iter < 0)
     return CFUST_EINVAL;
   BPlan pl;
-  int rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, precision, max_iter, &pl);
+  int rc = make_bplan(n_problems, p, q, n_obs, g, n_qmc, precision, max_iter, false, &pl);
   if (rc) return rc;
   *bytes = pl.total;
   return CFUST_OK;

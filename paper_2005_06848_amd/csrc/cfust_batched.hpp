@@ -83,7 +83,8 @@ __global__ void bprecompute_kernel(BatchDev b, const double* __restrict__ pi,
 template <typename T>
 __global__ void bchi_kernel(BatchDev b, const double* __restrict__ comp, int comp_stride,
                             int nu_off, int G, const double* __restrict__ u, int N,
-                            T* __restrict__ sA, T* __restrict__ sB, T* __restrict__ rsB) {
+                            T* __restrict__ sA, T* __restrict__ sB, T* __restrict__ rsB,
+                            T* __restrict__ tA) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)2 * G * N) return;
   int which = (int)(t / ((int64_t)G * N));
@@ -94,9 +95,11 @@ __global__ void bchi_kernel(BatchDev b, const double* __restrict__ comp, int com
   if (!b.active[k]) return;
   double v = comp[(size_t)c * comp_stride + nu_off];
   double dof = v + b.p + (which ? 2.0 : 0.0);
-  double s = sqrt(chi2_quantile(u[(size_t)kk * (b.q + 1)], dof) / dof);
+  const double x = chi2_quantile(u[(size_t)kk * (b.q + 1)], dof);
+  double s = sqrt(x / dof);
   if (which == 0) {
     sA[(size_t)c * N + kk] = (T)s;
+    if (tA) tA[(size_t)c * N + kk] = (T)chi_scale_tangent(x, dof, s);
   } else {
     sB[(size_t)c * N + kk] = (T)s;
     rsB[(size_t)c * N + kk] = (T)(1.0 / s);
@@ -108,20 +111,22 @@ __global__ void bchi_kernel(BatchDev b, const double* __restrict__ comp, int com
 // The loop and slot lookup around pair_eval cost registers.  For FP32 at
 // Q = 5 the budget is held at 4 waves per SIMD (128 VGPRs): 7% faster on
 // 64 problems of 5000-50000 observations than 3 waves (159 VGPRs), and the
-// compiler alone picks 2.  Other Q keep the compiler's choice.
+// compiler alone picks 2.  Other Q keep the compiler's choice.  EXACT adds
+// the tangent of integral A (exact E[log W | y]; tA the chi-scale tangent).
 template <typename T, int Q>
 constexpr int bpair_occupancy() {
   return (sizeof(T) == 4 && Q == 5) ? 4 : 1;
 }
 
-template <typename T, int Q>
+template <typename T, int Q, bool EXACT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bpair_occupancy<T, Q>())))
 void bpair_kernel(BatchDev b, const double* __restrict__ y,
                              const double* __restrict__ mu, const double* __restrict__ comp,
                              const T* __restrict__ sA, const T* __restrict__ sB,
                              const T* __restrict__ rsB, const T* __restrict__ uT,
                              const T* __restrict__ ubT, int N, double* __restrict__ pairbuf,
-                             unsigned int* counter, unsigned int total, int chunk) {
+                             unsigned int* counter, unsigned int total, int chunk,
+                             const T* __restrict__ tA) {
   const int lane = threadIdx.x & 63;
   const CompLayout cl(b.p, Q);
   constexpr int RW = record_width<Q, true>();
@@ -141,10 +146,11 @@ void bpair_kernel(BatchDev b, const double* __restrict__ y,
       const int i = (int)(local - j * g);
       const int c = c0 + i;
       double out;
-      bool ok = kOk == pair_eval<T, Q, true>(y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
-                                      comp + (size_t)c * cl.stride, sA + (size_t)c * N,
-                                      sB + (size_t)c * N, rsB + (size_t)c * N, uT, ubT, N, lane,
-                                      &out);
+      bool ok = kOk == pair_eval<T, Q, true, EXACT>(
+                           y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
+                           comp + (size_t)c * cl.stride, sA + (size_t)c * N, sB + (size_t)c * N,
+                           rsB + (size_t)c * N, uT, ubT, N, lane, &out,
+                           EXACT ? tA + (size_t)c * N : nullptr);
       if (!ok) {
         if (lane == 0) fail_problem(b, k, kENonFinite, -1);
         continue;

@@ -114,16 +114,14 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m)
   off = align_up(off + (size_t)g * N * es);
   pl.o_rsB = off;
   off = align_up(off + (size_t)g * N * es);
-  pl.o_sAp = off;
-  off = align_up(off + (size_t)g * N * es);
-  pl.o_sAm = off;
+  pl.o_tA = off;
   off = align_up(off + (size_t)g * N * es);
   pl.o_pair = off;
   off = align_up(off + (size_t)(n > 0 ? n : 1) * g * pl.W * sizeof(double));
   pl.split = split_of(n * g, N);
   if (pl.split > 1) {
-    // widest record: B with moments plus the two exact-nu integrals
-    const size_t pw = 2 + 2 + q + (size_t)q * (q + 1) / 2 + 4;
+    // widest record: A with its tangent, B with moments
+    const size_t pw = 3 + 2 + q + (size_t)q * (q + 1) / 2;
     pl.o_parts = off;
     off = align_up(off + (size_t)n * g * pl.split * pw * sizeof(double));
   }
@@ -227,7 +225,7 @@ int fetch_status(Ws& ws, const Plan& pl, int* bad) {
 int check_opts(const cfust_opts* o) {
   if (!o) return CFUST_OK;
   if (o->precision != CFUST_FP64 && o->precision != CFUST_FP32) return CFUST_EINVAL;
-  if (o->nu_mode != CFUST_NU_OSL && o->nu_mode != CFUST_NU_EXACT_FD &&
+  if (o->nu_mode != CFUST_NU_OSL && o->nu_mode != CFUST_NU_EXACT &&
       o->nu_mode != CFUST_NU_FIXED)
     return CFUST_EINVAL;
   if (!(o->nu_lo > 0.0) || !(o->nu_hi >= o->nu_lo)) return CFUST_EINVAL;
@@ -277,12 +275,11 @@ void launch_prepare(const Ws& ws, const Plan& pl, const double* pi, const double
     points_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, ws.st>>>(
         u, pl.N, q1, ws.at<T>(pl.o_uT), ws.at<T>(pl.o_ubT), ws.at<int>(pl.o_status));
   }
-  const int tables = pl.exact ? 4 : 2;
-  int64_t tot = (int64_t)tables * pl.g * pl.N;
+  int64_t tot = (int64_t)2 * pl.g * pl.N;
   chi_kernel<T><<<(unsigned)((tot + 127) / 128), 128, 0, ws.st>>>(
       ws.at<double>(pl.o_comp), pl.stride, CompLayout(pl.p, pl.q).nu, pl.p, pl.g, u, pl.N, q1,
-      ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB), ws.at<T>(pl.o_rsB), ws.at<T>(pl.o_sAp),
-      ws.at<T>(pl.o_sAm), tables, ws.at<int>(pl.o_status));
+      ws.at<T>(pl.o_sA), ws.at<T>(pl.o_sB), ws.at<T>(pl.o_rsB),
+      pl.exact ? ws.at<T>(pl.o_tA) : nullptr, ws.at<int>(pl.o_status));
 }
 
 
@@ -391,7 +388,7 @@ int check_surrogate(const cfust_opts* o, int q) {
   const cfust_surrogate* s = o->surrogate;
   // the network has no derivative output for the exact E[log W | y], and it
   // was trained on natural-order GHK labels
-  if (o->nu_mode == CFUST_NU_EXACT_FD || o->reorder) return CFUST_EINVAL;
+  if (o->nu_mode == CFUST_NU_EXACT || o->reorder) return CFUST_EINVAL;
   return surrogate_ready(s, q) ? CFUST_OK : CFUST_EINVAL;
 }
 
@@ -403,8 +400,7 @@ int64_t check_of(const cfust_opts* o) {
 // forms that exist only up to kMaxQFull
 int check_q_forms(const cfust_opts* o, int q) {
   if (!o || q <= kMaxQFull) return CFUST_OK;
-  return (o->nu_mode == CFUST_NU_EXACT_FD || o->reorder || o->surrogate) ? CFUST_EINVAL
-                                                                          : CFUST_OK;
+  return (o->reorder || o->surrogate) ? CFUST_EINVAL : CFUST_OK;
 }
 
 }  // namespace
@@ -467,7 +463,7 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
     return CFUST_EINVAL;
   const int prec = o ? o->precision : CFUST_FP64;
   Plan pl = make_plan(n, p, q, g, n_qmc, prec, check_of(o));
-  pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
+  pl.exact = o && o->nu_mode == CFUST_NU_EXACT;
   pl.reorder = o && o->reorder;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
@@ -550,7 +546,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
   if (!o) o = &def;
   if (o->max_iter < 0) return CFUST_EINVAL;
   Plan pl = make_plan(n, p, q, g, n_qmc, o->precision, check_of(o));
-  pl.exact = o && o->nu_mode == CFUST_NU_EXACT_FD;
+  pl.exact = o && o->nu_mode == CFUST_NU_EXACT;
   pl.reorder = o->reorder != 0;
   Ws ws;
   if ((rc = acquire(pl, o, &ws))) return rc;
@@ -612,7 +608,7 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
 
 int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
                        void* stream) {
-  if (!x || !out || n < 0 || fn < 0 || fn > 10 || (fn == 4 && !x2)) return CFUST_EINVAL;
+  if (!x || !out || n < 0 || fn < 0 || fn > 13 || ((fn == 4 || fn == 11) && !x2)) return CFUST_EINVAL;
   if (n == 0) return CFUST_OK;
   hipStream_t st = (hipStream_t)stream;
   special_kernel<<<(unsigned)((n + 127) / 128), 128, 0, st>>>(fn, x, x2, out, n);

@@ -31,10 +31,10 @@ struct Plan {
   int tile, nb, ny;
   int64_t per_block;
   size_t lds_bytes;
-  bool exact = false;    // exact E[log W | y] (nu_mode EXACT_FD)
+  bool exact = false;    // exact E[log W | y] (nu_mode EXACT)
   bool reorder = false;  // Genz-Bretz variable order per pair (opts.reorder)
   // byte offsets inside the workspace
-  size_t o_sAp, o_sAm;
+  size_t o_tA;  // tangent of integral A's chi scale (exact E[log W | y])
   size_t o_status, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll, o_pitmp, o_mwork,
       o_ll, o_stats, total;
   // waves per pair (pair_part_kernel + pair_finish_kernel when > 1)

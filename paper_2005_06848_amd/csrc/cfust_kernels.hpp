@@ -32,9 +32,6 @@ constexpr int kMaxQ = 12;      // E-step, log-likelihood, M-step and EM fit (FP6
 constexpr int kMaxQFull = 8;   // exact nu step, variable ordering, batched form, surrogate
 constexpr int kMaxG = 16;
 
-// relative step in a = (nu+p)/2 of the central difference that gives the
-// exact E[log W | y] (derivative of log T_A with respect to a)
-constexpr double kFdRel = 1e-3;
 
 enum Status : int {
   kOk = 0,
@@ -364,17 +361,16 @@ __global__ void points_kernel(const double* __restrict__ u, int N, int q1, T* __
 // chi scale tables: s[i][k] for dof nu_i + p (integral A) and nu_i + p + 2
 // (integral B), with 1/s for integral B.
 // ---------------------------------------------------------------------------
+// chi scale tables per component: sA (dof nu+p), sB and rsB (dof nu+p+2),
+// and, when tA is not null, the tangent of integral A's scale in
+// a = (nu+p)/2 for the exact E[log W | y] (chi_scale_tangent)
 template <typename T>
-// chi scale tables per component: `tables` = 2 gives sA (dof nu+p) and sB,
-// rsB (dof nu+p+2); 4 adds sAp, sAm at dof (nu+p)(1 +- kFdRel) for the
-// exact E[log W | y]
 __global__ void chi_kernel(const double* __restrict__ comp, int comp_stride, int nu_off, int p,
                            int g, const double* __restrict__ u, int N, int q1,
                            T* __restrict__ sA, T* __restrict__ sB, T* __restrict__ rsB,
-                           T* __restrict__ sAp, T* __restrict__ sAm, int tables,
-                           const int* __restrict__ status) {
+                           T* __restrict__ tA, const int* __restrict__ status) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)tables * g * N) return;
+  if (t >= (int64_t)2 * g * N) return;
   if (status[0] != kOk) return;
   int which = (int)(t / ((int64_t)g * N));
   int rem = (int)(t - (int64_t)which * g * N);
@@ -383,19 +379,15 @@ __global__ void chi_kernel(const double* __restrict__ comp, int comp_stride, int
   double v = comp[(size_t)i * comp_stride + nu_off];
   double dof = v + p;
   if (which == 1) dof += 2.0;
-  if (which == 2) dof *= 1.0 + kFdRel;
-  if (which == 3) dof *= 1.0 - kFdRel;
-  double s = sqrt(chi2_quantile(u[(size_t)k * q1], dof) / dof);
+  const double x = chi2_quantile(u[(size_t)k * q1], dof);
+  double s = sqrt(x / dof);
   const size_t o = (size_t)i * N + k;
   if (which == 0) {
     sA[o] = (T)s;
-  } else if (which == 1) {
+    if (tA) tA[o] = (T)chi_scale_tangent(x, dof, s);
+  } else {
     sB[o] = (T)s;
     rsB[o] = (T)(1.0 / s);
-  } else if (which == 2) {
-    sAp[o] = (T)s;
-  } else {
-    sAm[o] = (T)s;
   }
 }
 
@@ -453,29 +445,40 @@ __device__ __forceinline__ int shift_of(int d) { return max(d, -1100); }
 // ---------------------------------------------------------------------------
 // Wave-uniform sums of one GHK integral over a subset of the points, scaled
 // by 2^-R: S0 = sum w, S1 = sum w ehat, S2 = sum w ehat ehat^T (upper
-// triangle).  A subset's R is the largest exponent of its lanes; an empty
+// triangle), and with TAN (integral A of the exact E[log W | y])
+// D = sum w (log w)', the weights' derivative along the tangent of the
+// scale.  A subset's R is the largest exponent of its lanes; an empty
 // subset has R at the exponent floor and zero sums.
-template <int Q, bool MOM>
+template <int Q, bool MOM, bool TAN = false>
 struct GhkPart {
   static constexpr int NT = Q * (Q + 1) / 2;
   double R, S0;
   double S1[MOM ? Q : 1];
   double S2[MOM ? NT : 1];
+  double D;
 };
 
 // Sums of the points k0 + lane, k0 + lane + kstep, ... below N (lane t of
 // the wave; kstep a multiple of 64).  Every lane returns the wave's sums.
-template <typename T, int Q, bool MOM>
+// With TAN the factor of ht at point k moves at rate t_tab[k]; the weight's
+// log-derivative follows by the chain rule through the sequential bounds and
+// draws: ub_m' = t ht_m - sum_{l<m} Ct_ml eps_l', (log Phi(ub_m))' =
+// phi(ub_m)/Phi(ub_m) ub_m', and, from Phi(eps_m) = u_m Phi(ub_m),
+// eps_m' = u_m phi(ub_m)/phi(eps_m) ub_m'.
+template <typename T, int Q, bool MOM, bool TAN = false>
 __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
                                          const T* __restrict__ s_tab,
                                          const T* __restrict__ rs_tab,
+                                         const T* __restrict__ t_tab,
                                          const T* __restrict__ uT, const T* __restrict__ ubT,
                                          int N, int k0, int kstep, int lane,
-                                         GhkPart<Q, MOM>& part) {
+                                         GhkPart<Q, MOM, TAN>& part) {
+  static_assert(!(MOM && TAN), "the tangent is taken of integral A only");
   constexpr int NT = Q * (Q + 1) / 2;
   using E = decltype(PhiVal<T>::n);  // exponent type: double (FP64) or int (FP32)
-  Acc<T> b0, b1[MOM ? Q : 1], b2[MOM ? NT : 1];
+  Acc<T> b0, b1[MOM ? Q : 1], b2[MOM ? NT : 1], bt;
   b0.zero();
+  bt.zero();
   if (MOM) {
 #pragma unroll
     for (int m = 0; m < Q; ++m) b1[m].zero();
@@ -486,8 +489,9 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
 #pragma unroll 1
   for (int k = k0 + lane; k < N; k += kstep) {
     const T s = s_tab[k];
-    T eps[Q];
-    T prod = T(1);
+    const T tk = TAN ? t_tab[k] : T(0);
+    T eps[Q], deps[TAN ? Q : 1];
+    T prod = T(1), dlw = T(0);
     E ex = 0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
@@ -499,10 +503,18 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
       ex += cc.n;
       if (MOM || m < Q - 1)
         eps[m] = draw_eval(uT[(size_t)(m + 1) * N + k], ubT[(size_t)(m + 1) * N + k], cc);
+      if constexpr (TAN) {
+        T dub = tk * ht[m];
+#pragma unroll
+        for (int l = 0; l < m; ++l) dub -= Ct[m][l] * deps[l];
+        dlw += mills(cc) * dub;
+        if (m < Q - 1) deps[m] = uT[(size_t)(m + 1) * N + k] * dens_ratio(eps[m], bnd) * dub;
+      }
     }
     if (ex > ref + Prec<T>::kRescale) {
       T f = Prec<T>::ldexp_(T(1), shift_of(ref - ex));
       b0.scale(f);
+      if (TAN) bt.scale(f);
       if (MOM) {
 #pragma unroll
         for (int m = 0; m < Q; ++m) b1[m].scale(f);
@@ -513,6 +525,7 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
     }
     T wgt = Prec<T>::ldexp_(prod, shift_of(ex - ref));
     b0.add(wgt);
+    if (TAN) bt.add_prod(wgt, dlw);
     if (MOM) {
       const T rs = rs_tab[k];
       T eh[Q];
@@ -534,6 +547,7 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
   double sc = ldexp(1.0, shift_of(ref - R));
   part.R = (double)R;
   part.S0 = wave_sum(b0.value() * sc);
+  part.D = TAN ? wave_sum(bt.value() * sc) : 0.0;
   if (MOM) {
 #pragma unroll
     for (int m = 0; m < Q; ++m) part.S1[m] = wave_sum(b1[m].value() * sc);
@@ -544,8 +558,8 @@ __device__ __forceinline__ void ghk_sums(const T (&ht)[Q], const T (&Ct)[Q][Q],
 
 // log P(V <= h) and, with MOM, E[V | V <= h] = C S1/S0 and
 // E[V V^T | V <= h] = C (S2/S0) C^T from the sums of all N points.
-template <int Q, bool MOM>
-__device__ __forceinline__ void ghk_finish(const GhkPart<Q, MOM>& part,
+template <int Q, bool MOM, bool TAN = false>
+__device__ __forceinline__ void ghk_finish(const GhkPart<Q, MOM, TAN>& part,
                                            const double* __restrict__ C, int N, double* logT,
                                            double (&m1)[Q], double (&m2)[Q][Q]) {
   const double S0 = part.S0;
@@ -591,14 +605,16 @@ __device__ __forceinline__ void ghk_finish(const GhkPart<Q, MOM>& part,
 
 // Sums of several subsets combined in a fixed order (their references
 // aligned to the largest).
-template <int Q, bool MOM>
-__device__ __forceinline__ void ghk_combine(GhkPart<Q, MOM>& acc, const GhkPart<Q, MOM>& x) {
+template <int Q, bool MOM, bool TAN = false>
+__device__ __forceinline__ void ghk_combine(GhkPart<Q, MOM, TAN>& acc,
+                                            const GhkPart<Q, MOM, TAN>& x) {
   constexpr int NT = Q * (Q + 1) / 2;
   const double R = fmax(acc.R, x.R);
   const double fa = ldexp(1.0, shift_of(acc.R - R));
   const double fx = ldexp(1.0, shift_of(x.R - R));
   acc.R = R;
   acc.S0 = acc.S0 * fa + x.S0 * fx;
+  if (TAN) acc.D = acc.D * fa + x.D * fx;
   if (MOM) {
 #pragma unroll
     for (int m = 0; m < Q; ++m) acc.S1[m] = acc.S1[m] * fa + x.S1[m] * fx;
@@ -618,7 +634,7 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
                                              int N, int lane, double* logT, double (&m1)[Q],
                                              double (&m2)[Q][Q]) {
   GhkPart<Q, MOM> part;
-  ghk_sums<T, Q, MOM>(ht, Ct, s_tab, rs_tab, uT, ubT, N, 0, 64, lane, part);
+  ghk_sums<T, Q, MOM>(ht, Ct, s_tab, rs_tab, nullptr, uT, ubT, N, 0, 64, lane, part);
   ghk_finish<Q, MOM>(part, C, N, logT, m1, m2);
 }
 
@@ -626,7 +642,6 @@ __device__ __forceinline__ void ghk_integral(const T (&ht)[Q], const T (&Ct)[Q][
 // Variable ordering (Genz & Bretz 2009, section 4.1.3) for the GHK integrals
 // of one pair.
 // ---------------------------------------------------------------------------
-constexpr double kSqrt2OverPi = 0.79788456080286535588;  // sqrt(2 / pi)
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;   // 1 / sqrt(2 pi)
 
 // E[Z | Z <= b] for Z ~ N(0, 1), i.e. -phi(b) / Phi(b); for b < 0 written
@@ -731,17 +746,18 @@ __host__ __device__ constexpr int record_width() {
 // Returns kOk, kENonFinite if y_j is not finite, or kENotPD if the ordered
 // factorisation meets a non-positive pivot.
 // ---------------------------------------------------------------------------
-// doubles of one partial-sum record: A (R, S0) | B (R, S0, S1[Q], S2[NT]) |
-// the two exact-nu integrals (R, S0) each
+// doubles of one partial-sum record: A (R, S0, and D with the exact
+// E[log W | y]) | B (R, S0, S1[Q], S2[NT])
 template <int Q, bool MOM, bool EXACT>
 __host__ __device__ constexpr int part_width() {
-  return 2 + (MOM ? 2 + Q + Q * (Q + 1) / 2 : 0) + ((EXACT && MOM) ? 4 : 0);
+  return 2 + ((EXACT && MOM) ? 1 : 0) + (MOM ? 2 + Q + Q * (Q + 1) / 2 : 0);
 }
 
-template <int Q, bool MOM>
-__device__ __forceinline__ void part_store(const GhkPart<Q, MOM>& x, double* o) {
+template <int Q, bool MOM, bool TAN = false>
+__device__ __forceinline__ void part_store(const GhkPart<Q, MOM, TAN>& x, double* o) {
   o[0] = x.R;
   o[1] = x.S0;
+  if (TAN) o[2] = x.D;
   if (MOM) {
 #pragma unroll
     for (int m = 0; m < Q; ++m) o[2 + m] = x.S1[m];
@@ -750,10 +766,12 @@ __device__ __forceinline__ void part_store(const GhkPart<Q, MOM>& x, double* o) 
   }
 }
 
-template <int Q, bool MOM>
-__device__ __forceinline__ void part_load(const double* __restrict__ o, GhkPart<Q, MOM>& x) {
+template <int Q, bool MOM, bool TAN = false>
+__device__ __forceinline__ void part_load(const double* __restrict__ o,
+                                          GhkPart<Q, MOM, TAN>& x) {
   x.R = o[0];
   x.S0 = o[1];
+  x.D = TAN ? o[2] : 0.0;
   if (MOM) {
 #pragma unroll
     for (int m = 0; m < Q; ++m) x.S1[m] = o[2 + m];
@@ -763,14 +781,14 @@ __device__ __forceinline__ void part_load(const double* __restrict__ o, GhkPart<
 }
 
 // the K records at part combined in order 0, 1, ..., K-1
-template <int Q, bool MOM>
+template <int Q, bool MOM, bool TAN = false>
 __device__ __forceinline__ void part_reduce(const double* __restrict__ part, int PW, int off,
-                                            int K, GhkPart<Q, MOM>& acc) {
-  part_load<Q, MOM>(part + off, acc);
+                                            int K, GhkPart<Q, MOM, TAN>& acc) {
+  part_load<Q, MOM, TAN>(part + off, acc);
   for (int k = 1; k < K; ++k) {
-    GhkPart<Q, MOM> x;
-    part_load<Q, MOM>(part + (size_t)k * PW + off, x);
-    ghk_combine<Q, MOM>(acc, x);
+    GhkPart<Q, MOM, TAN> x;
+    part_load<Q, MOM, TAN>(part + (size_t)k * PW + off, x);
+    ghk_combine<Q, MOM, TAN>(acc, x);
   }
 }
 
@@ -781,13 +799,12 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
                                          const T* __restrict__ sAi, const T* __restrict__ sBi,
                                          const T* __restrict__ rsBi, const T* __restrict__ uT,
                                          const T* __restrict__ ubT, int N, int lane,
-                                         double* lane_out, const T* __restrict__ sApi = nullptr,
-                                         const T* __restrict__ sAmi = nullptr,
+                                         double* lane_out, const T* __restrict__ tAi = nullptr,
                                          double* cw = nullptr, double* part = nullptr,
                                          int k0 = 0, int kstep = 64, int K = 1) {
-  constexpr int NT = Q * (Q + 1) / 2;
   constexpr int PW = part_width<Q, MOM, EXACT>();
-  constexpr int OFF_B = 2, OFF_P = 2 + (MOM ? 2 + Q + NT : 0), OFF_M = OFF_P + 2;
+  constexpr bool TAN = EXACT && MOM;  // integral A carries its tangent
+  constexpr int OFF_B = TAN ? 3 : 2;
   const CompLayout cl(p, Q);
   const double v = cp[cl.nu];
 
@@ -873,69 +890,36 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
   }
 
   // ---- a5 / a6: the two GHK integrals over this lane's points ----
-  // (the exact-nu integrals at bounds h_A sqrt(1 +- kFdRel) with it)
-  double logTA, logTB = 0.0, lp = 0.0, lm = 0.0;
+  // (integral A with the tangent of its estimate for the exact nu step)
+  double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
-  T hp[Q], hm[Q];
-  if (EXACT && MOM) {
-#pragma unroll
-    for (int m = 0; m < Q; ++m) {
-      hp[m] = (T)(hAd[m] * sqrt(1.0 + kFdRel));
-      hm[m] = (T)(hAd[m] * sqrt(1.0 - kFdRel));
-    }
-  }
+  GhkPart<Q, false, TAN> pa;
   if constexpr (PHASE == 0) {
-    ghk_integral<T, Q, false>(htA, Ct, Cm, sAi, nullptr, uT, ubT, N, lane, &logTA, m1, m2);
+    ghk_sums<T, Q, false, TAN>(htA, Ct, sAi, nullptr, tAi, uT, ubT, N, 0, 64, lane, pa);
+    ghk_finish<Q, false, TAN>(pa, Cm, N, &logTA, m1, m2);
     if (MOM) ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
-    if (EXACT && MOM) {
-      ghk_integral<T, Q, false>(hp, Ct, Cm, sApi, nullptr, uT, ubT, N, lane, &lp, m1, m2);
-      ghk_integral<T, Q, false>(hm, Ct, Cm, sAmi, nullptr, uT, ubT, N, lane, &lm, m1, m2);
-    }
   } else if constexpr (PHASE == 1) {
-    GhkPart<Q, false> pa;
-    ghk_sums<T, Q, false>(htA, Ct, sAi, nullptr, uT, ubT, N, k0, kstep, lane, pa);
-    if (lane == 0) part_store<Q, false>(pa, part);
+    ghk_sums<T, Q, false, TAN>(htA, Ct, sAi, nullptr, tAi, uT, ubT, N, k0, kstep, lane, pa);
+    if (lane == 0) part_store<Q, false, TAN>(pa, part);
     if (MOM) {
       GhkPart<Q, MOM> pb;
-      ghk_sums<T, Q, MOM>(htB, Ct, sBi, rsBi, uT, ubT, N, k0, kstep, lane, pb);
+      ghk_sums<T, Q, MOM>(htB, Ct, sBi, rsBi, nullptr, uT, ubT, N, k0, kstep, lane, pb);
       if (lane == 0) part_store<Q, MOM>(pb, part + OFF_B);
-    }
-    if (EXACT && MOM) {
-      GhkPart<Q, false> pp, pm;
-      ghk_sums<T, Q, false>(hp, Ct, sApi, nullptr, uT, ubT, N, k0, kstep, lane, pp);
-      ghk_sums<T, Q, false>(hm, Ct, sAmi, nullptr, uT, ubT, N, k0, kstep, lane, pm);
-      if (lane == 0) {
-        part_store<Q, false>(pp, part + OFF_P);
-        part_store<Q, false>(pm, part + OFF_M);
-      }
     }
     return kOk;
   } else {
-    GhkPart<Q, false> pa;
-    part_reduce<Q, false>(part, PW, 0, K, pa);
-    ghk_finish<Q, false>(pa, Cm, N, &logTA, m1, m2);
+    part_reduce<Q, false, TAN>(part, PW, 0, K, pa);
+    ghk_finish<Q, false, TAN>(pa, Cm, N, &logTA, m1, m2);
     if (MOM) {
       GhkPart<Q, MOM> pb;
       part_reduce<Q, MOM>(part, PW, OFF_B, K, pb);
       ghk_finish<Q, MOM>(pb, Cm, N, &logTB, m1, m2);
     }
-    if (EXACT && MOM) {
-      GhkPart<Q, false> pp, pm;
-      part_reduce<Q, false>(part, PW, OFF_P, K, pp);
-      part_reduce<Q, false>(part, PW, OFF_M, K, pm);
-      ghk_finish<Q, false>(pp, Cm, N, &lp, m1, m2);
-      ghk_finish<Q, false>(pm, Cm, N, &lm, m1, m2);
-    }
   }
 
-  // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a
-  // by a central difference over the same points ----
-  double dlogJ = 0.0;
-  bool fd_ok = false;
-  if (EXACT && MOM) {
-    fd_ok = isfinite(lp) && isfinite(lm);
-    dlogJ = (lp - lm) / (2.0 * kFdRel * 0.5 * (v + p));
-  }
+  // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a,
+  // the derivative of the estimate over the same points ----
+  const double dlogJ = TAN ? pa.D / pa.S0 : 0.0;
 
   // moments back to the original labelling: m1[perm[m]] = m1'[m],
   // m2[perm[m]][perm[n]] = m2'[m][n] (rows, then columns, by selects)
@@ -996,8 +980,8 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
     }
     put(1, e2);
     // e1 - e2: one-step-late psi(a) - log b - a/b, or with the exact derivative
-    const double e1m2 = (EXACT && ok && fd_ok) ? (cp[cl.psi_a] - log(bb) + dlogJ - e2)
-                                               : (cp[cl.psi_a] - log(bb) - aa / bb);
+    const double e1m2 = (TAN && ok) ? (cp[cl.psi_a] - log(bb) + dlogJ - e2)
+                                    : (cp[cl.psi_a] - log(bb) - aa / bb);
     put(2, e1m2);
 #pragma unroll
     for (int k = 0; k < Q; ++k) put(3 + k, ok ? e2 * (c[k] - mx[k]) : 0.0);
@@ -1020,15 +1004,14 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
 
 // one wave per pair, four pairs per 256-thread block; OCC > 0 asks for at
 // least OCC resident waves per SIMD (the register budget follows); EXACT adds
-// the two integrals of the exact E[log W | y]
+// the tangent of integral A for the exact E[log W | y]
 template <typename T, int Q, bool MOM, int OCC = 0, bool EXACT = false, bool REORDER = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 void pair_kernel(
     const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
     const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N,
-    double* __restrict__ pairbuf, int W, int* status, const T* __restrict__ sAp = nullptr,
-    const T* __restrict__ sAm = nullptr) {
+    double* __restrict__ pairbuf, int W, int* status, const T* __restrict__ tA = nullptr) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pair = (int64_t)blockIdx.x * 4 + wv;
@@ -1044,8 +1027,7 @@ void pair_kernel(
   const int rc = pair_eval<T, Q, MOM, EXACT, REORDER>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
       sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
-      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr,
-      REORDER ? cfac + wv * Q * Q : nullptr);
+      EXACT ? tA + (size_t)i * N : nullptr, REORDER ? cfac + wv * Q * Q : nullptr);
   if (rc != kOk) {
     if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
     return;
@@ -1067,8 +1049,7 @@ void pair_part_kernel(
     const double* __restrict__ y, int64_t n, int p, int g, const double* __restrict__ mu,
     const double* __restrict__ comp, const T* __restrict__ sA, const T* __restrict__ sB,
     const T* __restrict__ rsB, const T* __restrict__ uT, const T* __restrict__ ubT, int N, int K,
-    double* __restrict__ parts, int* status, const T* __restrict__ sAp = nullptr,
-    const T* __restrict__ sAm = nullptr) {
+    double* __restrict__ parts, int* status, const T* __restrict__ tA = nullptr) {
   constexpr int PW = part_width<Q, MOM, EXACT>();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1084,8 +1065,8 @@ void pair_part_kernel(
   const int rc = pair_eval<T, Q, MOM, EXACT, REORDER, 1>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
       sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
-      EXACT ? sAp + (size_t)i * N : nullptr, EXACT ? sAm + (size_t)i * N : nullptr, nullptr,
-      parts + (size_t)w * PW, 64 * sub, 64 * K, K);
+      EXACT ? tA + (size_t)i * N : nullptr, nullptr, parts + (size_t)w * PW, 64 * sub, 64 * K,
+      K);
   if (rc != kOk && lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
 }
 
@@ -1108,7 +1089,7 @@ __global__ __launch_bounds__(256) void pair_finish_kernel(
   double out[RW > 64 ? 2 : 1];
   const int rc = pair_eval<T, Q, MOM, EXACT, REORDER, 2>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, nullptr, nullptr, nullptr,
-      nullptr, nullptr, N, lane, out, nullptr, nullptr, REORDER ? cfac + wv * Q * Q : nullptr,
+      nullptr, nullptr, N, lane, out, nullptr, REORDER ? cfac + wv * Q * Q : nullptr,
       const_cast<double*>(parts) + (size_t)pair * K * PW, 0, 64, K);
   if (rc != kOk) {
     if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
@@ -1691,7 +1672,7 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
       c.n = 0.0;
       c.ebar = 0.0;
       c.neg = false;
-      c.lphi = 0.0;
+      c.ex = 1.0;
       r = draw_eval(a, 1.0 - a, c);
       break;
     }
@@ -1711,12 +1692,15 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
       c.n = 0;
       c.ebar = 0.0f;
       c.neg = false;
-      c.lphi = 0.0;
+      c.ex = 1.0f;
       r = (double)draw_eval((float)a, (float)(1.0 - a), c);
       break;
     }
     case 9: r = log_(a); break;
     case 10: r = sqrt_(a); break;
+    case 11: r = chi2_quantile_ddof(chi2_quantile(a, x2[t]), x2[t]); break;  // d x / d dof
+    case 12: r = mills(phi_eval(a)); break;                                  // phi / Phi
+    case 13: r = (double)mills(phi_eval((float)a)); break;                   // FP32
     default: r = NAN;
   }
   out[t] = r;

@@ -56,7 +56,7 @@ struct PhiVal {
   typename std::conditional<sizeof(T) == 8, double, int>::type n;
   T ebar;     // 1 - Phi(ub)
   bool neg;   // ub < 0
-  double lphi;  // unused (kept zero)
+  T ex;       // erfcx(|ub| / sqrt 2)
 };
 
 // FP64 building blocks --------------------------------------------------------
@@ -185,7 +185,7 @@ __device__ __forceinline__ PhiVal<double> phi_eval(double ub) {
   v.m = v.neg ? mh : 1.0 - small;
   v.n = v.neg ? n : 0.0;
   v.ebar = v.neg ? 1.0 - small : small;
-  v.lphi = 0.0;
+  v.ex = ex;
   return v;
 }
 
@@ -263,7 +263,7 @@ __device__ __forceinline__ PhiVal<float> phi_eval(float ub) {
   v.n = v.neg ? n : 0;
   v.ebar = v.neg ? 1.0f - small : small;
   v.e = v.neg ? small : v.m;
-  v.lphi = 0.0;
+  v.ex = ex;
   return v;
 }
 
@@ -283,6 +283,40 @@ __device__ __forceinline__ float draw_eval(float u, float ubar, const PhiVal<flo
     w = (float)deep_draw_f((double)L2 * kLn2);
   }
   return lower ? w : -w;
+}
+
+// ---------------------------------------------------------------------------
+// Pieces of the derivative of a GHK weight (the exact E[log W | y]).
+// ---------------------------------------------------------------------------
+constexpr double kSqrt2OverPi = 0.79788456080286535588;  // sqrt(2 / pi)
+
+// phi(ub) / Phi(ub) from the pieces of phi_eval, with z = |ub| / sqrt 2 and
+// ex = erfcx(z): below zero Phi(ub) = ex exp(-z^2) / 2 and phi(ub) =
+// exp(-z^2) / sqrt(2 pi), so the ratio is sqrt(2/pi) / ex; above zero
+// ebar = 1 - Phi(ub) = ex exp(-z^2) / 2 gives phi(ub) = sqrt(2/pi) ebar / ex
+// and the ratio sqrt(2/pi) ebar / (ex Phi(ub)).
+__device__ __forceinline__ double mills(const PhiVal<double>& v) {
+  const double num = v.neg ? 1.0 : v.ebar;
+  const double den = v.neg ? v.ex : v.ex * v.m;
+  return kSqrt2OverPi * num * rcp_(den);
+}
+__device__ __forceinline__ float mills(const PhiVal<float>& v) {
+  const float num = v.neg ? 1.0f : v.ebar;
+  const float den = v.neg ? v.ex : v.ex * v.m;
+  return (float)kSqrt2OverPi * num * __builtin_amdgcn_rcpf(den);
+}
+
+// phi(ub) / phi(eps) = exp((eps^2 - ub^2) / 2), the argument clamped to a
+// range where the result is 0 or finite.
+__device__ __forceinline__ double dens_ratio(double eps, double ub) {
+  const double x = fmin(fmax(0.5 * (eps - ub) * (eps + ub), -1000.0), 700.0);
+  double n;
+  const double r = exp_split(x, &n);
+  return ldexp(r, (int)n);
+}
+__device__ __forceinline__ float dens_ratio(float eps, float ub) {
+  const float x = fminf(fmaxf(0.5f * (eps - ub) * (eps + ub), -100.0f), 80.0f);
+  return __builtin_amdgcn_exp2f(x * kLog2eF);
 }
 
 // ---------------------------------------------------------------------------
@@ -373,6 +407,40 @@ __device__ double chi2_quantile(double u, double dof) {
     x = xn;
   }
   return 2.0 * x;
+}
+
+// Derivative of the chi-square quantile x (P(dof/2, x/2) = u) in the degrees
+// of freedom.  With a = dof/2 and z = x/2, implicit differentiation gives
+// dz/da = -(dP/da) / (dP/dz) and dx/d(dof) = dz/da, where
+// dP/dz = z^(a-1) e^-z / Gamma(a) and, term by term from the series of P,
+// dP/da = sum_k w_k (log z - psi(a+k+1)), w_k = e^-z z^(a+k) / Gamma(a+k+1).
+// The terms follow by recurrence (w_k = w_{k-1} z / (a+k),
+// psi(a+k+1) = psi(a+k) + 1/(a+k)) and stop past their peak once below 1e-20.
+__device__ double digamma_(double x);
+__device__ double chi2_quantile_ddof(double x, double dof) {
+  const double a = 0.5 * dof, z = 0.5 * x, lz = log(z);
+  double w = exp(a * lz - z - lgamma(a + 1.0));
+  double ps = digamma_(a + 1.0);
+  double sum = w * (lz - ps);
+  for (int k = 1; k < 100000; ++k) {
+    const double ak = a + k;
+    w *= z / ak;
+    ps += 1.0 / ak;
+    sum += w * (lz - ps);
+    if (ak > z && w < 1e-20) break;
+  }
+  const double dPdz = exp((a - 1.0) * lz - z - lgamma(a));
+  return -sum / dPdz;
+}
+
+// Tangent of the chi scale of integral A in a' = dof'/2 at a' = a: the bounds
+// of J(a') are s(a') h sqrt(a'/a) with s(a') = sqrt(x(2a') / (2a')), so the
+// factor of h moves at 2 ds/d(dof) + s / dof, with
+// ds/d(dof) = (dx/d(dof) / dof - x / dof^2) / (2 s).
+__device__ double chi_scale_tangent(double x, double dof, double s) {
+  const double dx = chi2_quantile_ddof(x, dof);
+  const double ds = (dx / dof - x / (dof * dof)) / (2.0 * s);
+  return 2.0 * ds + s / dof;
 }
 
 // ---------------------------------------------------------------------------

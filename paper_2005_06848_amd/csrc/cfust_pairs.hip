@@ -38,19 +38,19 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
   int* status = ws.at<int>(pl.o_status);
   const T *sA = ws.at<T>(pl.o_sA), *sB = ws.at<T>(pl.o_sB), *rsB = ws.at<T>(pl.o_rsB);
   const T *uT = ws.at<T>(pl.o_uT), *ubT = ws.at<T>(pl.o_ubT);
-  // the exact-nu variants exist for the E-step only (MOM); the ordered ones
-  // keep the default occupancy (the ordering adds registers).  Above
-  // kMaxQFull only the natural-order kernel exists (the entry points reject
-  // the other forms there).
+  const T* tA = pl.exact ? ws.at<T>(pl.o_tA) : nullptr;
+  // The exact-nu variants (tangent of integral A) exist for the E-step only
+  // (MOM) and keep the compiler's occupancy in the one-wave kernel, as do the
+  // ordered ones (both add registers).  Above kMaxQFull the ordered kernels
+  // do not exist (the entry points reject the ordering there).
   if (pl.split > 1 && !pl.reorder) {
     const int K = pl.split;
     double* parts = ws.at<double>(pl.o_parts);
     const unsigned pblocks = (unsigned)((pairs * K + 3) / 4);
-    if constexpr (MOM && Q <= kMaxQFull) {
+    if constexpr (MOM) {
       if (pl.exact) {
         pair_part_kernel<T, Q, MOM, OCC, true><<<pblocks, 256, 0, ws.st>>>(
-            y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status,
-            ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
+            y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, K, parts, status, tA);
         pair_finish_kernel<T, Q, MOM, true><<<blocks, 256, 0, ws.st>>>(
             y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
         return;
@@ -62,32 +62,31 @@ void launch_pairs_q(const Ws& ws, const Plan& pl, const double* y, const double*
         y, pl.n, pl.p, pl.g, mu, comp, pl.N, K, parts, pairs_out, pl.W, status);
     return;
   }
-  if constexpr (Q > kMaxQFull) {
-    pair_kernel<T, Q, MOM><<<blocks, 256, 0, ws.st>>>(
-        y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
-  } else if constexpr (MOM) {
-    if (pl.exact && pl.reorder)
-      pair_kernel<T, Q, MOM, 0, true, true><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
-          ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
-    else if (pl.exact)
+  if constexpr (MOM) {
+    if (pl.exact) {
+      if constexpr (Q <= kMaxQFull) {
+        if (pl.reorder) {
+          pair_kernel<T, Q, MOM, 0, true, true><<<blocks, 256, 0, ws.st>>>(
+              y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
+              tA);
+          return;
+        }
+      }
       pair_kernel<T, Q, MOM, 0, true><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status,
-          ws.at<T>(pl.o_sAp), ws.at<T>(pl.o_sAm));
-    else if (pl.reorder)
-      pair_kernel<T, Q, MOM, 0, false, true><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
-    else
-      pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
-  } else {
-    if (pl.reorder)
-      pair_kernel<T, Q, MOM, 0, false, true><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
-    else
-      pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
-          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status, tA);
+      return;
+    }
   }
+  if constexpr (Q <= kMaxQFull) {
+    if (pl.reorder) {
+      pair_kernel<T, Q, MOM, 0, false, true><<<blocks, 256, 0, ws.st>>>(
+          y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
+      return;
+    }
+  }
+  // natural order
+  pair_kernel<T, Q, MOM, OCC><<<blocks, 256, 0, ws.st>>>(
+      y, pl.n, pl.p, pl.g, mu, comp, sA, sB, rsB, uT, ubT, pl.N, pairs_out, pl.W, status);
 }
 
 

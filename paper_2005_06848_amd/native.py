@@ -16,7 +16,7 @@ LIB_PATH = _build.LIB_PATH
 
 OK, EINVAL, ENOTPD, ENONFINITE, EHIP, ENOMEM = 0, 1, 2, 3, 4, 5
 FP64, FP32 = 0, 1
-NU_OSL, NU_EXACT_FD, NU_FIXED = 0, 1, 2
+NU_OSL, NU_EXACT, NU_FIXED = 0, 1, 2
 
 
 class CfustError(RuntimeError):
@@ -186,7 +186,7 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
-    o.nu_mode = ({"osl": NU_OSL, "exact": NU_EXACT_FD, "fixed": NU_FIXED}[nu_mode]
+    o.nu_mode = ({"osl": NU_OSL, "exact": NU_EXACT, "fixed": NU_FIXED}[nu_mode]
                  if isinstance(nu_mode, str) else int(nu_mode))
     o.fix_delta_zero = int(bool(fix_delta_zero))
     o.max_iter = int(max_iter)

@@ -86,6 +86,28 @@ def test_special_functions(dev):
     np.testing.assert_allclose(native.cfust_eval_special(9, T(xl, dev)).cpu().numpy(), np.log(xl), rtol=4e-16, atol=4e-16)
     xs2 = np.logspace(-200, 200, 200)
     np.testing.assert_allclose(native.cfust_eval_special(10, T(xs2, dev)).cpu().numpy(), np.sqrt(xs2), rtol=3e-16)
+    # pieces of the exact nu step: the chi-square quantile's derivative in
+    # the dof (against the oracle's, itself pinned by mpmath) and the
+    # inverse Mills ratio phi/Phi (against scipy), FP64 and FP32
+    import oracle
+    for dof in [3.5, 9.3, 17.0, 60.0, 212.0]:
+        uq = np.array([0.5 / 2 ** 30, 1e-6, 0.3, 0.5, 0.77, 0.999, 0.99994])
+        d = native.cfust_eval_special(11, T(uq, dev), T(np.full(uq.size, dof), dev)).cpu().numpy()
+        ref = np.array([oracle.chi2_quantile_ddof(v, dof) for v in uq])
+        tol = np.where(uq > 0.99, 1e-10, 1e-12)
+        assert np.all(np.abs(d - ref) <= tol * np.abs(ref)), (dof, d, ref)
+    xm = np.concatenate([np.linspace(-30, 9, 157), [-200.0, 20.0]])
+    # below zero phi/Phi = sqrt(2/pi) / erfcx(-x/sqrt 2) (no cancellation)
+    with np.errstate(invalid="ignore"):
+        mref = np.where(xm < 0, np.sqrt(2 / np.pi) / sp.erfcx(-xm / np.sqrt(2)),
+                        np.exp(-0.5 * xm * xm) / np.sqrt(2 * np.pi) / sp.ndtr(xm))
+    m64 = native.cfust_eval_special(12, T(xm, dev)).cpu().numpy()
+    np.testing.assert_allclose(m64, mref, rtol=1e-13)
+    # FP32: above zero the ratio carries exp(-x^2/2), whose float argument
+    # has a relative rounding of about x^2 * 6e-8 / 2 (2.4e-6 at x = 9)
+    m32 = native.cfust_eval_special(13, T(xm, dev)).cpu().numpy()
+    ok32 = xm < 9  # above that phi(x) is below the float range
+    np.testing.assert_allclose(m32[ok32], mref[ok32], rtol=1e-5)
 
 
 def test_estep_config1(dev, orc):
@@ -401,7 +423,7 @@ def test_split_waves_parity(dev, orc, shape):
     n, p, q, g, N = shape
     c = inputs.random_case(201 + n, n, p, q, g, N)
     y, par, u = c["y"], c["params"], c["u"]
-    for mode, omode in (("osl", orc.NU_OSL), ("exact", orc.NU_EXACT_FD)):
+    for mode, omode in (("osl", orc.NU_OSL), ("exact", orc.NU_EXACT)):
         ref = orc.estep(y, par, u, nu_mode=omode)
         print(f"[gpu] split estep n={n} q={q} g={g} N={N} {mode}", flush=True)
         g_ = native.cfust_estep(T(y, dev), gpu_params(par, dev), T(u, dev), nu_mode=mode)

@@ -87,7 +87,7 @@ def test_reorder_loglik_and_exact_nu(dev, orc):
     ll, lf = native.cfust_loglik(T(y, dev), P(par, dev), T(u, dev), want_logf=True, reorder=True)
     assert abs(float(ll) - ll_ref) <= TOL * abs(ll_ref)
     assert np.max(np.abs(lf.cpu().numpy() - lf_ref)) <= TOL
-    ref = orc.estep(y, par, u, nu_mode=orc.NU_EXACT_FD, reorder=True)
+    ref = orc.estep(y, par, u, nu_mode=orc.NU_EXACT, reorder=True)
     got = gpu_estep(dev, y, par, u, nu_mode="exact")
     err = parity.estep_errors(got, ref, 5, 4)
     assert max(err.values()) <= TOL, err

@@ -387,7 +387,7 @@ def test_stats_assembly_recomputed(orc, shape):
     mis-packed triangle changes the layout and fails."""
     n, p, q, g = shape
     c = inputs.random_case(500 + n + p, n, p, q, g, 256)
-    for mode in (orc.NU_OSL, orc.NU_EXACT_FD):
+    for mode in (orc.NU_OSL, orc.NU_EXACT_FD, orc.NU_EXACT):
         out = orc.estep(c["y"], c["params"], c["u"], nu_mode=mode)
         ref = _stats_from_pairs(c["y"], np.asarray(c["params"]["mu"]), out["tau"], out["e1"],
                                 out["e2"], out["e3"], out["e4"])
