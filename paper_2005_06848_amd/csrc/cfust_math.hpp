@@ -73,6 +73,16 @@ __device__ __forceinline__ int opaque_zero() {
   asm volatile("s_mov_b32 %0, 0" : "=s"(z));
   return z;
 }
+// The same as a 64-bit byte offset (one s_mov_b64, no widening or scaling).
+__device__ __forceinline__ uint64_t opaque_zero64() {
+  uint64_t z;
+  asm volatile("s_mov_b64 %0, 0" : "=s"(z));
+  return z;
+}
+template <int K>
+__device__ __forceinline__ const double* opaque_table(const double (&c)[K]) {
+  return reinterpret_cast<const double*>(reinterpret_cast<const char*>(c) + opaque_zero64());
+}
 
 // sum_j c[j] x^j as four interleaved power sums over y = x^4,
 //   acc_m = sum_k c[4k+m] y^k,  result = acc_0 + x (acc_1 + x (acc_2 + x acc_3)).
@@ -103,6 +113,60 @@ __device__ __forceinline__ double poly(const double (&c)[K], double x) {
   return fma(x2, fma(x, r3, r2), fma(x, r1, r0));
 }
 
+// Horner steps acc = acc * x + c_k (eight or four per block) with each
+// coefficient taken straight from an SGPR pair as the addend of a VOP3
+// v_fma_f64.  (Written as plain fma the compiler picks the two-address
+// v_fmac_f64, whose addend is the destination register, and copies every
+// coefficient into VGPRs first.)
+__device__ __forceinline__ double horner8(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t"
+      "v_fma_f64 %0, %0, %1, %3\n\t"
+      "v_fma_f64 %0, %0, %1, %4\n\t"
+      "v_fma_f64 %0, %0, %1, %5\n\t"
+      "v_fma_f64 %0, %0, %1, %6\n\t"
+      "v_fma_f64 %0, %0, %1, %7\n\t"
+      "v_fma_f64 %0, %0, %1, %8\n\t"
+      "v_fma_f64 %0, %0, %1, %9"
+      : "+v"(acc)
+      : "v"(x), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]),
+        "s"(c[0]));
+  return acc;
+}
+__device__ __forceinline__ double horner4(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t"
+      "v_fma_f64 %0, %0, %1, %3\n\t"
+      "v_fma_f64 %0, %0, %1, %4\n\t"
+      "v_fma_f64 %0, %0, %1, %5"
+      : "+v"(acc)
+      : "v"(x), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+__device__ __forceinline__ double horner1(double acc, double x, double c) {
+  asm("v_fma_f64 %0, %0, %1, %2" : "+v"(acc) : "v"(x), "s"(c));
+  return acc;
+}
+
+// sum_j c[j] x^j by Horner's rule, K - 1 fma.  The coefficients are read
+// through scalar loads at the point of use (opaque_zero keeps the compiler
+// from hoisting them out of the point loop, where they would not fit the
+// SGPR file) and enter as SGPR operands.  Rounding stays at a few ulp for the
+// tables used here (|x| <= 1 with decaying coefficients, or all terms of one
+// sign).
+template <int K>
+__device__ __forceinline__ double horner(const double (&c)[K], double x) {
+  static_assert(K >= 2, "horner: at least 2 coefficients");
+  const double* cp = opaque_table(c);
+  double acc = cp[K - 1];
+  int j = K - 2;  // next coefficient
+#pragma unroll
+  for (; j >= 7; j -= 8) acc = horner8(acc, x, cp + j - 7);
+#pragma unroll
+  for (; j >= 3; j -= 4) acc = horner4(acc, x, cp + j - 3);
+#pragma unroll
+  for (; j >= 0; --j) acc = horner1(acc, x, cp[j]);
+  return acc;
+}
+
 // 1/x for x > 0 normal: hardware reciprocal plus two Newton steps.
 __device__ __forceinline__ double rcp_(double x) {
   double y = __builtin_amdgcn_rcp(x);
@@ -125,32 +189,46 @@ __device__ __forceinline__ double exp_split(double x, double* n) {
   double r = fma(k, -kLn2Hi, x);
   r = fma(k, -kLn2Lo, r);
   *n = k;
-  return poly(kExpTaylor, r);
+  return horner(kExpTaylor, r);
+}
+
+// exp(x + xl) = r * 2^n for a small correction xl (|xl| <= ulp(x)): the
+// correction joins the reduced argument.
+__device__ __forceinline__ double exp_split2(double x, double xl, double* n) {
+  double k = rint(x * kLog2e);
+  double r = fma(k, -kLn2Hi, x);
+  r = fma(k, -kLn2Lo, r) + xl;
+  *n = k;
+  return horner(kExpTaylor, r);
 }
 
 // 1/3, 1/5, ..., 1/21: the odd series of atanh after its leading term
 __constant__ double kAtanhOdd[10] = {1.0 / 3,  1.0 / 5,  1.0 / 7,  1.0 / 9,  1.0 / 11,
                                      1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21};
 
-// Natural log of a positive normal double: x = m 2^k, m in [sqrt(1/2), sqrt(2)),
-// log m = 2 atanh(s), s = (m - 1) / (m + 1), by its odd series in s up to s^21.
-__device__ __forceinline__ double log_(double x) {
+// Natural log of x 2^e for a positive normal double x and an integer-valued
+// e: x = m 2^k, m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(s),
+// s = (m - 1) / (m + 1), by its odd series in s up to s^21, plus (k + e) ln 2.
+__device__ __forceinline__ double log_(double x, double e = 0.0) {
   int k;
   double m = frexp(x, &k);
   bool lo = m < kSqrtHalf;
   m = lo ? m + m : m;
-  double kd = (double)(lo ? k - 1 : k);
+  double kd = (double)(lo ? k - 1 : k) + e;
   double f = m - 1.0;
   double s = f * rcp_(2.0 + f);
   double s2 = s * s;
-  double p = poly(kAtanhOdd, s2);
+  double p = horner(kAtanhOdd, s2);
   // log m = 2 s + 2 s s2 p = f - s f + 2 s s2 p  (f - s f = 2s exactly in real arithmetic)
   double two_s = s + s;
   double lm = fma(two_s * s2, p, two_s);
   return fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
 }
 
-// sqrt of x > 0: hardware reciprocal square root plus two Newton steps.
+// sqrt of x > 0: hardware reciprocal square root (relative error about
+// 5e-8) refined by one coupled Newton (Goldschmidt) step for sqrt(x) and
+// 1/(2 sqrt(x)), which squares the error to about 4e-15, then a final
+// correction on the exact residual x - g^2, which squares it again.
 __device__ __forceinline__ double sqrt_(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double h = 0.5 * y;
@@ -158,9 +236,6 @@ __device__ __forceinline__ double sqrt_(double x) {
   double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  // final correction on the residual
   double d = fma(-g, g, x);
   return fma(d, h, g);
 }
@@ -168,16 +243,17 @@ __device__ __forceinline__ double sqrt_(double x) {
 // Phi(ub) for FP64, branch-free: with z = |ub| / sqrt 2 and t = 2 / (2 + z),
 // erfc(z) = erfcx(z) exp(-z^2) = t Q(2t - 1) exp(-z^2); the exponent of
 // exp(-z^2) is kept apart.  z^2 is split into its rounded value and the exact
-// residual (fma) so that exp(-z^2) keeps full relative accuracy.
+// residual (fma) so that exp(-z^2) keeps full relative accuracy.  With
+// h = t / 2 = 1 / (2 + z): erfc(z) / 2 = h Q(4h - 1) exp(-z^2).
 __device__ __forceinline__ PhiVal<double> phi_eval(double ub) {
   double z = fmin(fabs(ub) * kSqrtHalf, 1.0e7);
-  double t = 2.0 * rcp_(2.0 + z);
-  double ex = t * poly(kErfcxQ, fma(2.0, t, -1.0));
+  double h = rcp_(2.0 + z);
+  double exh = h * horner(kErfcxQ, fma(4.0, h, -1.0));  // erfcx(z) / 2
   double zz = z * z;
   double res = fma(z, z, -zz);
   double n;
-  double er = exp_split(-zz, &n);
-  double mh = 0.5 * ex * er * (1.0 - res);  // erfc(z)/2 = mh 2^n
+  double er = exp_split2(-zz, -res, &n);
+  double mh = exh * er;  // erfc(z)/2 = mh 2^n
   double small = ldexp(mh, (int)fmax(n, -1100.0));
   PhiVal<double> v;
   v.neg = ub < 0.0;
@@ -185,7 +261,7 @@ __device__ __forceinline__ PhiVal<double> phi_eval(double ub) {
   v.m = v.neg ? mh : 1.0 - small;
   v.n = v.neg ? n : 0.0;
   v.ebar = v.neg ? 1.0 - small : small;
-  v.ex = ex;
+  v.ex = exh + exh;
   return v;
 }
 
@@ -215,12 +291,12 @@ __device__ __forceinline__ double draw_eval(double u, double ubar, const PhiVal<
   bool lower = v.neg || um <= 0.5;
   double a = lower ? um : fma(u, v.ebar, ubar);
   double nl = lower ? v.n : 0.0;
-  double L = fma(nl, kLn2Hi, fma(nl, kLn2Lo, log_(a)));
+  double L = log_(a, nl);
   double t2 = -2.0 * L;
   double w;
   if (t2 <= kNinvTMax * kNinvTMax) {
     double t = sqrt_(t2);
-    w = fma(poly(kNinvP, t), rcp_(poly(kNinvR, t)), -t);
+    w = fma(horner(kNinvP, t), rcp_(horner(kNinvR, t)), -t);
   } else {
     w = ninv_from_log(L);
   }
