@@ -224,13 +224,14 @@ double orc_chi2_quantile_ddof(double u, double dof) {
 /* small dense linear algebra                                                */
 /* ------------------------------------------------------------------------- */
 
-/* A = L L^T, L lower (m*m row-major).  Returns 0 on success. */
-static int cholesky(const double* A, int m, double* L) {
+/* A = L L^T, L lower (m*m row-major).  Returns 0 on success, 1 when a
+ * pivot (the squared diagonal entry of L) is not above min_pivot. */
+static int cholesky_min(const double* A, int m, double* L, double min_pivot) {
   memset(L, 0, sizeof(double) * m * m);
   for (int j = 0; j < m; ++j) {
     double s = A[j * m + j];
     for (int k = 0; k < j; ++k) s -= L[j * m + k] * L[j * m + k];
-    if (!(s > 0.0) || !isfinite(s)) return 1;
+    if (!(s > min_pivot) || !isfinite(s)) return 1;
     L[j * m + j] = sqrt(s);
     for (int i = j + 1; i < m; ++i) {
       double t = A[i * m + j];
@@ -240,6 +241,8 @@ static int cholesky(const double* A, int m, double* L) {
   }
   return 0;
 }
+
+static int cholesky(const double* A, int m, double* L) { return cholesky_min(A, m, L, 0.0); }
 
 /* solve L x = b (forward) */
 static void fwd_solve(const double* L, int m, const double* b, double* x) {
@@ -761,7 +764,10 @@ static int make_comps(int p, int q, int g, const double* pi, const double* Sigma
     for (int k = 0; k < q; ++k)
       for (int l = 0; l < q; ++l) Rm[k * q + l] = Lam[k * q + l] / (c->D[k] * c->D[l]);
     memcpy(c->R, Rm, sizeof(double) * q * q);
-    if (cholesky(Rm, q, c->C)) {
+    /* R has a unit diagonal, so its pivots are conditional variances; one at
+     * or below ORC_R_PIVOT_MIN makes R numerically singular (the GHK bounds
+     * divide by its square root) and counts as not positive definite */
+    if (cholesky_min(Rm, q, c->C, ORC_R_PIVOT_MIN)) {
       rc = ORC_ENOTPD;
       *bad = i;
       break;

@@ -27,6 +27,7 @@
 #define ORC_NU_EXACT_FD 1   /* e1 = E[log W | y] with a central difference in a */
 #define ORC_FD_REL 1e-3     /* relative step of that difference */
 #define ORC_NU_FIXED 2
+#define ORC_R_PIVOT_MIN 1e-10 /* smallest accepted pivot of chol(R) (R: unit diagonal) */
 #define ORC_NU_EXACT 3      /* e1 = E[log W | y] with the derivative of the estimate itself */
 
 #ifdef __cplusplus

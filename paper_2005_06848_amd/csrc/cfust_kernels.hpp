@@ -31,6 +31,8 @@ constexpr int kMaxP = 32;
 constexpr int kMaxQ = 12;      // E-step, log-likelihood, M-step and EM fit (FP64, FP32)
 constexpr int kMaxQFull = 8;   // exact nu step, variable ordering, batched form, surrogate
 constexpr int kMaxG = 16;
+// smallest accepted pivot of the Cholesky factor of R (unit diagonal)
+constexpr double kRPivotMin = 1e-10;
 
 
 enum Status : int {
@@ -126,10 +128,10 @@ __host__ __device__ inline int precompute_lds_bytes(int p, int q, int g) {
 // offset `off` of every live component's block (upper triangle already zero).
 // Column j takes two phases: every entry r >= j subtracts its j-term dot
 // product (the diagonal's result goes to piv[c]), then the column is divided
-// by the square root of the pivot.  A non-positive pivot marks the component
-// kENotPD.
+// by the square root of the pivot.  A pivot not above min_pivot marks the
+// component kENotPD.
 __device__ __forceinline__ void chol_columns(int m, int g, int off, double* base, int W,
-                                             int* rcs, double* piv) {
+                                             int* rcs, double* piv, double min_pivot = 0.0) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int j = 0; j < m; ++j) {
     const int h = m - j;
@@ -149,7 +151,7 @@ __device__ __forceinline__ void chol_columns(int m, int g, int off, double* base
       const int c = t / h, r = j + (t - c * h);
       if (rcs[c] != kOk) continue;
       const double s = piv[c];
-      if (!(s > 0.0)) {
+      if (!(s > min_pivot)) {
         if (r == j) rcs[c] = kENotPD;
         continue;
       }
@@ -305,7 +307,10 @@ __device__ int precompute_block(int p, int q, int g, const double* pi, const dou
     blk[cl.Rm + x] = (k == l) ? 1.0 : lv / (D[k] * D[l]);
   }
   __syncthreads();
-  chol_columns(q, g, cl.C, base, W, rcs, piv);
+  // R has a unit diagonal, so its pivots are conditional variances: one at
+  // or below kRPivotMin makes R numerically singular (the GHK bounds divide
+  // by its square root) and the component counts as not positive definite
+  chol_columns(q, g, cl.C, base, W, rcs, piv, kRPivotMin);
   if (tid < g && rcs[tid] == kOk) {
     double* blk = base + (size_t)tid * W;
     double logdet = 0.0;

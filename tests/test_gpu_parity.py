@@ -348,6 +348,16 @@ def test_setup_error_paths(dev, orc):
         par["Sigma"][1] = np.linalg.inv(np.array([[0.9, 0.3], [0.3, 0.2]])) - np.eye(2)
         par["Delta"][1] = np.eye(2)
 
+    def near_singular_r(eig):
+        # Delta = I: Lambda = M (M + I)^{-1} with Sigma = M = V diag(1, eig) V^T
+        # (V a 45-degree rotation), so R has eigenvalues near 2 and 4 eig and
+        # its second pivot is about 4 eig
+        def edit(par):
+            v = np.array([[1.0, -1.0], [1.0, 1.0]]) / np.sqrt(2.0)
+            par["Sigma"][1] = v @ np.diag([1.0, eig]) @ v.T
+            par["Delta"][1] = np.eye(2)
+        return edit
+
     def pi_off(par):
         par["pi"][0] += 1e-6
 
@@ -357,7 +367,8 @@ def test_setup_error_paths(dev, orc):
              ("mu NaN", put("mu", 1, 1, np.nan), native.ENONFINITE, 1),
              ("pi off the simplex", pi_off, native.EINVAL, None),
              ("Lambda diagonal", lam_diag, native.ENOTPD, 1),
-             ("R indefinite", r_indefinite, native.ENOTPD, 1)]
+             ("R indefinite", r_indefinite, native.ENOTPD, 1),
+             ("R pivot below 1e-10", near_singular_r(1e-12), native.ENOTPD, 1)]
     for name, edit, code, bad in cases:
         par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
         edit(par)

@@ -395,3 +395,26 @@ def test_stats_assembly_recomputed(orc, shape):
         scale = np.maximum(np.abs(ref).max(1, keepdims=True), 1e-300)
         err = np.abs(out["stats"] - ref) / scale
         assert err.max() < 1e-13, (mode, err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_r_pivot_guard(orc):
+    """R (unit diagonal) is factored with a smallest accepted pivot of 1e-10:
+    with Delta = I and Sigma = V diag(1, eig) V^T (V a 45-degree rotation),
+    Lambda = Sigma (Sigma + I)^{-1} and R's second pivot is about 4 eig, so
+    eig = 1e-12 is rejected (ENOTPD, that component) and 1e-9 accepted."""
+    c = inputs.random_case(17, 10, 2, 2, 2, 64)
+    v = np.array([[1.0, -1.0], [1.0, 1.0]]) / np.sqrt(2.0)
+    for eig, ok in ((1e-12, False), (1e-9, True)):
+        par = {k: np.array(x, copy=True) for k, x in c["params"].items()}
+        par["Sigma"][1] = v @ np.diag([1.0, eig]) @ v.T
+        par["Delta"][1] = np.eye(2)
+        lam = par["Sigma"][1] @ np.linalg.inv(par["Sigma"][1] + np.eye(2))
+        d = np.sqrt(np.diag(lam))
+        piv2 = np.linalg.cholesky(lam / np.outer(d, d))[1, 1] ** 2
+        assert (piv2 > 1e-10) == ok
+        if ok:
+            orc.estep(c["y"], par, c["u"])
+        else:
+            with pytest.raises(orc.OracleError) as e:
+                orc.estep(c["y"], par, c["u"])
+            assert e.value.code == orc.ENOTPD and e.value.bad == 1
