@@ -114,6 +114,12 @@ typedef struct cfust_opts {
                              m >= n gives the GHK E-step).  Per-pair outputs (tau, logf,
                              e1..e4) stay the network's.  The workspace then needs
                              cfust_workspace_size_opts bytes.  0 (default): no check */
+  double surrogate_switch; /* cfust_em_fit with a surrogate: the surrogate phase also
+                             ends (and the GHK phase begins) after an iteration that
+                             changed l by less than surrogate_switch * |l|, the network's
+                             relative accuracy on l: further surrogate iterations cannot
+                             be told apart from its error.  0 (default): only Aitken's
+                             rule ends the surrogate phase */
 } cfust_opts;
 
 #define CFUST_PROF_SLOTS 4

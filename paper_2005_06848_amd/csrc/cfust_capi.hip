@@ -231,6 +231,7 @@ int check_opts(const cfust_opts* o) {
   if (!(o->nu_lo > 0.0) || !(o->nu_hi >= o->nu_lo)) return CFUST_EINVAL;
   if (o->reorder != 0 && o->reorder != 1) return CFUST_EINVAL;
   if (o->surrogate_check < 0) return CFUST_EINVAL;
+  if (!(o->surrogate_switch >= 0.0)) return CFUST_EINVAL;
   return CFUST_OK;
 }
 
@@ -589,6 +590,11 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
       double linf = cfust_aitken_linf(loglik_trace[t - 2], loglik_trace[t - 1], ll);
       conv = fabs(linf - ll) < o->tol;
     }
+    // with a surrogate, an iteration that moved l by less than the network's
+    // accuracy also ends the surrogate phase
+    if (ws.surr && o->surrogate_switch > 0.0 && t > phase_start &&
+        fabs(ll - loglik_trace[t - 1]) < o->surrogate_switch * fabs(ll))
+      conv = true;
     if (conv && ws.surr && !last) {
       ws.surr = nullptr;
       surrogate_set_switch(surr, t + 1);

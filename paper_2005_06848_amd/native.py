@@ -47,6 +47,7 @@ class Opts(ctypes.Structure):
         ("adapt_epochs", ctypes.c_int),
         ("reorder", ctypes.c_int),
         ("surrogate_check", ctypes.c_int),
+        ("surrogate_switch", ctypes.c_double),
     ]
 
 
@@ -182,7 +183,7 @@ def _ptr(t):
 def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=100, tol=1e-6,
               nu_lo=1.0, nu_hi=200.0, stream=None, workspace=None, prof=None, graph=True, tile=0,
               surrogate=None, adapt_samples=0, adapt_epochs=0, reorder=False,
-              surrogate_check=0):
+              surrogate_check=0, surrogate_switch=0.0):
     o = Opts()
     _lib().cfust_default_opts(ctypes.byref(o))
     o.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
@@ -209,6 +210,7 @@ def make_opts(precision="fp64", nu_mode="osl", fix_delta_zero=False, max_iter=10
     o.adapt_epochs = int(adapt_epochs)
     o.reorder = int(bool(reorder))
     o.surrogate_check = int(surrogate_check)
+    o.surrogate_switch = float(surrogate_switch)
     return o
 
 
@@ -321,11 +323,15 @@ def cfust_em_fit(y, params0, u, max_iter=100, tol=1e-6, **opt):
     rc = _lib().cfust_em_fit(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
                              _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), trace,
                              ctypes.byref(n_iter), ctypes.byref(bad))
-    if rc:
-        raise CfustError(rc, "cfust_em_fit", bad.value)
     k = n_iter.value
     par["trace"] = [trace[t] for t in range(k + 1)]
     par["n_iter"] = k
+    if rc:
+        # the fit up to the last completed E-step: l^(0..n_iter) and the
+        # parameters the failing iteration started from
+        err = CfustError(rc, "cfust_em_fit", bad.value)
+        err.partial = par
+        raise err
     return par
 
 
