@@ -17,8 +17,11 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -28,31 +31,81 @@ if ROOT not in sys.path:
 
 WORKLOAD = "cfust-em n=20000 p=4 q=4 g=3 N=4096 fp64"
 PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_FP32_VALU_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic flop model of one (observation, component) pair (both GHK
-# integrals over N points plus the pair set-up), with fixed nominal costs per
-# special-function call: Phi (erfc) 40, Phi^-1 50, scaled accumulation 20.
-#   F_A = q^2 + q + q*40 + (q-1)*50 + 20
-#   F_B = q^2 + q + q*40 + q*50 + q(q+1) + 4q + 20
+# integrals over N points plus the pair set-up):
+#   F_A = q^2 + q + q*c_phi + (q-1)*c_phiinv + c_acc
+#   F_B = q^2 + q + q*c_phi + q*c_phiinv + q(q+1) + 4q + c_acc
 #   F_pair = N (F_A + F_B) + 2p^2 + 2pq + 40
-C_PHI, C_PHIINV, C_ACC = 40, 50, 20
+# with c_phi, c_phiinv the VALU flops per call of the implementation's normal
+# CDF and quantile, measured with rocprofv3 on the diagnostic kernels
+# (`python bench.py --cost-probe` under rocprofv3 --pmc with the
+# SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 / _F32 counters: 64 lanes per
+# instruction, an FMA counting 2), and c_acc the flops of the per-point
+# accumulation (the exponent-aligned add of the weight: no exp is taken).
+# NOMINAL are the fixed costs of the first version of the model (Phi 40,
+# Phi^-1 50, an exp-scaled accumulation 20), reported beside it.
+NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
+# measured per precision; "sources" is the digest of the kernel sources they
+# were measured on (the model falls back to NOMINAL when it differs)
+MEASURED_COSTS = None
+
+# HBM bytes per launch of the FP64 pair kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
+# plain elementwise copy of known size), with the digest of the kernel
+# sources they were taken on: `traffic` is null once the sources differ.
+PAIR_KERNEL_COUNTERS = None
 
 
-# HBM bytes per launch of the pair kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE
-# (KiB per dispatch, scaled by the same counters on a plain copy kernel:
-# fetch x 1.99978, write x 0.99999); None when the kernel has changed since
-# the counters were taken.
-TRAFFIC_BYTES_PER_LAUNCH = 43747657
-# executed FP64 flops per launch of the same kernel from the SQ_INSTS_VALU_*_F64
-# counters (64 lanes, FMA = 2)
-EXECUTED_FP64_FLOPS_PER_LAUNCH = 4.5937e11
+def kernel_sources_digest():
+    """sha256 (first 16 hex digits) of the HIP sources of the library."""
+    d = os.path.join(ROOT, "paper_2005_06848_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def flops_per_pair(p, q, N):
-    fa = q * q + q + q * C_PHI + (q - 1) * C_PHIINV + C_ACC
-    fb = q * q + q + q * C_PHI + q * C_PHIINV + q * (q + 1) + 4 * q + C_ACC
+def flops_per_pair(p, q, N, costs=None):
+    c = costs or NOMINAL_COSTS
+    fa = q * q + q + q * c["phi"] + (q - 1) * c["phiinv"] + c["acc"]
+    fb = q * q + q + q * c["phi"] + q * c["phiinv"] + q * (q + 1) + 4 * q + c["acc"]
     return N * (fa + fb) + 2 * p * p + 2 * p * q + 40
+
+
+def cost_probe(native, torch, dev):
+    """Diagnostic kernels for the per-call cost model: 2^24 evaluations each
+    of the FP64 normal CDF (inputs uniform in [-6, 6]), the FP64 quantile
+    (probabilities uniform in (0, 1)), then the same two in FP32, one
+    dispatch each in that order."""
+    n = 1 << 24
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x = (torch.rand(n, generator=g, dtype=torch.float64) * 12.0 - 6.0).to(dev)
+    pr = ((torch.arange(n, dtype=torch.float64) + 0.5) / n).to(dev)
+    for fn, arg in ((0, x), (2, pr), (7, x), (8, pr)):
+        native.cfust_eval_special(fn, arg)
+        torch.cuda.synchronize()
+    print(json.dumps({"cost_probe": "dispatches: Phi f64, Phi^-1 f64, Phi f32, Phi^-1 f32",
+                      "evaluations_per_dispatch": n}), flush=True)
+
+
+def host_description():
+    """CPU model and core counts of the host (for the CPU baseline)."""
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def precision_form(args, native, L, torch, np, inputs, dev):
@@ -97,9 +150,36 @@ def precision_form(args, native, L, torch, np, inputs, dev):
         del ws
     res["fp32_speedup_vs_fp64"] = round(res["fp64"]["ms_per_estep"] / res["fp32"]["ms_per_estep"], 3)
     res["loglik_rel_diff"] = abs(res["fp32"]["loglik"] / res["fp64"]["loglik"] - 1)
+    if not args.no_form_errors:
+        res["fp32_errors_vs_fp64_all_pairs"] = fp32_errors(native, torch, y, par, u, c)
     res["workload"] = "cfust E-step n=200000 p=6 q=6 g=4 N=8192"
     res["tolerance"] = "fp32 vs fp64 oracle: moments 1e-4, log-likelihood 1e-7 (tests/test_gpu_fp32.py)"
     return res
+
+
+def fp32_errors(native, torch, y, par, u, c):
+    """Per-quantity errors of the FP32 E-step against the FP64 GPU E-step
+    (which matches the FP64 oracle to 1e-10 in the tests) on every pair of
+    the precision workload, by the measures of tests/parity.py: tau and
+    log f absolute; e1 relative to max(|e1|, 1); e2 relative; e3, e4
+    normwise per pair; all over pairs with tau >= 1e-8; the partial sums
+    normwise per component; l relative."""
+    print("[bench] form errors: fp32 vs fp64 on all pairs", file=sys.stderr, flush=True)
+    want = ("tau", "logf", "e1", "e2", "e3", "e4")
+    r64 = native.cfust_estep(y, par, u, want=want, precision="fp64")
+    r32 = native.cfust_estep(y, par, u, want=want, precision="fp32")
+    mask = r64["tau"] >= 1e-8
+    ab = lambda k: (r32[k] - r64[k]).abs()
+    e = {"tau": ab("tau").max().item(), "logf": ab("logf").max().item(),
+         "e1": (ab("e1") / r64["e1"].abs().clamp(min=1.0))[mask].max().item(),
+         "e2": (ab("e2") / r64["e2"].abs())[mask].max().item(),
+         "e3": (ab("e3").amax(-1) / r64["e3"].abs().amax(-1))[mask].max().item(),
+         "e4": (ab("e4").amax((-1, -2)) / r64["e4"].abs().amax((-1, -2)))[mask].max().item(),
+         "stats": ((r32["stats"] - r64["stats"]).abs().amax(1)
+                   / r64["stats"].abs().amax(1)).max().item(),
+         "loglik": abs(r32["loglik"].item() / r64["loglik"].item() - 1)}
+    del r64, r32
+    return {k: float(f"{v:.3e}") for k, v in e.items()}
 
 
 def surrogate_form(args, native, torch, np, inputs, dev):
@@ -337,6 +417,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32-form speedup leg (n=200000, p=q=6, g=4, N=8192)")
     ap.add_argument("--form-reps", type=int, default=2)
+    ap.add_argument("--no-form-errors", action="store_true",
+                    help="precision leg: skip the per-quantity FP32 errors on all pairs")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form leg (64 starts, p=q=5, N=4096, FP32)")
     ap.add_argument("--batched-iters", type=int, default=50)
@@ -350,6 +432,9 @@ def parse():
                     help="skip the high-q stress leg (100 EM iterations, n=202, p=q=11, g=2, N=8192)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched leg: skip fitting the starts one by one for comparison")
+    ap.add_argument("--cost-probe", action="store_true",
+                    help="only run the diagnostic kernels of the per-call cost model (for "
+                         "rocprofv3 counters) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (traffic calibration)")
     return ap.parse_args()
@@ -367,6 +452,9 @@ def main():
 
     L = native.lib()
     dev = torch.device("cuda:0")
+    if args.cost_probe:
+        cost_probe(native, torch, dev)
+        return
     c = inputs.config(2)
     n, p, q, g, N = c["n"], c["p"], c["q"], c["g"], c["n_qmc"]
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -427,18 +515,32 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy probe {args.copy_probe_mib} MiB done", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (pair kernel): ALU-bound (FP64 VALU)
-    fpp = flops_per_pair(p, q, N)
+    # roofline of the dominant kernel (pair kernel): ALU-bound (FP64 VALU).
+    # Per-call costs as measured on the current sources, else the nominal
+    # ones; HBM traffic from counters taken on the current sources, else null.
+    digest = kernel_sources_digest()
+    prec_key = "fp64" if args.precision == "fp64" else "fp32"
+    measured = (MEASURED_COSTS is not None and MEASURED_COSTS.get("sources") == digest)
+    costs = MEASURED_COSTS[prec_key] if measured else NOMINAL_COSTS
+    fpp = flops_per_pair(p, q, N, costs)
     ach = fpp * pairs / (pair_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_VALU_TFLOPS, 4),
-            "traffic": TRAFFIC_BYTES_PER_LAUNCH if args.precision == "fp64" else None,
-            "kernel": f"pair_kernel<double,{q},true>",
-            "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp}
-    if args.precision == "fp64" and EXECUTED_FP64_FLOPS_PER_LAUNCH:
-        ex = EXECUTED_FP64_FLOPS_PER_LAUNCH / (pair_ms * 1e-3) / 1e12
-        roof["executed_tflops"] = round(ex, 3)
-        roof["executed_frac"] = round(ex / PEAK_FP64_VALU_TFLOPS, 4)
+    fpp_nom = flops_per_pair(p, q, N, NOMINAL_COSTS)
+    ach_nom = fpp_nom * pairs / (pair_ms * 1e-3) / 1e12
+    traffic = None
+    if (args.precision == "fp64" and PAIR_KERNEL_COUNTERS is not None
+            and PAIR_KERNEL_COUNTERS.get("sources") == digest):
+        traffic = PAIR_KERNEL_COUNTERS["traffic"]
+    peak = PEAK_FP64_VALU_TFLOPS if prec_key == "fp64" else PEAK_FP32_VALU_TFLOPS
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+            "traffic": traffic,
+            "kernel": f"pair_kernel<{'double' if prec_key == 'fp64' else 'float'},{q},true>",
+            "kernel_ms": round(pair_ms, 4), "flops_per_pair": fpp,
+            "cost_model": ({"source": "measured per call", **costs} if measured else
+                           {"source": "nominal (no measurement on these sources)", **costs}),
+            "nominal_model": {"flops_per_pair": fpp_nom, "achieved": round(ach_nom, 3),
+                              "frac": round(ach_nom / peak, 4)},
+            "sources_digest": digest}
 
     forms = None
     if not args.no_forms:
@@ -465,10 +567,12 @@ def main():
         tc0 = time.perf_counter()
         oracle.estep(c["y"][:m], c["init"], c["u"], want=())
         tc = time.perf_counter() - tc0
-        # all host cores: one thread per block of observations (the paper's
-        # J_l blocks); the oracle's C calls release the GIL
+        # one thread per block of observations (the paper's J_l blocks) on
+        # the host cores this process may use, at most 16: the host's CPU
+        # share for one GPU; the oracle's C calls release the GIL
         from concurrent.futures import ThreadPoolExecutor
-        nt = max(1, min(16, len(os.sched_getaffinity(0))))
+        host = host_description()
+        nt = max(1, min(16, host["affinity"]))
         per = max(1, min(args.cpu_obs_per_thread, (n - m) // nt))
         blocks = [c["y"][m + t * per:m + (t + 1) * per] for t in range(nt)]
         print(f"[bench] cpu baseline: oracle E-step on {nt} threads x {per} observations",
@@ -484,7 +588,8 @@ def main():
                          f"sums, {nt} threads of {per} observations each, {tm:.1f} s",
                "single_thread": {"value": round(m * g / tc, 3), "cores": 1,
                                  "sample": f"first {m} observations ({m * g} pairs), "
-                                           f"{tc:.1f} s"}}
+                                           f"{tc:.1f} s"},
+               "host": host}
 
     line = {
         "metric": "E-step (obs x comp) evals/sec at stated tol; FP32/surrogate vs FP64 QMC speedup",

@@ -23,7 +23,7 @@ def test_flop_model_per_pair():
     integral A draws q - 1 coordinates, integral B all q and adds the moment
     sums q(q+1) + 4q.  At p = q = 4, N = 4096 that is 3,219,560 flops."""
     import bench
-    assert (bench.C_PHI, bench.C_PHIINV, bench.C_ACC) == (40, 50, 20)
+    assert bench.NOMINAL_COSTS == {"phi": 40, "phiinv": 50, "acc": 20}
     assert bench.flops_per_pair(4, 4, 4096) == 3219560
     # by hand for p = q = 1, N = 1: A = 1+1+40+0+20, B = 1+1+40+50+2+4+20
     assert bench.flops_per_pair(1, 1, 1) == 62 + 118 + 2 + 2 + 40
@@ -33,3 +33,17 @@ def test_flop_model_per_pair():
     fa = q * q + q + 40 * q + 50 * (q - 1) + 20
     fb = q * q + q + 40 * q + 50 * q + q * (q + 1) + 4 * q + 20
     assert d == fa + fb
+    # measured per-call costs enter the same formula
+    c = {"phi": 30, "phiinv": 70, "acc": 3}
+    assert bench.flops_per_pair(1, 1, 1, c) == (2 + 30 + 3) + (2 + 30 + 70 + 2 + 4 + 3) + 44
+
+
+def test_source_digest_gates_the_counter_fields():
+    """roofline.traffic and the measured cost model apply only to the kernel
+    sources they were taken on: the digest covers every HIP source."""
+    import bench
+    d = bench.kernel_sources_digest()
+    assert len(d) == 16 and d == bench.kernel_sources_digest()
+    for name in ("PAIR_KERNEL_COUNTERS", "MEASURED_COSTS"):
+        v = getattr(bench, name)
+        assert v is None or set(v) >= {"sources"}
