@@ -165,6 +165,26 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
                 const double* mu, const double* Sigma, const double* Delta, const double* nu,
                 const double* u, int n_qmc, const cfust_opts* opts, cfust_estep_out* out);
 
+/* The E-step of cfust_estep for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs and results as cfust_estep (the same
+ * kernels in the same order, so the outputs are identical), but the
+ * workspace is the library's static device scratch array of
+ * CFUST_NOALLOC_SCRATCH_BYTES bytes: one copy per GPU, allocated when the
+ * library's code is loaded on that GPU and held until the process ends.
+ * The call allocates nothing.  Returns CFUST_ENOMEM when the problem needs
+ * more workspace than that (cfust_workspace_size_opts gives the bytes), and
+ * CFUST_EINVAL if opts sets a surrogate (its buffers grow on demand),
+ * prof_ms (timing events) or a workspace of its own.  Every call on one GPU
+ * uses that GPU's one scratch array: calls that overlap on one GPU (several
+ * host threads, or streams that run concurrently) race and must be
+ * serialised by the caller. */
+#define CFUST_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int cfust_estep_noalloc(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                        const double* mu, const double* Sigma, const double* Delta,
+                        const double* nu, const double* u, int n_qmc, const cfust_opts* opts,
+                        cfust_estep_out* out);
+
 /* One M-step from the partial sums (section 3.3, Algorithm 3): conditional
  * maximisation in the order mu (with the old Delta), Delta, Sigma, then nu
  * (root of 1 + log(nu/2) - psi(nu/2) + s8/s1 = 0 in [nu_lo, nu_hi], clipped)

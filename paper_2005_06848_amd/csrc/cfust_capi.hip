@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/cfust.h"
 #include "cfust_host.hpp"
@@ -406,6 +407,38 @@ int check_q_forms(const cfust_opts* o, int q) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free E-step (cfust_estep_noalloc): one
+// copy per GPU, allocated when this code object is loaded on the GPU.  Host
+// code must never pass `scratch` itself to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): scratch_ptr() gives the device
+// address of the current GPU's copy.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = CFUST_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// device address of the current GPU's scratch array, looked up once per GPU
+int scratch_ptr(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return CFUST_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CFUST_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CFUST_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void cfust_default_opts(cfust_opts* o) {
@@ -479,6 +512,31 @@ int cfust_estep(const double* y, int64_t n, int p, int q, int g, const double* p
   int st = fetch_status(ws, pl, &out->bad_component);
   release(&ws);
   return rc ? rc : st;
+}
+
+int cfust_estep_noalloc(const double* y, int64_t n, int p, int q, int g, const double* pi,
+                        const double* mu, const double* Sigma, const double* Delta,
+                        const double* nu, const double* u, int n_qmc, const cfust_opts* o,
+                        cfust_estep_out* out) {
+  if (!out) return CFUST_EINVAL;
+  out->bad_component = -1;
+  int rc = check_dims(n, p, q, g, n_qmc);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (o && (o->surrogate || o->prof_ms || o->workspace)) return CFUST_EINVAL;
+  if ((rc = check_q_forms(o, q))) return rc;
+  const Plan pl = make_plan(n, p, q, g, n_qmc, o ? o->precision : CFUST_FP64);
+  if (pl.total > kScratchBytes) return CFUST_ENOMEM;
+  void* base = nullptr;
+  if ((rc = scratch_ptr(&base))) return rc;
+  cfust_opts oo;
+  if (o)
+    oo = *o;
+  else
+    cfust_default_opts(&oo);
+  oo.workspace = base;
+  oo.workspace_bytes = kScratchBytes;
+  return cfust_estep(y, n, p, q, g, pi, mu, Sigma, Delta, nu, u, n_qmc, &oo, out);
 }
 
 int cfust_loglik(const double* y, int64_t n, int p, int q, int g, const double* pi,

@@ -88,6 +88,8 @@ def _lib():
         L.cfust_estep.argtypes = [P, i64, i, i, i, P, P, P, P, P, P, i, ctypes.POINTER(Opts),
                                   ctypes.POINTER(EstepOut)]
         L.cfust_estep.restype = i
+        L.cfust_estep_noalloc.argtypes = L.cfust_estep.argtypes
+        L.cfust_estep_noalloc.restype = i
         L.cfust_mstep.argtypes = [P, i64, i, i, i, P, P, P, ctypes.POINTER(Opts), P, P, P, P, P,
                                   ctypes.POINTER(i)]
         L.cfust_mstep.restype = i
@@ -252,6 +254,16 @@ def _params(params):
 
 def cfust_estep(y, params, u, want=("tau", "logf", "e1", "e2", "e3", "e4"), **opt):
     """One E-step (section 3.2, Algorithm 2) on the GPU."""
+    return _estep("cfust_estep", y, params, u, want, opt)
+
+
+def cfust_estep_noalloc(y, params, u, want=("tau", "logf", "e1", "e2", "e3", "e4"), **opt):
+    """The same E-step in the library's static device scratch (no allocation
+    inside the call; the output tensors are allocated here, by the caller)."""
+    return _estep("cfust_estep_noalloc", y, params, u, want, opt)
+
+
+def _estep(fn, y, params, u, want, opt):
     y = _dev(y, "y")
     u = _dev(u, "u")
     (pi, mu, Sigma, Delta, nu), g, p, q = _params(params)
@@ -265,10 +277,10 @@ def cfust_estep(y, params, u, want=("tau", "logf", "e1", "e2", "e3", "e4"), **op
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     eo = EstepOut(*[_ptr(out[k]) for k in shapes], _ptr(stats), _ptr(ll), -1)
     o = make_opts(**opt)
-    rc = _lib().cfust_estep(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
-                            _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), ctypes.byref(eo))
+    rc = getattr(_lib(), fn)(_ptr(y), n, p, q, g, _ptr(pi), _ptr(mu), _ptr(Sigma), _ptr(Delta),
+                             _ptr(nu), _ptr(u), u.shape[0], ctypes.byref(o), ctypes.byref(eo))
     if rc:
-        raise CfustError(rc, "cfust_estep", eo.bad_component)
+        raise CfustError(rc, fn, eo.bad_component)
     res = {k: v for k, v in out.items() if v is not None}
     res["stats"] = stats
     res["loglik"] = ll
