@@ -202,27 +202,30 @@ __device__ __forceinline__ double exp_split2(double x, double xl, double* n) {
   return horner(kExpTaylor, r);
 }
 
-// 1/3, 1/5, ..., 1/21: the odd series of atanh after its leading term
-__constant__ double kAtanhOdd[10] = {1.0 / 3,  1.0 / 5,  1.0 / 7,  1.0 / 9,  1.0 / 11,
-                                     1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21};
-
 // Natural log of x 2^e for a positive normal double x and an integer-valued
-// e: x = m 2^k, m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(s),
-// s = (m - 1) / (m + 1), by its odd series in s up to s^21, plus (k + e) ln 2.
+// e: x = m 2^k with m in [1/2, 1).  F_j is m with all but the top 7 bits of
+// its fraction cleared (F_j = (1 + j/128) / 2), so d = m - F_j is exact and
+// r = d / F_j (with 1/F_j from kLogTab) is below 1/128 in size; then
+// log m = log F_j + log1p(r), log1p(r) = r + r^2 P(r) by its series to r^8
+// (truncation below 5e-20), and log(x 2^e) = (k + e) ln 2 + log m.  The
+// table's log F_j carries a rounding of at most 5.5e-17, so the result is
+// within about 1e-16 absolute and 2e-16 relative: near x = 1 (not a case of
+// the draws, whose probabilities are at most 1/2) the absolute bound rules.
+__constant__ double kLog1pTail[7] = {-1.0 / 2, 1.0 / 3, -1.0 / 4, 1.0 / 5, -1.0 / 6, 1.0 / 7,
+                                     -1.0 / 8};
 __device__ __forceinline__ double log_(double x, double e = 0.0) {
   int k;
-  double m = frexp(x, &k);
-  bool lo = m < kSqrtHalf;
-  m = lo ? m + m : m;
-  double kd = (double)(lo ? k - 1 : k) + e;
-  double f = m - 1.0;
-  double s = f * rcp_(2.0 + f);
-  double s2 = s * s;
-  double p = horner(kAtanhOdd, s2);
-  // log m = 2 s + 2 s s2 p = f - s f + 2 s s2 p  (f - s f = 2s exactly in real arithmetic)
-  double two_s = s + s;
-  double lm = fma(two_s * s2, p, two_s);
-  return fma(kd, kLn2Hi, fma(kd, kLn2Lo, lm));
+  const double m = frexp(x, &k);
+  const unsigned hi = (unsigned)__double2hiint(m);
+  const int j = (int)((hi >> 13) & 127u);
+  const double F = __hiloint2double((int)(hi & ~0x1FFFu), 0);
+  const double d = m - F;
+  const LogTab t = kLogTab[j];
+  const double r = d * t.inv;
+  const double r2 = r * r;
+  const double lp = fma(r2, horner(kLog1pTail, r), r);
+  const double kd = (double)k + e;
+  return fma(kd, kLn2Hi, fma(kd, kLn2Lo, t.lg + lp));
 }
 
 // sqrt of x > 0: hardware reciprocal square root (relative error about
