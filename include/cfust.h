@@ -189,6 +189,10 @@ int cfust_estep_noalloc(const double* y, int64_t n, int p, int q, int g, const d
  * maximisation in the order mu (with the old Delta), Delta, Sigma, then nu
  * (root of 1 + log(nu/2) - psi(nu/2) + s8/s1 = 0 in [nu_lo, nu_hi], clipped)
  * and pi = s1 / n.  Outputs may alias the old parameters.
+ * CFUST_ENOTPD (bad_component set) when a pivot of the new Sigma's Cholesky
+ * factor is at or below 2^-26 (the square root of the FP64 epsilon) times
+ * its diagonal entry: the component has degenerated.  CFUST_ENONFINITE when
+ * a component's partial sums are not finite.
  * bad_component: host pointer or NULL. */
 int cfust_mstep(const double* stats, int64_t n, int p, int q, int g, const double* mu_old,
                 const double* Delta_old, const double* nu_old, const cfust_opts* opts,

@@ -244,6 +244,25 @@ static int cholesky_min(const double* A, int m, double* L, double min_pivot) {
 
 static int cholesky(const double* A, int m, double* L) { return cholesky_min(A, m, L, 0.0); }
 
+/* A = L L^T with every pivot above rel times its diagonal entry A_jj (the
+ * share of coordinate j's variance left after the earlier coordinates);
+ * returns 1 otherwise. */
+static int cholesky_rel(const double* A, int m, double* L, double rel) {
+  memset(L, 0, sizeof(double) * m * m);
+  for (int j = 0; j < m; ++j) {
+    double s = A[j * m + j];
+    for (int k = 0; k < j; ++k) s -= L[j * m + k] * L[j * m + k];
+    if (!(s > rel * A[j * m + j]) || !isfinite(s)) return 1;
+    L[j * m + j] = sqrt(s);
+    for (int i = j + 1; i < m; ++i) {
+      double t = A[i * m + j];
+      for (int k = 0; k < j; ++k) t -= L[i * m + k] * L[j * m + k];
+      L[i * m + j] = t / L[j * m + j];
+    }
+  }
+  return 0;
+}
+
 /* solve L x = b (forward) */
 static void fwd_solve(const double* L, int m, const double* b, double* x) {
   for (int i = 0; i < m; ++i) {
@@ -951,17 +970,22 @@ int orc_estep(const double* y, int64_t n, int p, int q, int g, const double* pi,
       const double* r = R + i * p;
       const double* e3v = E3 + i * q;
       const double* e4v = E4 + i * q * q;
-      st[o.s1] += t;
-      st[o.s2] += t * E2[i];
-      for (int a = 0; a < p; ++a) st[o.s3 + a] += t * E2[i] * r[a];
-      for (int k = 0; k < q; ++k) st[o.s4 + k] += t * e3v[k];
-      for (int k = 0; k < q; ++k)
-        for (int l = k; l < q; ++l) st[o.s5 + tri_idx(k, l, q)] += t * e4v[k * q + l];
-      for (int a = 0; a < p; ++a)
-        for (int k = 0; k < q; ++k) st[o.s6 + a * q + k] += t * r[a] * e3v[k];
-      for (int a = 0; a < p; ++a)
-        for (int b = a; b < p; ++b) st[o.s7 + tri_idx(a, b, p)] += t * E2[i] * r[a] * r[b];
-      st[o.s8] += t * E1m2[i];
+      /* a pair whose responsibility underflows to zero adds nothing (the
+       * limit of tau e as tau -> 0): its GHK ratio T_B/T_A may be beyond
+       * the double range, and 0 * inf would poison the sums */
+      if (t > 0.0) {
+        st[o.s1] += t;
+        st[o.s2] += t * E2[i];
+        for (int a = 0; a < p; ++a) st[o.s3 + a] += t * E2[i] * r[a];
+        for (int k = 0; k < q; ++k) st[o.s4 + k] += t * e3v[k];
+        for (int k = 0; k < q; ++k)
+          for (int l = k; l < q; ++l) st[o.s5 + tri_idx(k, l, q)] += t * e4v[k * q + l];
+        for (int a = 0; a < p; ++a)
+          for (int k = 0; k < q; ++k) st[o.s6 + a * q + k] += t * r[a] * e3v[k];
+        for (int a = 0; a < p; ++a)
+          for (int b = a; b < p; ++b) st[o.s7 + tri_idx(a, b, p)] += t * E2[i] * r[a] * r[b];
+        st[o.s8] += t * E1m2[i];
+      }
       size_t ji = (size_t)j * g + i;
       if (tau) tau[ji] = t;
       if (logf) logf[ji] = lf[i];
@@ -1145,7 +1169,11 @@ int orc_mstep(const double* stats, int64_t n, int p, int q, int g, const double*
         Sg[a * p + b] = t;
         Sg[b * p + a] = t;
       }
-    if (cholesky(Sg, p, Ls)) {
+    /* a pivot of Sigma' at or below ORC_SIGMA_PIVOT_REL (sqrt(eps)) of its
+     * diagonal entry: one coordinate is a linear function of the others
+     * to about half the digits, Sigma' is numerically singular and the
+     * component has degenerated (the likelihood is unbounded there) */
+    if (cholesky_rel(Sg, p, Ls, ORC_SIGMA_PIVOT_REL)) {
       if (bad_component) *bad_component = i;
       return ORC_ENOTPD;
     }

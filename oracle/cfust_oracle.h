@@ -28,6 +28,8 @@
 #define ORC_FD_REL 1e-3     /* relative step of that difference */
 #define ORC_NU_FIXED 2
 #define ORC_R_PIVOT_MIN 1e-10 /* smallest accepted pivot of chol(R) (R: unit diagonal) */
+#define ORC_SIGMA_PIVOT_REL 0x1p-26 /* smallest accepted pivot of chol(Sigma'), relative to
+                                       its diagonal entry: sqrt of the FP64 epsilon */
 #define ORC_NU_EXACT 3      /* e1 = E[log W | y] with the derivative of the estimate itself */
 
 #ifdef __cplusplus

@@ -33,6 +33,10 @@ constexpr int kMaxQFull = 8;   // exact nu step, variable ordering, batched form
 constexpr int kMaxG = 16;
 // smallest accepted pivot of the Cholesky factor of R (unit diagonal)
 constexpr double kRPivotMin = 1e-10;
+// smallest accepted pivot of the Cholesky factor of the new Sigma, relative
+// to its diagonal entry: the square root of the FP64 epsilon (below it one
+// coordinate is a linear function of the others to half the digits)
+constexpr double kSigmaPivotRel = 0x1p-26;
 
 
 enum Status : int {
@@ -1307,6 +1311,10 @@ __device__ __forceinline__ void stats_body(
         const double* rec = recs + (x * g + i) * W;
         const double* yx = ys + x * p;
         double val;
+        // a pair whose responsibility underflows to zero adds nothing (the
+        // limit of tau e as tau -> 0): its GHK ratio T_B/T_A may be beyond
+        // the double range, and 0 * inf would poison the sums
+        if (ta == 0.0) continue;
         switch (kind[e]) {
           case 1: val = ta; break;
           case 2: val = ta * rec[1]; break;
@@ -1378,11 +1386,14 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double* __restrict__ p
 // all components (mstep_body).
 // CM order: mu (old Delta), Delta (new mu), Sigma, then nu and pi.
 // ---------------------------------------------------------------------------
-__device__ bool chol_small(double* A, int m) {
+// In-place Cholesky factor of the m x m matrix A (lower triangle); false
+// when a pivot is not above rel times its diagonal entry.
+__device__ bool chol_small(double* A, int m, double rel = 0.0) {
   for (int j = 0; j < m; ++j) {
     double s = A[j * m + j];
+    const double ajj = s;
     for (int k = 0; k < j; ++k) s -= A[j * m + k] * A[j * m + k];
-    if (!(s > 0.0) || !isfinite(s)) return false;
+    if (!(s > rel * ajj) || !isfinite(s)) return false;
     double l = sqrt(s);
     A[j * m + j] = l;
     for (int r = j + 1; r < m; ++r) {
@@ -1603,7 +1614,10 @@ __device__ __forceinline__ void mstep_body(const double* __restrict__ stats, int
   if (tid < g) {
     double vnew = nu_old[tid];
     if (okc[tid]) {
-      if (!chol_small(wk(tid).Lc, p)) {
+      // a pivot of Sigma' at or below kSigmaPivotRel of its diagonal entry:
+      // Sigma' is numerically singular, the component has degenerated (the
+      // likelihood is unbounded there)
+      if (!chol_small(wk(tid).Lc, p, kSigmaPivotRel)) {
         okc[tid] = 0;
         set_status(status, kENotPD, tid);
         fail = 1;

@@ -114,16 +114,31 @@ def test_workload6_full_size_vs_oracle(dev):
     assert max(err.values()) <= TOL, err
 
 
-def test_workload6_whole_fit_increases_loglik(dev):
+def test_workload6_exact_fit_ends_cleanly(dev):
+    """The whole fit of the stress workload (n = 202, p = q = 11, g = 2,
+    N = 8192) with the exact nu step, from the k-means start, for up to 600
+    iterations.  With about 200 free parameters per component and 202
+    observations one component degenerates (its Sigma turns singular, where
+    the likelihood is unbounded); the fit must end either by Aitken's rule or
+    with ENOTPD naming that component (the new Sigma's pivot guard), never
+    with a non-finite value.  l rises monotonically (up to 1e-9 relative)
+    over the first 60 iterations."""
     from paper_2005_06848_amd import inputs, native
     c = inputs.config(6)
-    print("[gpu] high-q whole fit workload 6 (max 200 iterations)", flush=True)
-    fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(c["u"], dev), max_iter=200,
-                              tol=1e-6)
+    print("[gpu] high-q whole fit workload 6, exact nu (max 600 iterations)", flush=True)
+    try:
+        fit = native.cfust_em_fit(T(c["y"], dev), P(c["init"], dev), T(c["u"], dev),
+                                  max_iter=600, tol=1e-6, nu_mode="exact")
+        end = "converged" if fit["n_iter"] < 600 else "iteration cap"
+    except native.CfustError as e:
+        assert e.code == native.ENOTPD and e.bad in (0, 1), str(e)
+        fit, end = e.partial, f"ENOTPD, component {e.bad}"
     tr = np.array(fit["trace"])
-    print(f"  iterations {fit['n_iter']}, l {tr[0]:.4f} -> {tr[-1]:.4f}")
-    assert tr[-1] > tr[0]
+    print(f"  {end} after {fit['n_iter']} iterations; l {tr[0]:.4f} -> max {tr.max():.4f} "
+          f"at {tr.argmax()} -> {tr[-1]:.4f}")
     assert np.all(np.isfinite(tr))
+    d = np.diff(tr[:61])
+    assert np.all(d > -1e-9 * np.abs(tr[1:61])), d.min()
 
 
 def test_high_q_forms_rejected(dev):

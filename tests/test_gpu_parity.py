@@ -445,3 +445,47 @@ def test_split_waves_parity(dev, orc, shape):
     ll_ref = orc.loglik(y, par, u)
     ll = float(native.cfust_loglik(T(y, dev), gpu_params(par, dev), T(u, dev)).cpu()[0])
     assert abs(ll - ll_ref) <= TOL * abs(ll_ref)
+
+
+def test_degenerate_component_guards(dev, orc):
+    """Two guards that end a fit on a degenerated component cleanly, as in
+    the oracle: (a) a pair whose responsibility underflows to zero is left
+    out of the partial sums (its T_B/T_A may overflow), so the E-step stays
+    finite and equal to the oracle's; (b) a new Sigma whose Cholesky pivot
+    falls to 2^-26 of its diagonal entry gives ENOTPD naming the component
+    (relative pivots 0 and about 3e-9), while one above it (about 2.5e-8)
+    is accepted."""
+    from paper_2005_06848_amd import inputs, native
+    import parity
+    c = inputs.random_case(31, 30, 2, 2, 2, 128)
+    par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    y = np.array(c["y"], copy=True)
+    y[0] = par["mu"][0] + 0.1
+    par["mu"][1] = par["mu"][0] + 1e120
+    ref = orc.estep(y, par, c["u"])
+    assert ref["tau"][0, 1] == 0.0
+    got = run_pair(dev, y, par, c["u"])
+    assert np.all(np.isfinite(got["stats"]))
+    check(parity.estep_errors(got, ref, 2, 2))
+
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(50)
+    noise = rng.standard_normal(50)
+    c = inputs.random_case(23, 4, 2, 1, 1, 64)
+    par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    par["Delta"][:] = 0.0
+    for off, ok in ((0.0, False), (1e-4, False), (3e-4, True)):
+        yy = np.stack([x, 2 * x + off * noise], axis=1)
+        e = orc.estep(yy, par, c["u"])
+        print(f"[gpu] Sigma pivot guard, offset {off}", flush=True)
+        if ok:
+            r = orc.mstep(e["stats"], 50, par, fix_delta_zero=True)
+            gg = native.cfust_mstep(T(e["stats"], dev), 50, gpu_params(par, dev),
+                                    fix_delta_zero=True)
+            err = parity.params_rel_err({k: v.cpu().numpy() for k, v in gg.items()}, r)
+            assert max(err.values()) < 1e-10, err
+        else:
+            with pytest.raises(native.CfustError) as er:
+                native.cfust_mstep(T(e["stats"], dev), 50, gpu_params(par, dev),
+                                   fix_delta_zero=True)
+            assert er.value.code == native.ENOTPD and er.value.bad == 0

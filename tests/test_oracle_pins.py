@@ -418,3 +418,48 @@ def test_r_pivot_guard(orc):
             with pytest.raises(orc.OracleError) as e:
                 orc.estep(c["y"], par, c["u"])
             assert e.value.code == orc.ENOTPD and e.value.bad == 1
+
+
+def test_sigma_pivot_guard(orc):
+    """The new Sigma must keep every Cholesky pivot above 2^-26 (the square
+    root of the FP64 epsilon) times its diagonal entry; below it the
+    component has degenerated.  One component with Delta held at zero (the
+    t-mixture case, Sigma' the weighted scatter of the data about mu'):
+    observations on the line y2 = 2 y1 make Sigma' singular to rounding;
+    moved off the line by 1e-4 times a fixed noise vector the relative pivot
+    is near 3e-9 (still rejected: the guard is not a rounding-level test),
+    and by 3e-4 near 2.5e-8, which is accepted."""
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(50)
+    noise = rng.standard_normal(50)
+    c = inputs.random_case(23, 4, 2, 1, 1, 64)
+    par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    par["Delta"][:] = 0.0
+    for off, ok in ((0.0, False), (1e-4, False), (3e-4, True)):
+        y = np.stack([x, 2 * x + off * noise], axis=1)
+        e = orc.estep(y, par, c["u"])
+        if ok:
+            new = orc.mstep(e["stats"], 50, par, fix_delta_zero=True)
+            S = new["Sigma"][0]
+            assert 2.0 ** -26 < np.linalg.cholesky(S)[1, 1] ** 2 / S[1, 1] < 1e-7
+        else:
+            with pytest.raises(orc.OracleError) as er:
+                orc.mstep(e["stats"], 50, par, fix_delta_zero=True)
+            assert er.value.code == orc.ENOTPD and er.value.bad == 0
+
+
+def test_zero_responsibility_pairs_add_nothing(orc):
+    """A pair whose responsibility underflows to exactly zero is left out of
+    the partial sums: with one observation far from component 1 (its tau
+    there is 0.0), the sums equal those of the other observations plus that
+    observation's component-0 terms alone."""
+    c = inputs.random_case(31, 30, 2, 2, 2, 128)
+    par = {k: np.array(v, copy=True) for k, v in c["params"].items()}
+    y = np.array(c["y"], copy=True)
+    y[0] = par["mu"][0] + 0.1
+    par["mu"][1] = par["mu"][0] + 1e120  # t tails: log f falls like log d
+    out = orc.estep(y, par, c["u"], want=("tau", "e1", "e2", "e3", "e4"))
+    assert out["tau"][0, 1] == 0.0
+    ref = _stats_from_pairs(y, par["mu"], out["tau"], out["e1"], out["e2"], out["e3"], out["e4"])
+    assert np.all(np.isfinite(out["stats"]))
+    np.testing.assert_allclose(out["stats"], ref, rtol=1e-13, atol=1e-300)
