@@ -49,14 +49,21 @@ HBM_PEAK_GBS = 8000.0
 # Phi^-1 50, an exp-scaled accumulation 20), reported beside it.
 NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # measured per precision; "sources" is the digest of the kernel sources they
-# were measured on (the model falls back to NOMINAL when it differs)
-MEASURED_COSTS = None
+# were measured on (the model falls back to NOMINAL when it differs).
+# FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
+# Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
+# step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
+MEASURED_COSTS = {"sources": "33aa241a358c70c6",
+                  "fp64": {"phi": 99, "phiinv": 91, "acc": 5},
+                  "fp32": {"phi": 41, "phiinv": 30, "acc": 2}}
 
 # HBM bytes per launch of the FP64 pair kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
 # plain elementwise copy of known size), with the digest of the kernel
 # sources they were taken on: `traffic` is null once the sources differ.
-PAIR_KERNEL_COUNTERS = None
+# FETCH_SIZE 7480.42 KiB x 1.99976 + WRITE_SIZE 28299.1 KiB x 0.99999 (the
+# copy probe, 262144 KiB each way, read 131088 and 262146).
+PAIR_KERNEL_COUNTERS = {"sources": "33aa241a358c70c6", "traffic": 44296088}
 
 
 def kernel_sources_digest():
@@ -79,18 +86,26 @@ def flops_per_pair(p, q, N, costs=None):
 
 
 def cost_probe(native, torch, dev):
-    """Diagnostic kernels for the per-call cost model: 2^24 evaluations each
-    of the FP64 normal CDF (inputs uniform in [-6, 6]), the FP64 quantile
-    (probabilities uniform in (0, 1)), then the same two in FP32, one
-    dispatch each in that order."""
+    """Diagnostic kernels for the per-call cost model, 2^24 evaluations each,
+    one dispatch each in this order: the normal CDF (inputs uniform in
+    [-6, 6]) and quantile (probabilities uniform in (0, 1)) in FP64, the
+    same two in FP32, then the GHK coordinate step Phi^-1(u Phi(x)) in FP64
+    and FP32, and the accumulation of a point's weight in FP64 and FP32.
+    c_phi is the CDF's count; c_phiinv is the coordinate step's count less
+    the CDF's and less the probe's own 1 - u; c_acc is the accumulation's
+    count."""
     n = 1 << 24
     g = torch.Generator(device="cpu").manual_seed(5)
     x = (torch.rand(n, generator=g, dtype=torch.float64) * 12.0 - 6.0).to(dev)
     pr = ((torch.arange(n, dtype=torch.float64) + 0.5) / n).to(dev)
-    for fn, arg in ((0, x), (2, pr), (7, x), (8, pr)):
-        native.cfust_eval_special(fn, arg)
+    m = (0.5 + 0.5 * torch.rand(n, generator=g, dtype=torch.float64)).to(dev)
+    ex = torch.randint(-20, 21, (n,), generator=g).to(torch.float64).to(dev)
+    for fn, arg, arg2 in ((0, x, None), (2, pr, None), (7, x, None), (8, pr, None),
+                          (14, x, pr), (15, x, pr), (16, m, ex), (17, m, ex)):
+        native.cfust_eval_special(fn, arg, arg2)
         torch.cuda.synchronize()
-    print(json.dumps({"cost_probe": "dispatches: Phi f64, Phi^-1 f64, Phi f32, Phi^-1 f32",
+    print(json.dumps({"cost_probe": "dispatches: Phi f64, Phi^-1 f64, Phi f32, Phi^-1 f32, "
+                                    "step f64, step f32, acc f64, acc f32",
                       "evaluations_per_dispatch": n}), flush=True)
 
 
@@ -295,14 +310,27 @@ def batched_form(args, native, torch, np, inputs, dev):
            "launch_shape": native.cfust_batched_config()}
     if not args.no_sequential:
         print("[bench] batched: same starts one by one", file=sys.stderr, flush=True)
+        ys = [T(c["y"]) for c in probs]
+        ps = [{kk: T(v) for kk, v in c["init"].items()} for c in probs]
+        prof = native.prof_buffer()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k, c in enumerate(probs):
-            native.cfust_em_fit(T(c["y"]), {kk: T(v) for kk, v in c["init"].items()}, ut,
-                                max_iter=it, tol=1e-6, precision="fp32")
+        seq_iters = 0
+        for k in range(len(probs)):
+            f = native.cfust_em_fit(ys[k], ps[k], ut, max_iter=it, tol=1e-6, precision="fp32",
+                                    prof=prof)
+            seq_iters += int(f["n_iter"]) + 1
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
+        kern = sum(prof[s] for s in range(native.PROF_SLOTS)) * 1e-3
         res["sequential_seconds"] = round(ts, 3)
         res["speedup_vs_sequential"] = round(ts / tb, 3)
+        # what batching can save on these problems: the one-by-one fits'
+        # time outside their kernels (host round trip and launches per
+        # iteration), each problem filling the GPU on its own
+        res["sequential_kernel_seconds"] = round(kern, 3)
+        res["sequential_host_us_per_iteration"] = round(1e6 * (ts - kern) / seq_iters, 1)
+        res["sequential_kernel_ms_per_iteration"] = round(1e3 * kern / seq_iters, 3)
     res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
     return res
 
@@ -373,14 +401,16 @@ def em_fit_form(args, native, torch, np, inputs, dev):
 
 
 def high_q_form(args, native, torch, np, inputs, dev):
-    """High-q stress case (workload 6: n=202, p=q=11, g=2, N=8192): 100 EM
-    iterations from the k-means start, FP64 and FP32 integrands.  From this
-    start the fit does not converge: l peaks near iteration 75 while the
-    smallest eigenvalue of Sigma keeps falling (about 1e-11 by iteration
-    285, where e2 overflows), so a fixed iteration count is timed.  The
-    paper's only timings are whole fits of R and MATLAB code on a data set
-    of this shape (4-core PCs, iteration count and tolerance not stated):
-    context, not a like-for-like baseline."""
+    """High-q stress case (workload 6: n=202, p=q=11, g=2, N=8192) from the
+    k-means start.  (1) 100 EM iterations, FP64 and FP32 integrands, timed
+    per iteration.  (2) The whole fit with the exact nu step, FP64, Aitken
+    tolerance 1e-6, up to 600 iterations, and how it ends: with about 200
+    free parameters per component and 202 observations a component
+    degenerates (its Sigma turns singular, where the likelihood is
+    unbounded), which the new Sigma's pivot guard reports as ENOTPD naming
+    that component.  The paper's only timings are whole fits of R and
+    MATLAB code on a data set of this shape (4-core PCs, iteration count
+    and tolerance not stated): context, not a like-for-like baseline."""
     c = inputs.config(6)
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     y, par, u = T(c["y"]), {k: T(v) for k, v in c["init"].items()}, T(c["u"])
@@ -398,6 +428,23 @@ def high_q_form(args, native, torch, np, inputs, dev):
         res[prec] = {"seconds": round(ts, 3), "ms_per_iteration": round(1e3 * ts / iters, 3),
                      "loglik_start": float(tr[0]), "loglik_max": float(tr.max()),
                      "iteration_of_max": int(tr.argmax()), "loglik_end": float(tr[-1])}
+    print("[bench] high-q: whole fit, exact nu step, FP64", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        fit = native.cfust_em_fit(y, par, u, max_iter=600, tol=1e-6, nu_mode="exact")
+        end = "converged (Aitken, 1e-6)" if fit["n_iter"] < 600 else "iteration cap (600)"
+    except native.CfustError as e:
+        if e.code != native.ENOTPD or e.partial is None:
+            raise
+        fit, end = e.partial, f"ENOTPD: component {e.bad} degenerated (new Sigma singular)"
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    tr = np.asarray(fit["trace"])
+    res["whole_fit_exact_fp64"] = {
+        "end": end, "iterations": int(fit["n_iter"]), "seconds": round(ts, 3),
+        "loglik_start": float(tr[0]), "loglik_max": float(tr.max()),
+        "iteration_of_max": int(tr.argmax()), "loglik_end": float(tr[-1])}
     res["paper_whole_fit_seconds_context"] = {
         "R_1_thread": 2310.83, "MATLAB_1_thread": 2635.69, "R_best": 532.29, "MATLAB_best": 516.34}
     return res

@@ -402,7 +402,12 @@ double cfust_aitken_linf(double l0, double l1, double l2);
  * 3 Phi^-1 from log p, 4 chi-square quantile at (x, x2 = dof), 5 digamma,
  * 6 trigamma, 7 Phi in float32, 8 Phi^-1 in float32, 9 log, 10 sqrt,
  * 11 d/d(dof) of the chi-square quantile at (x, x2 = dof), 12 phi(x)/Phi(x),
- * 13 phi(x)/Phi(x) in float32.  x2 may be NULL unless fn is 4 or 11. */
+ * 13 phi(x)/Phi(x) in float32; the per-call cost probes of the GHK point
+ * loop (section 2): 14 one coordinate step Phi^-1(u Phi(x)) with u = x2,
+ * 15 the same in float32, 16 the accumulation of the weight x 2^x2 into a
+ * running sum and reference exponent taken from element i ^ 1 (out[i] =
+ * the new sum), 17 the same with a float32 weight.  x2 may be NULL unless
+ * fn is 4, 11 or 14..17. */
 int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
                        void* stream);
 

@@ -672,7 +672,8 @@ int cfust_em_fit(const double* y, int64_t n, int p, int q, int g, double* pi, do
 
 int cfust_eval_special(int fn, const double* x, const double* x2, double* out, int64_t n,
                        void* stream) {
-  if (!x || !out || n < 0 || fn < 0 || fn > 13 || ((fn == 4 || fn == 11) && !x2)) return CFUST_EINVAL;
+  if (!x || !out || n < 0 || fn < 0 || fn > 17 || ((fn == 4 || fn == 11 || fn >= 14) && !x2))
+    return CFUST_EINVAL;
   if (n == 0) return CFUST_OK;
   hipStream_t st = (hipStream_t)stream;
   special_kernel<<<(unsigned)((n + 127) / 128), 128, 0, st>>>(fn, x, x2, out, n);

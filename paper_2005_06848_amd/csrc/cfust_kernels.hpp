@@ -1720,6 +1720,48 @@ __global__ void special_kernel(int fn, const double* __restrict__ x, const doubl
     case 11: r = chi2_quantile_ddof(chi2_quantile(a, x2[t]), x2[t]); break;  // d x / d dof
     case 12: r = mills(phi_eval(a)); break;                                  // phi / Phi
     case 13: r = (double)mills(phi_eval((float)a)); break;                   // FP32
+    // per-call cost probes of the GHK point loop: one coordinate step
+    // (Phi at the bound x, then the draw Phi^-1(u Phi(x)) with u = x2), and
+    // one accumulation of a point's weight x 2^x2 into a running sum whose
+    // value and reference exponent come from the neighbouring element
+    case 14: {
+      const double u = x2[t];
+      r = draw_eval(u, 1.0 - u, phi_eval(a));
+      break;
+    }
+    case 15: {
+      const float u = (float)x2[t];
+      r = (double)draw_eval(u, 1.0f - u, phi_eval((float)a));
+      break;
+    }
+    case 16: {
+      const int64_t t1 = (t ^ 1) < n ? (t ^ 1) : t;
+      Acc<double> b;
+      b.s = x[t1];
+      double ref = x2[t1];
+      const double ex = x2[t];
+      if (ex > ref + Prec<double>::kRescale) {
+        b.scale(ldexp(1.0, shift_of(ref - ex)));
+        ref = ex;
+      }
+      b.add(Prec<double>::ldexp_(a, shift_of(ex - ref)));
+      r = b.value();
+      break;
+    }
+    case 17: {
+      const int64_t t1 = (t ^ 1) < n ? (t ^ 1) : t;
+      Acc<float> b;
+      b.s = x[t1];
+      int ref = (int)x2[t1];
+      const int ex = (int)x2[t];
+      if (ex > ref + Prec<float>::kRescale) {
+        b.scale(ldexpf(1.0f, shift_of(ref - ex)));
+        ref = ex;
+      }
+      b.add(Prec<float>::ldexp_((float)a, shift_of(ex - ref)));
+      r = b.value();
+      break;
+    }
     default: r = NAN;
   }
   out[t] = r;

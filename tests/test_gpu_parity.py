@@ -108,6 +108,32 @@ def test_special_functions(dev):
     m32 = native.cfust_eval_special(13, T(xm, dev)).cpu().numpy()
     ok32 = xm < 9  # above that phi(x) is below the float range
     np.testing.assert_allclose(m32[ok32], mref[ok32], rtol=1e-5)
+    # the per-call cost probes compute what the point loop computes: the
+    # coordinate step Phi^-1(u Phi(b)) (against scipy), and the weight's
+    # accumulation into a running sum with its reference exponent (exact:
+    # power-of-two scalings and one rounded add, redone in numpy)
+    rng = np.random.default_rng(9)
+    b = rng.uniform(-8.0, 5.0, 400)
+    u = rng.uniform(0.0, 1.0, 400)
+    wref = sp.ndtri(u * sp.ndtr(b))
+    w64 = native.cfust_eval_special(14, T(b, dev), T(u, dev)).cpu().numpy()
+    assert np.all(np.abs(w64 - wref) <= 1e-12 * np.maximum(np.abs(wref), 1.0))
+    w32 = native.cfust_eval_special(15, T(b, dev), T(u, dev)).cpu().numpy()
+    assert np.all(np.abs(w32 - wref) <= 2e-5 * np.maximum(np.abs(wref), 1.0))
+    m = rng.uniform(0.5, 1.0, 401)
+    e = rng.integers(-20, 21, 401).astype(np.float64)
+    e[::7] += 70.0  # some points move the reference (re-scaling the sum)
+    nb = np.arange(401) ^ 1
+    nb[nb >= 401] = 400
+    for fn, kr, mm in ((16, 64, m), (17, 32, m.astype(np.float32).astype(np.float64))):
+        # the running sum is a double in both; the FP32 weight is a float
+        s0, ref0 = m[nb].copy(), e[nb].copy()
+        up = e > ref0 + kr
+        s0[up] *= 2.0 ** (ref0[up] - e[up])
+        ref0[up] = e[up]
+        expect = s0 + mm * 2.0 ** (e - ref0)
+        got = native.cfust_eval_special(fn, T(m, dev), T(e, dev)).cpu().numpy()
+        np.testing.assert_array_equal(got, expect)
 
 
 def test_estep_config1(dev, orc):
