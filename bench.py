@@ -53,7 +53,7 @@ NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
 # Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
 # step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
-MEASURED_COSTS = {"sources": "33aa241a358c70c6",
+MEASURED_COSTS = {"sources": "173c98161bde5594",
                   "fp64": {"phi": 99, "phiinv": 91, "acc": 5},
                   "fp32": {"phi": 41, "phiinv": 30, "acc": 2}}
 
@@ -63,18 +63,23 @@ MEASURED_COSTS = {"sources": "33aa241a358c70c6",
 # sources they were taken on: `traffic` is null once the sources differ.
 # FETCH_SIZE 7480.42 KiB x 1.99976 + WRITE_SIZE 28299.1 KiB x 0.99999 (the
 # copy probe, 262144 KiB each way, read 131088 and 262146).
-PAIR_KERNEL_COUNTERS = {"sources": "33aa241a358c70c6", "traffic": 44296088}
+PAIR_KERNEL_COUNTERS = {"sources": "173c98161bde5594", "traffic": 44296088}
+
+
+# the sources the pair kernels, their launches and the diagnostic
+# special-function kernel are compiled from
+PAIR_KERNEL_SOURCES = ("cfust_coeffs.hpp", "cfust_host.hpp", "cfust_kernels.hpp",
+                       "cfust_math.hpp", "cfust_pairs.hip")
 
 
 def kernel_sources_digest():
-    """sha256 (first 16 hex digits) of the HIP sources of the library."""
+    """sha256 (first 16 hex digits) of the HIP sources of the pair kernels."""
     d = os.path.join(ROOT, "paper_2005_06848_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in PAIR_KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -64,16 +64,11 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2Hi = 0.69314718055994528623;   // double(ln 2)
 constexpr double kLn2Lo = 2.3190468138462996154e-17; // ln 2 - kLn2Hi
 
-// A zero the compiler cannot see through (one s_mov_b32, no memory access).
-// Offsetting table reads by it keeps the scalar loads of polynomial tables
-// next to their use: hoisted out of the point loop, the ~75 FP64 coefficients
-// would not fit the SGPR file and would spill into VGPR lanes.
-__device__ __forceinline__ int opaque_zero() {
-  int z;
-  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-  return z;
-}
-// The same as a 64-bit byte offset (one s_mov_b64, no widening or scaling).
+// A zero the compiler cannot see through, as a 64-bit byte offset (one
+// s_mov_b64, no memory access).  Offsetting table reads by it keeps the
+// scalar loads of polynomial tables next to their use: hoisted out of the
+// point loop, the ~75 FP64 coefficients would not fit the SGPR file and would
+// spill into VGPR lanes.
 __device__ __forceinline__ uint64_t opaque_zero64() {
   uint64_t z;
   asm volatile("s_mov_b64 %0, 0" : "=s"(z));
@@ -82,35 +77,6 @@ __device__ __forceinline__ uint64_t opaque_zero64() {
 template <int K>
 __device__ __forceinline__ const double* opaque_table(const double (&c)[K]) {
   return reinterpret_cast<const double*>(reinterpret_cast<const char*>(c) + opaque_zero64());
-}
-
-// sum_j c[j] x^j as four interleaved power sums over y = x^4,
-//   acc_m = sum_k c[4k+m] y^k,  result = acc_0 + x (acc_1 + x (acc_2 + x acc_3)).
-// Each coefficient enters as the multiplicand of an fma (acc += c * y^k), so it
-// is read straight from an SGPR; in Horner form it would be the tied addend of
-// v_fmac and cost two extra moves per step.  Rounding stays at a few ulp for
-// the tables used here (|x| <= 1 with decaying coefficients, or all terms of
-// one sign).
-template <int K>
-__device__ __forceinline__ double poly(const double (&c)[K], double x) {
-  static_assert(K >= 8, "poly: at least 8 coefficients");
-  const double* cp = c + opaque_zero();
-  double x2 = x * x;
-  double y = x2 * x2;
-  double acc[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) acc[m] = cp[4 + m] * y;  // c[4+m] y^1
-  double yk = y * y;
-#pragma unroll
-  for (int j = 8; j < K; j += 4) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (j + m < K) acc[m] = fma(cp[j + m], yk, acc[m]);
-    if (j + 4 < K) yk *= y;
-  }
-  // the constant terms c[0..3] enter through one add each (SGPR operand)
-  double r0 = acc[0] + cp[0], r1 = acc[1] + cp[1], r2 = acc[2] + cp[2], r3 = acc[3] + cp[3];
-  return fma(x2, fma(x, r3, r2), fma(x, r1, r0));
 }
 
 // Horner steps acc = acc * x + c_k (eight or four per block) with each

@@ -40,10 +40,24 @@ def test_flop_model_per_pair():
 
 def test_source_digest_gates_the_counter_fields():
     """roofline.traffic and the measured cost model apply only to the kernel
-    sources they were taken on: the digest covers every HIP source."""
+    sources they were taken on: the digest covers every source the pair
+    kernels and the cost probes are compiled from (every header the pair
+    translation unit includes from the package)."""
+    import re
     import bench
     d = bench.kernel_sources_digest()
     assert len(d) == 16 and d == bench.kernel_sources_digest()
+    csrc = os.path.join(ROOT, "paper_2005_06848_amd", "csrc")
+    seen, todo = set(), ["cfust_pairs.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f)) as fh:
+            todo += [m for m in re.findall(r'#include "([^"/]+)"', fh.read())
+                     if os.path.exists(os.path.join(csrc, m))]
+    assert seen == set(bench.PAIR_KERNEL_SOURCES), seen
     for name in ("PAIR_KERNEL_COUNTERS", "MEASURED_COSTS"):
         v = getattr(bench, name)
         assert v is None or set(v) >= {"sources"}
