@@ -53,7 +53,7 @@ NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
 # Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
 # step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
-MEASURED_COSTS = {"sources": "173c98161bde5594",
+MEASURED_COSTS = {"sources": "2170351f1694fff7",
                   "fp64": {"phi": 99, "phiinv": 91, "acc": 5},
                   "fp32": {"phi": 41, "phiinv": 30, "acc": 2}}
 
@@ -61,9 +61,9 @@ MEASURED_COSTS = {"sources": "173c98161bde5594",
 # WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
 # plain elementwise copy of known size), with the digest of the kernel
 # sources they were taken on: `traffic` is null once the sources differ.
-# FETCH_SIZE 7480.42 KiB x 1.99976 + WRITE_SIZE 28299.1 KiB x 0.99999 (the
-# copy probe, 262144 KiB each way, read 131088 and 262146).
-PAIR_KERNEL_COUNTERS = {"sources": "173c98161bde5594", "traffic": 44296088}
+# FETCH_SIZE 7475.85 KiB x 1.99977 + WRITE_SIZE 28190.1 KiB x 0.99997 (the
+# copy probe, 262144 KiB each way, read 131087 and 262153).
+PAIR_KERNEL_COUNTERS = {"sources": "2170351f1694fff7", "traffic": 44174460}
 
 
 # the sources the pair kernels, their launches and the diagnostic

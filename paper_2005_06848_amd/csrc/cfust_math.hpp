@@ -79,36 +79,146 @@ __device__ __forceinline__ const double* opaque_table(const double (&c)[K]) {
   return reinterpret_cast<const double*>(reinterpret_cast<const char*>(c) + opaque_zero64());
 }
 
-// Horner steps acc = acc * x + c_k (eight or four per block) with each
+// Horner steps acc = acc * x + c_k, k = n-1 .. 0, in one asm block, each
 // coefficient taken straight from an SGPR pair as the addend of a VOP3
 // v_fma_f64.  (Written as plain fma the compiler picks the two-address
 // v_fmac_f64, whose addend is the destination register, and copies every
-// coefficient into VGPRs first.)
-__device__ __forceinline__ double horner8(double acc, double x, const double* c) {
+// coefficient into VGPRs first.)  The scalar loads of a block's coefficients
+// complete before the block starts, behind one wait: scalar loads return out
+// of order, so every wait is for all of them, and a polynomial costs one
+// wait per block.  Blocks of up to 16 steps (32 SGPRs).
+// Steps per block: 16 measured 2.7% faster than 8 and 1.9% faster than 12 on
+// the FP64 pair kernel at p = q = 4 (fewer waits; larger blocks add SGPR
+// spills to VGPR lanes)
+constexpr int kHornerBlock = 16;
+template <int n>
+__device__ __forceinline__ double horner_block(double acc, double x, const double* c);
+
+template <>
+__device__ __forceinline__ double horner_block<1>(double acc, double x, const double* c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t"
-      "v_fma_f64 %0, %0, %1, %3\n\t"
-      "v_fma_f64 %0, %0, %1, %4\n\t"
-      "v_fma_f64 %0, %0, %1, %5\n\t"
-      "v_fma_f64 %0, %0, %1, %6\n\t"
-      "v_fma_f64 %0, %0, %1, %7\n\t"
-      "v_fma_f64 %0, %0, %1, %8\n\t"
-      "v_fma_f64 %0, %0, %1, %9"
       : "+v"(acc)
-      : "v"(x), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]),
-        "s"(c[0]));
+      : "v"(x), "s"(c[0]));
   return acc;
 }
-__device__ __forceinline__ double horner4(double acc, double x, const double* c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t"
-      "v_fma_f64 %0, %0, %1, %3\n\t"
-      "v_fma_f64 %0, %0, %1, %4\n\t"
-      "v_fma_f64 %0, %0, %1, %5"
+
+template <>
+__device__ __forceinline__ double horner_block<2>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<3>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<4>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
   return acc;
 }
-__device__ __forceinline__ double horner1(double acc, double x, double c) {
-  asm("v_fma_f64 %0, %0, %1, %2" : "+v"(acc) : "v"(x), "s"(c));
+
+template <>
+__device__ __forceinline__ double horner_block<5>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<6>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<7>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<8>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<9>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<10>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<11>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<12>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<13>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<14>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<15>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ double horner_block<16>(double acc, double x, const double* c) {
+  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t" "v_fma_f64 %0, %0, %1, %17\n\t"
+      : "+v"(acc)
+      : "v"(x), "s"(c[15]), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
   return acc;
 }
 
@@ -123,13 +233,12 @@ __device__ __forceinline__ double horner(const double (&c)[K], double x) {
   static_assert(K >= 2, "horner: at least 2 coefficients");
   const double* cp = opaque_table(c);
   double acc = cp[K - 1];
-  int j = K - 2;  // next coefficient
+  // K - 1 steps: blocks of kHornerBlock, then one block of the rest
+  constexpr int B = kHornerBlock;
+  constexpr int kFull = (K - 1) / B, kRest = (K - 1) % B;
 #pragma unroll
-  for (; j >= 7; j -= 8) acc = horner8(acc, x, cp + j - 7);
-#pragma unroll
-  for (; j >= 3; j -= 4) acc = horner4(acc, x, cp + j - 3);
-#pragma unroll
-  for (; j >= 0; --j) acc = horner1(acc, x, cp[j]);
+  for (int b = 0; b < kFull; ++b) acc = horner_block<B>(acc, x, cp + K - 1 - B - B * b);
+  if constexpr (kRest > 0) acc = horner_block<kRest>(acc, x, cp);
   return acc;
 }
 
