@@ -206,9 +206,11 @@ def surrogate_form(args, native, torch, np, inputs, dev):
     """Surrogate form on the n=1000000, p=q=6, g=4, N=8192 workload: E-step
     time of the FP64 and FP32 GHK paths, of the shipped network alone, with
     the GHK check over m sampled observations (difference estimator), and
-    with one adaptation (GHK labels of 16384 sampled pairs, 20 epochs) first;
-    the accuracy of each against the FP64 GHK E-step on all 1000000
-    observations.  The k-means start uses one restart here."""
+    with one adaptation (GHK labels of 16384 sampled pairs, 20 epochs) first,
+    and with both; the accuracy of each against the FP64 GHK E-step on all
+    1000000 observations; and the shipped network's fallback, time and
+    accuracy at the true parameters.  The k-means start uses one restart
+    here."""
     from paper_2005_06848_amd import surrogate as S
     print("[bench] surrogate: generating n=1000000 p=q=6 g=4", file=sys.stderr, flush=True)
     c = inputs.config(5, kmeans_restarts=1)
@@ -265,19 +267,108 @@ def surrogate_form(args, native, torch, np, inputs, dev):
     acc["adapted"] = err(native.cfust_estep(y, par, u, want=(), surrogate=net))
     acc["adapted_checked"] = err(native.cfust_estep(y, par, u, want=(), surrogate=net,
                                                     surrogate_check=M_CHECK))
+    # the E-step that meets both targets after an adaptation: adaptation,
+    # then the network with the check (FP64 and FP32 check pairs)
+    res["adapt_plus_checked_ms"] = round(timed(
+        lambda: (net.adapt(y, par, u, samples=16384, epochs=20),
+                 native.cfust_estep(y, par, u, want=(), surrogate=net,
+                                    surrogate_check=M_CHECK))), 2)
+    res["adapt_plus_checked_fp32_ms"] = round(timed(
+        lambda: (net.adapt(y, par, u, samples=16384, epochs=20),
+                 native.cfust_estep(y, par, u, want=(), surrogate=net, surrogate_check=M_CHECK,
+                                    precision="fp32"))), 2)
     res["accuracy_vs_fp64_ghk_all_observations"] = acc
+    # at the true parameters (where EM ends): the shipped network's fallback,
+    # time and accuracy, against the FP64 GHK E-step there
+    print("[bench] surrogate: at the true parameters", file=sys.stderr, flush=True)
+    net = native.Surrogate.load(S.DEFAULT_PATH)
     res["network_ms_at_true_params"] = round(timed(
         lambda: native.cfust_estep(y, ptrue, u, want=(), surrogate=net)), 2)
     res["fallback_pairs_at_true_params"] = net.fallback_count()
+    st_ref, ll_ref = totals(native.cfust_estep(y, ptrue, u, want=()))
+    res["accuracy_at_true_params"] = {
+        "shipped": err(native.cfust_estep(y, ptrue, u, want=(), surrogate=net)),
+        "shipped_checked": err(native.cfust_estep(y, ptrue, u, want=(), surrogate=net,
+                                                  surrogate_check=M_CHECK))}
     res["pairs"] = c["n"] * c["g"]
     res["speedup_network_vs_fp64"] = round(res["fp64_ghk_ms"] / res["network_ms"], 2)
     res["speedup_network_checked_vs_fp64"] = round(res["fp64_ghk_ms"] / res["network_checked_ms"], 2)
     res["speedup_network_checked_fp32_vs_fp64"] = round(
         res["fp64_ghk_ms"] / res["network_checked_fp32_ms"], 2)
     res["speedup_adapt_plus_network_vs_fp64"] = round(res["fp64_ghk_ms"] / res["adapt_plus_network_ms"], 2)
+    res["speedup_adapt_plus_checked_vs_fp64"] = round(
+        res["fp64_ghk_ms"] / res["adapt_plus_checked_ms"], 2)
+    res["speedup_adapt_plus_checked_fp32_vs_fp64"] = round(
+        res["fp64_ghk_ms"] / res["adapt_plus_checked_fp32_ms"], 2)
     res["speedup_fp32_vs_fp64"] = round(res["fp64_ghk_ms"] / res["fp32_ghk_ms"], 2)
     res["tolerance"] = ("target 1e-3 on moments (partial sums, normwise per component), 1e-5 "
                         "relative on the log-likelihood (tests/test_gpu_surrogate.py)")
+    return res
+
+
+def surrogate_em_form(args, native, torch, np, inputs, dev):
+    """Whole fits on the n=1000000, p=q=6, g=4, N=8192 workload from the
+    k-means start, FP32 integrand: GHK EM against the two-phase EM with the
+    shipped network, adapted before every surrogate E-step (16384 pairs, 10
+    epochs) and checked over 50000 observations (5%), switching at a relative
+    l change below 3e-7.  Both run in calls of 40 iterations, each printing
+    its l, and stop when a call with GHK E-steps stops by Aitken's rule
+    (each call restarts the rule).  Reports each fit's l, iterations and
+    wall time."""
+    from paper_2005_06848_amd import surrogate as S
+    c = inputs.config(5, kmeans_restarts=1)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    y, u = T(c["y"]), T(c["u"])
+    par0 = {k: T(v) for k, v in c["init"].items()}
+    keys = ("pi", "mu", "Sigma", "Delta", "nu")
+    tol, cap, switch = 25.0, 900, 3e-7
+    res = {"workload": "cfust-em n=1000000 p=q=6 g=4 N=8192 (k-means start), fp32 integrand",
+           "tol_abs": tol, "max_iter": cap, "surrogate_switch": switch, "check_observations": 50000}
+    print("[bench] surrogate EM: GHK EM in chunks of 40", file=sys.stderr, flush=True)
+    par, trace = dict(par0), []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while len(trace) < cap + 1:
+        f = native.cfust_em_fit(y, par, u, max_iter=40, tol=tol, precision="fp32")
+        trace += f["trace"] if not trace else f["trace"][1:]
+        par = {k: f[k] for k in keys}
+        print(f"[bench]   GHK EM: {len(trace) - 1} iterations, l {trace[-1]:.3f}",
+              file=sys.stderr, flush=True)
+        if f["n_iter"] < 40:  # stopped by Aitken's rule
+            break
+    torch.cuda.synchronize()
+    res["ghk"] = {"seconds": round(time.perf_counter() - t0, 2), "iterations": len(trace) - 1,
+                  "loglik_final": trace[-1]}
+    print("[bench] surrogate EM: two-phase fit in chunks of 40", file=sys.stderr, flush=True)
+    # chunks of 40 iterations: surrogate chunks until one switches to GHK
+    # E-steps, GHK chunks after that (each chunk restarts the stopping rule)
+    net = native.Surrogate.load(S.DEFAULT_PATH)
+    par, ts, sw, done = dict(par0), [], -1, False
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while not done and len(ts) < cap + 1:
+        if sw < 0:
+            f = native.cfust_em_fit(y, par, u, max_iter=40, tol=tol, precision="fp32",
+                                    surrogate=net, adapt_samples=16384, adapt_epochs=10,
+                                    surrogate_check=50000, surrogate_switch=switch)
+            s_ = net.em_switch()
+            if s_ >= 0:
+                sw = len(ts) + s_ - (1 if ts else 0)
+        else:
+            f = native.cfust_em_fit(y, par, u, max_iter=40, tol=tol, precision="fp32")
+        # after the switch a call that ends before its cap stopped by Aitken
+        done = sw >= 0 and f["n_iter"] < 40
+        ts += f["trace"] if not ts else f["trace"][1:]
+        par = {k: f[k] for k in keys}
+        print(f"[bench]   two-phase: {len(ts) - 1} iterations, switch {sw}, l {ts[-1]:.3f}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    res["two_phase"] = {"seconds": round(time.perf_counter() - t0, 2), "iterations": len(ts) - 1,
+                        "switch_iteration": sw, "loglik_final": ts[-1],
+                        "surrogate_phase_last_loglik": ts[sw - 1] if sw > 0 else None,
+                        "ghk_loglik_at_switch": ts[sw] if sw >= 0 else None}
+    res["final_loglik_rel_diff"] = abs(ts[-1] / trace[-1] - 1)
+    res["speedup_two_phase_vs_ghk"] = round(res["ghk"]["seconds"] / res["two_phase"]["seconds"], 3)
     return res
 
 
@@ -480,6 +571,9 @@ def parse():
                     help="batched leg: only the 256 small problems, not the 64 starts")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the 50-iteration EM fit of the benchmark workload")
+    ap.add_argument("--surrogate-em", action="store_true",
+                    help="also run the whole-fit comparison of GHK EM and the two-phase "
+                         "surrogate EM at n=1000000 (several minutes)")
     ap.add_argument("--no-high-q", action="store_true",
                     help="skip the high-q stress leg (100 EM iterations, n=202, p=q=11, g=2, N=8192)")
     ap.add_argument("--no-sequential", action="store_true",
@@ -606,6 +700,9 @@ def main():
     if not args.no_high_q:
         forms = forms or {}
         forms["high_q"] = high_q_form(args, native, torch, np, inputs, dev)
+    if args.surrogate_em:
+        forms = forms or {}
+        forms["surrogate_em"] = surrogate_em_form(args, native, torch, np, inputs, dev)
     if not args.no_fit:
         forms = forms or {}
         forms["em_fit"] = em_fit_form(args, native, torch, np, inputs, dev)

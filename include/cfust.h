@@ -323,7 +323,9 @@ typedef struct cfust_surrogate cfust_surrogate;
 /* Creates an untrained network for q with the training range
  * range[6] (host) = h_lo, h_hi (box for every h_m), dof_lo, dof_hi,
  * r_max (bound on |r|), eig_min (bound on the smallest eigenvalue of R):
- * the E-step uses the network only for pairs inside it.  Weights are drawn
+ * the E-step uses the network only for pairs inside it, after lowering
+ * every h_m above h_hi to h_hi (a coordinate bounded that high is nearly
+ * untruncated: the t tail above 6 is below 1e-3 for dof >= 5).  Weights are drawn
  * from a seeded normal of variance 2 / fan_in, biases zero. */
 int cfust_surrogate_create(int q, const double* range, unsigned long long seed,
                            cfust_surrogate** out);

@@ -896,9 +896,11 @@ int cfust_surrogate_adapt(cfust_surrogate* s, const double* y, int64_t n, int p,
   const SurrRange& r = s->rg;
   std::vector<double> hs, Rs, dofs, fs;
   for (int64_t k = 0; k < 2 * samples; ++k) {
-    const double* f = fh.data() + k * F;
+    double* f = fh.data() + k * F;
     bool in = f[F - 1] >= r.dof_lo && f[F - 1] <= r.dof_hi;
-    for (int a = 0; a < q && in; ++a) in = f[a] >= r.h_lo && f[a] <= r.h_hi;
+    // as in the E-step: bounds above h_hi lowered to h_hi, below h_lo out
+    for (int a = 0; a < q; ++a) f[a] = fmin(f[a], r.h_hi);
+    for (int a = 0; a < q && in; ++a) in = f[a] >= r.h_lo;
     for (int a = q; a < F - 1 && in; ++a) in = fabs(f[a]) <= r.r_max;
     if (!in) continue;
     fs.insert(fs.end(), f, f + F);

@@ -213,9 +213,14 @@ __global__ __launch_bounds__(256) void surr_feat_kernel(
   if (!fin) set_status(status, kENonFinite, -1);
   pair_bounds<Q>(cp, p, d, c, hA, hB);
   bool in = fin && cok[i] != 0;
+  // bounds above h_hi are lowered to h_hi (the coordinate is then nearly
+  // untruncated); bounds below h_lo send the pair to the GHK path
 #pragma unroll
-  for (int m = 0; m < Q; ++m)
-    in = in && hA[m] >= rg.h_lo && hA[m] <= rg.h_hi && hB[m] >= rg.h_lo && hB[m] <= rg.h_hi;
+  for (int m = 0; m < Q; ++m) {
+    hA[m] = fmin(hA[m], rg.h_hi);
+    hB[m] = fmin(hB[m], rg.h_hi);
+    in = in && hA[m] >= rg.h_lo && hB[m] >= rg.h_lo;
+  }
   const float* cfi = cf + i * 32;
   write_feature_row<Q>(X + (size_t)(2 * t) * kMlpPad, hA, cfi, cfi[NR], stdv, stdv + kMlpPad, !in);
   write_feature_row<Q>(X + (size_t)(2 * t + 1) * kMlpPad, hB, cfi, cfi[NR + 1], stdv,

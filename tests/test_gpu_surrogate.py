@@ -240,6 +240,28 @@ def test_out_of_range_pairs_fall_back_to_ghk(dev):
         assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b)), k
 
 
+def test_bounds_above_the_box_are_lowered_not_sent_to_ghk(dev):
+    """A bound above the network's box top is lowered to it (that coordinate
+    is then nearly untruncated); only a bound below the box bottom sends the
+    pair to the GHK path.  With the box [-4, 2] (and no limit on R or dof)
+    the pairs that fall back are exactly those with some bound below -4 in
+    either integral, while many in-range pairs have bounds above 2."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=3000)
+    par = {k: T(v, dev) for k, v in c["true"].items()}
+    y, u = T(c["y"], dev), T(inputs.qmc_points(256, c["q"]), dev)
+    net = native.Surrogate.create(6, [-4.0, 2.0, 1.0, 1000.0, 1.0, 0.0], seed=4)
+    net.set_state(None, np.tile(np.repeat(np.array([0.0, 1.0], np.float32), 64), 2))
+    f = native.cfust_pair_features(y, par).cpu().numpy()
+    h = f[:, :6].reshape(-1, 2, 6)
+    low = np.any(h < -4.0, axis=(1, 2))
+    high = np.any(h > 2.0, axis=(1, 2))
+    assert np.sum(high & ~low) > 1000 and np.sum(low) > 0
+    print("[gpu] estep with bounds above the box n=3000", flush=True)
+    native.cfust_estep(y, par, u, want=(), surrogate=net)
+    assert net.fallback_count() == int(np.sum(low))
+
+
 # ---------------------------------------------------------------------------
 # the trained network shipped with the package (trained on the GPU by
 # ``python -m paper_2005_06848_amd.surrogate``), checked against the GHK kernel
