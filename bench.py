@@ -53,7 +53,7 @@ NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
 # Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
 # step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
-MEASURED_COSTS = {"sources": "2170351f1694fff7",
+MEASURED_COSTS = {"sources": "d400d6de828237a2",
                   "fp64": {"phi": 99, "phiinv": 91, "acc": 5},
                   "fp32": {"phi": 41, "phiinv": 30, "acc": 2}}
 
@@ -61,9 +61,11 @@ MEASURED_COSTS = {"sources": "2170351f1694fff7",
 # WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
 # plain elementwise copy of known size), with the digest of the kernel
 # sources they were taken on: `traffic` is null once the sources differ.
-# FETCH_SIZE 7475.85 KiB x 1.99977 + WRITE_SIZE 28190.1 KiB x 0.99997 (the
-# copy probe, 262144 KiB each way, read 131087 and 262153).
-PAIR_KERNEL_COUNTERS = {"sources": "2170351f1694fff7", "traffic": 44174460}
+# FETCH_SIZE 3358.33 KiB x 1.99977 + WRITE_SIZE 7968.75 KiB x 0.99996 (the
+# copy probe, 262144 KiB each way, read 131087 and 262154): the writes are
+# the pair records alone, the reads y, the tables once per XCD and the
+# component blocks.
+PAIR_KERNEL_COUNTERS = {"sources": "d400d6de828237a2", "traffic": 15036762}
 
 
 # the sources the pair kernels, their launches and the diagnostic

@@ -801,7 +801,8 @@ __device__ __forceinline__ void part_reduce(const double* __restrict__ part, int
   }
 }
 
-template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false, int PHASE = 0>
+template <typename T, int Q, bool MOM, bool EXACT = false, bool REORDER = false, int PHASE = 0,
+          bool PARK = false>
 __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
                                          const double* __restrict__ mui,
                                          const double* __restrict__ cp,
@@ -810,7 +811,8 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
                                          const T* __restrict__ ubT, int N, int lane,
                                          double* lane_out, const T* __restrict__ tAi = nullptr,
                                          double* cw = nullptr, double* part = nullptr,
-                                         int k0 = 0, int kstep = 64, int K = 1) {
+                                         int k0 = 0, int kstep = 64, int K = 1,
+                                         double* park = nullptr) {
   constexpr int PW = part_width<Q, MOM, EXACT>();
   constexpr bool TAN = EXACT && MOM;  // integral A carries its tangent
   constexpr int OFF_B = TAN ? 3 : 2;
@@ -903,10 +905,36 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
   double logTA, logTB = 0.0;
   double m1[Q], m2[Q][Q];
   GhkPart<Q, false, TAN> pa;
+  double dlogJ = 0.0;
   if constexpr (PHASE == 0) {
+    // with PARK the wave-uniform values read again only after integral B
+    // wait in this wave's LDS slot park[Q + 3] instead of registers
+    constexpr bool kPark = PARK && MOM;
+    if (kPark && lane == 0) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) park[k] = c[k];
+      park[Q] = d;
+    }
     ghk_sums<T, Q, false, TAN>(htA, Ct, sAi, nullptr, tAi, uT, ubT, N, 0, 64, lane, pa);
     ghk_finish<Q, false, TAN>(pa, Cm, N, &logTA, m1, m2);
-    if (MOM) ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+    if (TAN) dlogJ = pa.D / pa.S0;
+    if (MOM) {
+      if (kPark && lane == 0) {
+        park[Q + 1] = logTA;
+        park[Q + 2] = dlogJ;
+      }
+      ghk_integral<T, Q, true>(htB, Ct, Cm, sBi, rsBi, uT, ubT, N, lane, &logTB, m1, m2);
+      if constexpr (kPark) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int k = 0; k < Q; ++k) c[k] = park[k];
+        d = park[Q];
+        logTA = park[Q + 1];
+        dlogJ = park[Q + 2];
+      }
+    }
   } else if constexpr (PHASE == 1) {
     ghk_sums<T, Q, false, TAN>(htA, Ct, sAi, nullptr, tAi, uT, ubT, N, k0, kstep, lane, pa);
     if (lane == 0) part_store<Q, false, TAN>(pa, part);
@@ -919,6 +947,7 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
   } else {
     part_reduce<Q, false, TAN>(part, PW, 0, K, pa);
     ghk_finish<Q, false, TAN>(pa, Cm, N, &logTA, m1, m2);
+    if (TAN) dlogJ = pa.D / pa.S0;
     if (MOM) {
       GhkPart<Q, MOM> pb;
       part_reduce<Q, MOM>(part, PW, OFF_B, K, pb);
@@ -926,9 +955,8 @@ __device__ __forceinline__ int pair_eval(const double* __restrict__ yj, int p,
     }
   }
 
-  // ---- exact E[log W | y]: d/da log T_q(h_A sqrt(a'/a); R, 2a') at a' = a,
-  // the derivative of the estimate over the same points ----
-  const double dlogJ = TAN ? pa.D / pa.S0 : 0.0;
+  // (dlogJ: the exact E[log W | y]'s d/da log T_q(h_A sqrt(a'/a); R, 2a') at
+  // a' = a, the derivative of the estimate over the same points)
 
   // moments back to the original labelling: m1[perm[m]] = m1'[m],
   // m2[perm[m]][perm[n]] = m2'[m][n] (rows, then columns, by selects)
@@ -1029,14 +1057,21 @@ void pair_kernel(
   const int64_t j = pair / g;
   const int i = (int)(pair - j * g);
   const CompLayout cl(p, Q);
-  // per-wave slot for the ordered Cholesky factor (REORDER only)
-  __shared__ double cfac[REORDER ? 4 * Q * Q : 1];
+  // per-wave LDS slot: the ordered Cholesky factor (REORDER only), then
+  // the values parked across integral B (MOM).  Parking pays at q <= 4,
+  // where the four-wave register budget otherwise spills them to scratch
+  // around integral B (0.9% faster at p = q = 4, and no scratch traffic);
+  // at q = 6 it added VALU instructions to the loops.
+  constexpr int SF = REORDER ? Q * Q : 0;
+  constexpr int SP = MOM ? Q + 3 : 0;
+  __shared__ double slot[4 * (SF + SP) + 1];
+  double* ws = slot + wv * (SF + SP);
   constexpr int RW = record_width<Q, MOM>();
   double out[RW > 64 ? 2 : 1];
-  const int rc = pair_eval<T, Q, MOM, EXACT, REORDER>(
+  const int rc = pair_eval<T, Q, MOM, EXACT, REORDER, 0, (Q <= 4)>(
       y + j * p, p, mu + (size_t)i * p, comp + (size_t)i * cl.stride, sA + (size_t)i * N,
       sB + (size_t)i * N, rsB + (size_t)i * N, uT, ubT, N, lane, out,
-      EXACT ? tA + (size_t)i * N : nullptr, REORDER ? cfac + wv * Q * Q : nullptr);
+      EXACT ? tA + (size_t)i * N : nullptr, REORDER ? ws : nullptr, nullptr, 0, 64, 1, ws + SF);
   if (rc != kOk) {
     if (lane == 0) set_status(status, rc, rc == kENotPD ? i : -1);
     return;

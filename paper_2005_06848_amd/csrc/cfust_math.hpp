@@ -64,19 +64,17 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2Hi = 0.69314718055994528623;   // double(ln 2)
 constexpr double kLn2Lo = 2.3190468138462996154e-17; // ln 2 - kLn2Hi
 
-// A zero the compiler cannot see through, as a 64-bit byte offset (one
-// s_mov_b64, no memory access).  Offsetting table reads by it keeps the
-// scalar loads of polynomial tables next to their use: hoisted out of the
-// point loop, the ~75 FP64 coefficients would not fit the SGPR file and would
-// spill into VGPR lanes.
-__device__ __forceinline__ uint64_t opaque_zero64() {
-  uint64_t z;
-  asm volatile("s_mov_b64 %0, 0" : "=s"(z));
-  return z;
-}
+// The address of a coefficient table, as a pointer into the constant address
+// space that the compiler cannot see through (an empty asm on the SGPR pair).
+// The table's scalar loads then stay next to their use, with immediate
+// offsets from this one base: hoisted out of the point loop, the ~75 FP64
+// coefficients would not fit the SGPR file and would spill into VGPR lanes.
+typedef const __attribute__((address_space(4))) double* const_dptr;
 template <int K>
-__device__ __forceinline__ const double* opaque_table(const double (&c)[K]) {
-  return reinterpret_cast<const double*>(reinterpret_cast<const char*>(c) + opaque_zero64());
+__device__ __forceinline__ const_dptr opaque_table(const double (&c)[K]) {
+  const_dptr p = (const_dptr)c;
+  asm volatile("" : "+s"(p));
+  return p;
 }
 
 // Horner steps acc = acc * x + c_k, k = n-1 .. 0, in one asm block, each
@@ -92,10 +90,10 @@ __device__ __forceinline__ const double* opaque_table(const double (&c)[K]) {
 // spills to VGPR lanes)
 constexpr int kHornerBlock = 16;
 template <int n>
-__device__ __forceinline__ double horner_block(double acc, double x, const double* c);
+__device__ __forceinline__ double horner_block(double acc, double x, const_dptr c);
 
 template <>
-__device__ __forceinline__ double horner_block<1>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<1>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[0]));
@@ -103,7 +101,7 @@ __device__ __forceinline__ double horner_block<1>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<2>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<2>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[1]), "s"(c[0]));
@@ -111,7 +109,7 @@ __device__ __forceinline__ double horner_block<2>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<3>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<3>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -119,7 +117,7 @@ __device__ __forceinline__ double horner_block<3>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<4>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<4>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -127,7 +125,7 @@ __device__ __forceinline__ double horner_block<4>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<5>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<5>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -135,7 +133,7 @@ __device__ __forceinline__ double horner_block<5>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<6>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<6>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -143,7 +141,7 @@ __device__ __forceinline__ double horner_block<6>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<7>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<7>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -151,7 +149,7 @@ __device__ __forceinline__ double horner_block<7>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<8>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<8>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -159,7 +157,7 @@ __device__ __forceinline__ double horner_block<8>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<9>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<9>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -167,7 +165,7 @@ __device__ __forceinline__ double horner_block<9>(double acc, double x, const do
 }
 
 template <>
-__device__ __forceinline__ double horner_block<10>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<10>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -175,7 +173,7 @@ __device__ __forceinline__ double horner_block<10>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<11>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<11>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -183,7 +181,7 @@ __device__ __forceinline__ double horner_block<11>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<12>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<12>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -191,7 +189,7 @@ __device__ __forceinline__ double horner_block<12>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<13>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<13>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -199,7 +197,7 @@ __device__ __forceinline__ double horner_block<13>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<14>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<14>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -207,7 +205,7 @@ __device__ __forceinline__ double horner_block<14>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<15>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<15>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -215,7 +213,7 @@ __device__ __forceinline__ double horner_block<15>(double acc, double x, const d
 }
 
 template <>
-__device__ __forceinline__ double horner_block<16>(double acc, double x, const double* c) {
+__device__ __forceinline__ double horner_block<16>(double acc, double x, const_dptr c) {
   asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t" "v_fma_f64 %0, %0, %1, %17\n\t"
       : "+v"(acc)
       : "v"(x), "s"(c[15]), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
@@ -223,7 +221,7 @@ __device__ __forceinline__ double horner_block<16>(double acc, double x, const d
 }
 
 // sum_j c[j] x^j by Horner's rule, K - 1 fma.  The coefficients are read
-// through scalar loads at the point of use (opaque_zero keeps the compiler
+// through scalar loads at the point of use (opaque_table keeps the compiler
 // from hoisting them out of the point loop, where they would not fit the
 // SGPR file) and enter as SGPR operands.  Rounding stays at a few ulp for the
 // tables used here (|x| <= 1 with decaying coefficients, or all terms of one
@@ -231,7 +229,7 @@ __device__ __forceinline__ double horner_block<16>(double acc, double x, const d
 template <int K>
 __device__ __forceinline__ double horner(const double (&c)[K], double x) {
   static_assert(K >= 2, "horner: at least 2 coefficients");
-  const double* cp = opaque_table(c);
+  const const_dptr cp = opaque_table(c);
   double acc = cp[K - 1];
   // K - 1 steps: blocks of kHornerBlock, then one block of the rest
   constexpr int B = kHornerBlock;
