@@ -11,6 +11,13 @@ place of E[V V^T].  Training runs the library's BF16 matrix-core forward/backwar
 Adam kernels (cfust_surrogate_train).
 
 Run:  python -m paper_2005_06848_amd.surrogate --out <file>
+
+Options reach beyond that recipe: --h-lo lowers the bottom of the h box
+(uniform samples then fill the core [-4, 6]^6 for --core-share of them and
+the whole box for the rest; proposal bounds above the top are lowered to it,
+as the E-step does), --with-true adds the draws' true parameters to the
+logged points, and --init starts from a saved network (its parameters and
+standardisation, under the new box).
 """
 from __future__ import annotations
 
@@ -53,7 +60,7 @@ def eig_threshold(R):
 
 
 def proposal_rows(seeds=PROPOSAL_SEEDS, n_obs=50_000, iterates=(0, 3, 10, 30), per_iterate=100_000,
-                  device="cuda"):
+                  device="cuda", with_true=False, clamp_top=False):
     """Feature rows (h | r | dof) of both integrals of the pairs of FP32 EM
     runs on other draws of the surrogate workload's recipe (n_obs
     observations, p = q = 6, g = 4), logged at the starting values and at
@@ -67,13 +74,19 @@ def proposal_rows(seeds=PROPOSAL_SEEDS, n_obs=50_000, iterates=(0, 3, 10, 30), p
         u = torch.tensor(c["u"], device=device)
         par = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=device)
                for k, v in c["init"].items()}
+        true = {k: torch.tensor(np.asarray(v, dtype=np.float64), device=device)
+                for k, v in c["true"].items() if k in ("pi", "mu", "Sigma", "Delta", "nu")}
         done = 0
-        for it in iterates:
-            if it > done:
+        for it in list(iterates) + ([None] if with_true else []):
+            if it is None:
+                par = true
+            elif it > done:
                 res = nat.cfust_em_fit(y, par, u, max_iter=it - done, tol=0.0, precision="fp32")
                 par = {k: res[k] for k in ("pi", "mu", "Sigma", "Delta", "nu")}
                 done = it
             f = nat.cfust_pair_features(y, par).cpu().numpy()
+            if clamp_top:
+                f[:, :Q] = np.minimum(f[:, :Q], H_HI)
             keep = (np.all((f[:, :Q] >= H_LO) & (f[:, :Q] <= H_HI), axis=1)
                     & np.all(np.abs(f[:, Q:-1]) <= R_MAX, axis=1)
                     & (f[:, -1] >= DOF_LO) & (f[:, -1] <= DOF_HI))
@@ -104,14 +117,18 @@ def label(h, R, dof, u, chunk=1 << 18, device="cuda"):
     return torch.cat(out)
 
 
-def training_set(m, seed=1, proposal=None, n_label=N_LABEL, device="cuda"):
+def training_set(m, seed=1, proposal=None, n_label=N_LABEL, device="cuda", core_share=0.0):
     """Feature rows (device [m][22]) and labels (device [m][28]): the first
     half (all rows without a proposal) with R ~ LKJ(2), dof on the grid and h
     uniform in the box, the second half drawn from the proposal rows.  Also
     returns the smallest-eigenvalue threshold of the LKJ part."""
     rng = np.random.default_rng(seed)
     k = m if proposal is None or not len(proposal) else m - m // 2
-    h, R, dof = inputs.surrogate_samples(rng, k, Q, H_LO, H_HI, DOF_LO, DOF_HI, 0.25, 2.0)
+    core = None
+    if core_share > 0.0:
+        core = rng.uniform(-4.0, 6.0, size=(int(core_share * k), Q))
+    h, R, dof = inputs.surrogate_samples(rng, k, Q, H_LO, H_HI, DOF_LO, DOF_HI, 0.25, 2.0,
+                                         h_extra=core)
     thr = eig_threshold(R)
     if k < m:
         pr = proposal[rng.integers(0, len(proposal), size=m - k)]
@@ -132,15 +149,20 @@ def output_weights(q=Q):
     return w
 
 
-def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, device="cuda"):
+def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, device="cuda",
+          with_true=False, clamp_top=False, core_share=0.0, init=None):
     t0 = time.time()
-    prop = proposal_rows(device=device)
+    prop = proposal_rows(device=device, with_true=with_true, clamp_top=clamp_top)
     log(f"proposal rows {len(prop)} ({time.time() - t0:.1f} s)")
-    feat, targ, thr = training_set(m, seed=seed, proposal=prop, device=device)
+    feat, targ, thr = training_set(m, seed=seed, proposal=prop, device=device,
+                                   core_share=core_share)
     torch.cuda.synchronize()
     log(f"training set {m} samples labelled ({time.time() - t0:.1f} s)")
     rng_ = [H_LO, H_HI, DOF_LO, DOF_HI, R_MAX, thr]
     net = nat.Surrogate.create(Q, rng_, seed=seed)
+    if init is not None:
+        # start from a saved network: its parameters and standardisation
+        net.set_state(*nat.Surrogate.load(init).get_state())
     trace = []
     step = 10
     for e0 in range(0, epochs, step):
@@ -157,6 +179,7 @@ def train(m=2_000_000, epochs=200, batch=4096, lr0=2e-3, lr1=2e-6, seed=7, devic
 
 
 def main():
+    global H_LO
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--samples", type=int, default=2_000_000)
@@ -165,8 +188,17 @@ def main():
     ap.add_argument("--lr0", type=float, default=2e-3)
     ap.add_argument("--lr1", type=float, default=2e-6)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--h-lo", type=float, default=H_LO, help="bottom of the h box")
+    ap.add_argument("--core-share", type=float, default=0.0,
+                    help="share of the uniform samples drawn in the core box [-4, 6]^6")
+    ap.add_argument("--with-true", action="store_true",
+                    help="log the draws' true parameters too")
+    ap.add_argument("--init", default=None, help="start from this saved network")
     a = ap.parse_args()
-    net, trace, rng_ = train(a.samples, a.epochs, a.batch, a.lr0, a.lr1, a.seed)
+    H_LO = a.h_lo
+    net, trace, rng_ = train(a.samples, a.epochs, a.batch, a.lr0, a.lr1, a.seed,
+                             with_true=a.with_true, clamp_top=a.h_lo != -4.0 or a.with_true,
+                             core_share=a.core_share, init=a.init)
     net.save(a.out)
     log(f"saved {a.out}; range {rng_}; final loss {trace[-1]:.3e}")
 
