@@ -53,7 +53,7 @@ NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
 # Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
 # step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
-MEASURED_COSTS = {"sources": "d400d6de828237a2",
+MEASURED_COSTS = {"sources": "a586ea317c7806bb",
                   "fp64": {"phi": 99, "phiinv": 91, "acc": 5},
                   "fp32": {"phi": 41, "phiinv": 30, "acc": 2}}
 
@@ -65,7 +65,7 @@ MEASURED_COSTS = {"sources": "d400d6de828237a2",
 # copy probe, 262144 KiB each way, read 131087 and 262154): the writes are
 # the pair records alone, the reads y, the tables once per XCD and the
 # component blocks.
-PAIR_KERNEL_COUNTERS = {"sources": "d400d6de828237a2", "traffic": 15036762}
+PAIR_KERNEL_COUNTERS = {"sources": "a586ea317c7806bb", "traffic": 15036762}
 
 
 # the sources the pair kernels, their launches and the diagnostic

@@ -92,133 +92,120 @@ constexpr int kHornerBlock = 16;
 template <int n>
 __device__ __forceinline__ double horner_block(double acc, double x, const_dptr c);
 
-template <>
-__device__ __forceinline__ double horner_block<1>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[0]));
-  return acc;
-}
+// horner_block<n>: n steps in one asm statement, operands %2 .. %(n+1) =
+// c[n-1] .. c[0] (one SGPR pair each)
+#define CFUST_FMA_STEP(i) "v_fma_f64 %0, %0, %1, %" #i "\n\t"
+#define CFUST_HORNER_BLOCK(n, steps, ...)                                              \
+  template <>                                                                          \
+  __device__ __forceinline__ double horner_block<n>(double acc, double x, const_dptr c) { \
+    asm(steps : "+v"(acc) : "v"(x), __VA_ARGS__);                                      \
+    return acc;                                                                        \
+  }
 
-template <>
-__device__ __forceinline__ double horner_block<2>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(1,
+                   CFUST_FMA_STEP(2),
+                   "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<3>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(2,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3),
+                   "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<4>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(3,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4),
+                   "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<5>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(4,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5),
+                   "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<6>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(5,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6),
+                   "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<7>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(6,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7),
+                   "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<8>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(7,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8),
+                   "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]),
+                   "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<9>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(8,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9),
+                   "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]),
+                   "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<10>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(9,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10),
+                   "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]),
+                   "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<11>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(10,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11),
+                   "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]),
+                   "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<12>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(11,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12),
+                   "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]),
+                   "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<13>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(12,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12) CFUST_FMA_STEP(13),
+                   "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]),
+                   "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<14>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(13,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12) CFUST_FMA_STEP(13)
+                   CFUST_FMA_STEP(14),
+                   "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]),
+                   "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]),
+                   "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<15>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(14,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12) CFUST_FMA_STEP(13)
+                   CFUST_FMA_STEP(14) CFUST_FMA_STEP(15),
+                   "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]),
+                   "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]),
+                   "s"(c[1]), "s"(c[0]))
 
-template <>
-__device__ __forceinline__ double horner_block<16>(double acc, double x, const_dptr c) {
-  asm("v_fma_f64 %0, %0, %1, %2\n\t" "v_fma_f64 %0, %0, %1, %3\n\t" "v_fma_f64 %0, %0, %1, %4\n\t" "v_fma_f64 %0, %0, %1, %5\n\t" "v_fma_f64 %0, %0, %1, %6\n\t" "v_fma_f64 %0, %0, %1, %7\n\t" "v_fma_f64 %0, %0, %1, %8\n\t" "v_fma_f64 %0, %0, %1, %9\n\t" "v_fma_f64 %0, %0, %1, %10\n\t" "v_fma_f64 %0, %0, %1, %11\n\t" "v_fma_f64 %0, %0, %1, %12\n\t" "v_fma_f64 %0, %0, %1, %13\n\t" "v_fma_f64 %0, %0, %1, %14\n\t" "v_fma_f64 %0, %0, %1, %15\n\t" "v_fma_f64 %0, %0, %1, %16\n\t" "v_fma_f64 %0, %0, %1, %17\n\t"
-      : "+v"(acc)
-      : "v"(x), "s"(c[15]), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]));
-  return acc;
-}
+CFUST_HORNER_BLOCK(15,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12) CFUST_FMA_STEP(13)
+                   CFUST_FMA_STEP(14) CFUST_FMA_STEP(15) CFUST_FMA_STEP(16),
+                   "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]), "s"(c[9]),
+                   "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]),
+                   "s"(c[2]), "s"(c[1]), "s"(c[0]))
+
+CFUST_HORNER_BLOCK(16,
+                   CFUST_FMA_STEP(2) CFUST_FMA_STEP(3) CFUST_FMA_STEP(4) CFUST_FMA_STEP(5)
+                   CFUST_FMA_STEP(6) CFUST_FMA_STEP(7) CFUST_FMA_STEP(8) CFUST_FMA_STEP(9)
+                   CFUST_FMA_STEP(10) CFUST_FMA_STEP(11) CFUST_FMA_STEP(12) CFUST_FMA_STEP(13)
+                   CFUST_FMA_STEP(14) CFUST_FMA_STEP(15) CFUST_FMA_STEP(16) CFUST_FMA_STEP(17),
+                   "s"(c[15]), "s"(c[14]), "s"(c[13]), "s"(c[12]), "s"(c[11]), "s"(c[10]),
+                   "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]),
+                   "s"(c[3]), "s"(c[2]), "s"(c[1]), "s"(c[0]))
+
+#undef CFUST_HORNER_BLOCK
+#undef CFUST_FMA_STEP
 
 // sum_j c[j] x^j by Horner's rule, K - 1 fma.  The coefficients are read
 // through scalar loads at the point of use (opaque_table keeps the compiler
