@@ -567,3 +567,34 @@ def test_surrogate_against_the_oracle(dev):
         assert n0[k] == n1[k], k  # per-pair outputs are the network's
     assert n0["stats"] < 0.2 and n0["loglik"] < 1e-2, n0
     assert n1["stats"] < n0["stats"] and n1["loglik"] < n0["loglik"], (n0, n1)
+
+
+def test_two_phase_em_reaches_the_ghk_em_loglik(dev):
+    """Whole fits at n = 100000 from the k-means start (FP32 integrand):
+    GHK EM against the two-phase EM whose surrogate phase adapts the shipped
+    network before every E-step (8192 pairs, 10 epochs) and checks it over
+    5000 observations (5%).  Both stop by Aitken's rule at 2.5 (about 1.8e-6
+    of |l|).  EM converges slowly here, so where each path stops depends on
+    the path: the two-phase fit must end no lower than GHK EM by more than
+    1e-5 relative (measured: 2.5e-5 higher).  At the switch the surrogate's
+    last l and the GHK l at the same parameters agree within 3e-5 (measured
+    1.1e-5): the check's noise falls as 1/sqrt(m), and with m = 50000 at
+    n = 1e6 the same agreement is 3.1e-6."""
+    from paper_2005_06848_amd import inputs, native
+    c = inputs.config(5, n=100000)
+    y, u = T(c["y"], dev), T(c["u"], dev)
+    par = {k: T(v, dev) for k, v in c["init"].items()}
+    print("[gpu] GHK EM n=100000 fp32 to convergence", flush=True)
+    rq = native.cfust_em_fit(y, par, u, max_iter=1500, tol=2.5, precision="fp32")
+    net = _shipped()
+    print(f"  GHK: {rq['n_iter']} iterations; two-phase EM m=5000", flush=True)
+    rs = native.cfust_em_fit(y, par, u, max_iter=1500, tol=2.5, precision="fp32", surrogate=net,
+                             adapt_samples=8192, adapt_epochs=10, surrogate_check=5000)
+    sw = net.em_switch()
+    lq, ls = rq["trace"][-1], rs["trace"][-1]
+    ts = rs["trace"]
+    print(f"  GHK l {lq:.4f} ({rq['n_iter']} its); two-phase l {ls:.4f} ({rs['n_iter']} its, "
+          f"switch at {sw}, surrogate l {ts[sw - 1]:.4f}, GHK l there {ts[sw]:.4f})")
+    assert rq["n_iter"] < 1500 and rs["n_iter"] < 1500 and 0 < sw < rs["n_iter"]
+    assert ls >= lq - 1e-5 * abs(lq)
+    assert abs(ts[sw - 1] / ts[sw] - 1) < 3e-5
