@@ -342,8 +342,11 @@ def test_two_phase_em_tracks_ghk_em(dev):
 
 
 def test_surrogate_estep_gain(dev):
-    """The gain: E-step time with the shipped network (and with one
-    adaptation first) against the FP64 GHK E-step, n=200000 p=q=6 g=4 N=8192."""
+    """The gain: E-step time with the shipped network, with one adaptation
+    first, and with the GHK check over 65536 observations using FP32 check
+    pairs (the configuration that meets both targets at this size,
+    test_surrogate_check_meets_the_accuracy_targets), against the FP64 GHK
+    E-step, n=200000 p=q=6 g=4 N=8192."""
     import time
     import torch
     from paper_2005_06848_amd import inputs, native
@@ -362,11 +365,14 @@ def test_surrogate_estep_gain(dev):
         return time.perf_counter() - t0
     t_ghk = timed(lambda: native.cfust_estep(y, par, u, want=()))
     t_net = timed(lambda: native.cfust_estep(y, par, u, want=(), surrogate=net))
+    t_chk = timed(lambda: native.cfust_estep(y, par, u, want=(), surrogate=_shipped(),
+                                             surrogate_check=65536, precision="fp32"))
     t_ad = timed(lambda: (net.adapt(y, par, u, samples=16384, epochs=20),
                           native.cfust_estep(y, par, u, want=(), surrogate=net)))
     print(f"  FP64 GHK {t_ghk * 1e3:.1f} ms, network {t_net * 1e3:.1f} ms "
-          f"({t_ghk / t_net:.0f}x), adaptation + network {t_ad * 1e3:.1f} ms ({t_ghk / t_ad:.1f}x)")
-    assert t_net * 20 < t_ghk and t_ad * 2 < t_ghk
+          f"({t_ghk / t_net:.0f}x), network + FP32 check {t_chk * 1e3:.1f} ms "
+          f"({t_ghk / t_chk:.1f}x), adaptation + network {t_ad * 1e3:.1f} ms ({t_ghk / t_ad:.1f}x)")
+    assert t_net * 20 < t_ghk and t_chk * 3 < t_ghk and t_ad * 2 < t_ghk
 
 
 def test_fused_inference_matches_reference(dev):
