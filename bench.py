@@ -472,14 +472,22 @@ def batched_small(args, native, torch, np, inputs, dev):
     if not args.no_sequential:
         ys = [T(c["y"]) for c in probs]
         ps = [{k: T(v) for k, v in c["init"].items()} for c in probs]
+        prof = native.prof_buffer()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        points = 0
         for k in range(len(probs)):
-            native.cfust_em_fit(ys[k], ps[k], u, max_iter=it, tol=1e-6, precision="fp32")
+            f = native.cfust_em_fit(ys[k], ps[k], u, max_iter=it, tol=1e-6, precision="fp32",
+                                    prof=prof)
+            points += (int(f["n_iter"]) + 1) * n[k] * g[k] * 1024
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         res["sequential_seconds"] = round(ts, 4)
         res["speedup_vs_sequential"] = round(ts / tb, 2)
+        # the one-by-one fits' pair kernels (each pair split over several
+        # waves at these sizes) per pair and QMC point, for comparison with
+        # the persistent batched kernel's (from its kernel trace)
+        res["sequential_pair_kernel_ps_per_pair_point"] = round(prof[1] * 1e9 / points, 2)
     return res
 
 
