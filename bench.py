@@ -392,7 +392,8 @@ def batched_form(args, native, torch, np, inputs, dev):
     iterations and autotuned launch shape; compared with fitting the same
     starts one after another through the single-problem entry point."""
     if args.no_batched_large:
-        return {"small_problems": batched_small(args, native, torch, np, inputs, dev)}
+        return {"small_problems": batched_small(args, native, torch, np, inputs, dev),
+                "paper_size_problems": batched_paper_size(args, native, torch, np, inputs, dev)}
     print("[bench] batched: generating 64 starts", file=sys.stderr, flush=True)
     probs = inputs.batched_problems(64)
     u = inputs.qmc_points(4096, 5)
@@ -442,7 +443,58 @@ def batched_form(args, native, torch, np, inputs, dev):
         res["sequential_host_us_per_iteration"] = round(1e6 * (ts - kern) / seq_iters, 1)
         res["sequential_kernel_ms_per_iteration"] = round(1e3 * kern / seq_iters, 3)
     res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
+    res["paper_size_problems"] = batched_paper_size(args, native, torch, np, inputs, dev)
     return res
+
+
+def batched_paper_size(args, native, torch, np, inputs, dev):
+    """Starts at the paper's data-set size, where one wave per pair leaves
+    the chip idle at the end of every launch: 32 starts with n = 202,
+    g ~ U{2..6}, p = q = 5, N = 4096, FP32 integrand, exactly 50 iterations
+    (tolerance 0).  The autotuned fit (it may give each pair K waves of
+    N / K points) against the fastest shape with one wave per pair, each
+    K = 1 candidate pinned in turn."""
+    print("[bench] batched: 32 starts of n = 202", file=sys.stderr, flush=True)
+    probs = inputs.batched_problems(32, n_lo=202, n_hi=202, seed_offset=6)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    u = T(inputs.qmc_points(4096, 5))
+    y = T(np.concatenate([c["y"] for c in probs]))
+    par = {k: T(np.concatenate([c["init"][k] for c in probs])) for k in ("pi", "mu", "Sigma", "Delta", "nu")}
+    n = [c["n"] for c in probs]
+    g = [c["g"] for c in probs]
+    it = 50
+
+    def fit(tile):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, trace, n_iter, status = native.cfust_em_fit_batched(y, n, g, par, u, max_iter=it,
+                                                               tol=0.0, precision="fp32",
+                                                               tile=tile)
+        torch.cuda.synchronize()
+        assert int((status != 0).sum()) == 0
+        return time.perf_counter() - t0, trace
+
+    native.cfust_em_fit_batched(y, n, g, par, u, max_iter=1, tol=0.0, precision="fp32")
+    ta, trace_a = fit(0)
+    shape = native.cfust_batched_config()
+    one_wave = {}
+    k = 0
+    while True:
+        s = native.cfust_batched_shape(k)
+        if s is None:
+            break
+        if s["waves_per_pair"] == 1:
+            one_wave[k + 1] = fit(k + 1)
+        k += 1
+    best = min(one_wave, key=lambda t: one_wave[t][0])
+    t1, trace_1 = one_wave[best]
+    pairs = sum(n[k] * g[k] for k in range(len(n)))
+    return {"workload": "32 starts, n=202, g~U{2..6}, p=q=5, N=4096, fp32 integrand, 50 iterations",
+            "pairs_per_iteration": pairs, "seconds": round(ta, 4), "launch_shape": shape,
+            "one_wave_per_pair_best_seconds": round(t1, 4),
+            "one_wave_per_pair_best_shape": native.cfust_batched_shape(best - 1),
+            "speedup_of_tuned_split": round(t1 / ta, 3),
+            "final_loglik_rel_diff_vs_one_wave": float(np.max(np.abs(trace_a[:, it] / trace_1[:, it] - 1)))}
 
 
 def batched_small(args, native, torch, np, inputs, dev):

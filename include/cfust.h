@@ -86,9 +86,10 @@ typedef struct cfust_opts {
                              [3] M-step */
   int graph;              /* cfust_em_fit_batched: nonzero = capture one iteration in a
                              hipGraph and replay it (default 1) */
-  int tile;               /* cfust_em_fit_batched: launch shape of the persistent pair
-                             kernel, 0 = autotune, else 1 + index into the candidate
-                             table (see cfust_batched_config) */
+  int tile;               /* cfust_em_fit_batched: launch shape of the pair kernels,
+                             0 = autotune, else 1 + index into the candidate table
+                             (cfust_batched_shape); a shape with more waves per pair
+                             than the batch allows is CFUST_EINVAL */
   struct cfust_surrogate* surrogate; /* optional trained surrogate network: when set,
                              cfust_estep / cfust_loglik / cfust_em_fit evaluate the two
                              GHK integrals of every in-range pair with it and the
@@ -278,11 +279,26 @@ int cfust_em_fit_multistart(const double* y, int64_t n, int p, int q, int g, int
 int cfust_batched_workspace_size(int p, int q, int n_problems, const int64_t* n_obs, const int* g,
                                  int n_qmc, int precision, int max_iter, size_t* bytes);
 
-/* Launch shape chosen for the last cfust_em_fit_batched call (host outputs):
- * waves per block, pairs per work-queue fetch, resident waves per SIMD, and
- * the autotuner's timing of that shape in ms (0 if not tuned).  Returns the
- * number of candidate shapes. */
-int cfust_batched_config(int* waves_per_block, int* chunk, int* waves_per_simd, double* tuned_ms);
+/* Launch shape chosen for the last cfust_em_fit_batched call (host outputs,
+ * each may be NULL): waves per block, work items per work-queue fetch,
+ * persistent waves per SIMD, waves per pair K (each of a pair's K waves
+ * integrates N / K of its QMC points; the K partial sums are combined in a
+ * fixed order), the QMC points per wave N / K, and the autotuner's timing of
+ * that shape in ms (0 if not tuned).  Returns the number of candidate shapes.
+ * The autotuner offers K > 1 only to batches of fewer than 65536 pairs, with
+ * K a power of two, K <= 8 and K <= N / 256; the choice is cached per (q, N,
+ * precision, largest K offered) for the life of the process.  Results depend
+ * on K only through the order of the QMC sums (FP64: about 1e-13 relative);
+ * pin the shape with opts.tile for results that are bitwise repeatable
+ * across processes. */
+int cfust_batched_config(int* waves_per_block, int* chunk, int* waves_per_simd,
+                         int* waves_per_pair, int* points_per_wave, double* tuned_ms);
+
+/* Candidate launch shape `index` (0-based; opts.tile = index + 1 selects it):
+ * host outputs as in cfust_batched_config, each may be NULL.  Returns
+ * CFUST_EINVAL for an index outside [0, number of candidates). */
+int cfust_batched_shape(int index, int* waves_per_block, int* chunk, int* waves_per_simd,
+                        int* waves_per_pair);
 
 /* GHK estimates for M standardised problems (the integrals behind eq. (2) and
  * the truncated moments of section 2): for sample s, V ~ t_q(0, R_s, dof_s)

@@ -21,27 +21,54 @@ using namespace cfust::host;
 
 namespace {
 
+// Launch shape of the pair kernels: waves per block, work items per fetch,
+// persistent waves per SIMD, and waves per pair (K: each wave integrates
+// N / K of the pair's QMC points; K > 1 runs bpart_kernel + bfinish_kernel).
 struct Shape {
-  int wpb, chunk, wps;  // waves per block, pairs per fetch, waves per SIMD
+  int wpb, chunk, wps, split;
 };
-const Shape kShapes[] = {{1, 1, 4}, {1, 4, 4}, {2, 2, 4}, {4, 1, 4}, {4, 4, 4},
-                         {1, 1, 8}, {2, 4, 8}, {4, 2, 8}, {1, 16, 4}, {4, 16, 8}};
+const Shape kShapes[] = {{1, 1, 4, 1}, {1, 4, 4, 1}, {2, 2, 4, 1}, {4, 1, 4, 1},
+                         {4, 4, 4, 1}, {1, 1, 8, 1}, {2, 4, 8, 1}, {4, 2, 8, 1},
+                         {1, 16, 4, 1}, {4, 16, 8, 1}, {1, 1, 4, 2}, {4, 1, 4, 2},
+                         {1, 2, 8, 2}, {1, 1, 4, 4}, {4, 1, 4, 4}, {1, 1, 4, 8}};
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
+// Splitting a pair is offered only to batches of fewer than kSplitPairs
+// pairs (above that the persistent waves are busy for at least 16 pairs
+// each and the tail is a small fraction), with at least four points per
+// lane in every slice (K <= N / 256), K a power of two up to kSplitMax.
+constexpr int64_t kSplitPairs = 65536;
+constexpr int kSplitMax = 8;
+
+int max_split(int64_t total_pairs, int N) {
+  if (total_pairs >= kSplitPairs) return 1;
+  int K = 1;
+  while (2 * K <= kSplitMax && 2 * K <= N / 256) K *= 2;
+  return K;
+}
+
+// doubles of one slice record of the split kernels (the exact-nu width, so
+// the workspace size does not depend on the nu mode): integral A's R, S0
+// and tangent, integral B's R, S0, S1[q] and S2[q(q+1)/2]
+int split_part_width(int q) { return 5 + q + q * (q + 1) / 2; }
+
 struct LastCfg {
-  Shape s{4, 4, 4};
+  Shape s{4, 4, 4, 1};
   double ms = 0.0;
+  int N = 0;
 };
 LastCfg g_last;
 std::mutex g_mu;
 struct TuneKey {
-  int q, N, prec;
-  bool operator==(const TuneKey& o) const { return q == o.q && N == o.N && prec == o.prec; }
+  int q, N, prec, kmax;
+  bool operator==(const TuneKey& o) const {
+    return q == o.q && N == o.N && prec == o.prec && kmax == o.kmax;
+  }
 };
 std::vector<std::pair<TuneKey, LastCfg>> g_tuned;
 
 struct BPlan {
-  int P, p, q, N, prec, W, S, G, stride, tile, ny, total_blocks, red_total, max_iter;
+  int P, p, q, N, prec, W, S, G, stride, tile, ny, total_blocks, red_total, max_iter, kmax;
   int64_t total_obs, total_pairs, total_part;
   std::vector<int64_t> n_off, pair_off, per_blk, part_off;
   std::vector<int> g_off, blk_off, red_off;
@@ -49,7 +76,7 @@ struct BPlan {
   // workspace offsets
   size_t o_noff, o_goff, o_poff, o_boff, o_perb, o_partoff, o_roff, o_active, o_status, o_iter,
       o_niter, o_llcur, o_trace, o_comp, o_uT, o_ubT, o_sA, o_sB, o_rsB, o_pair, o_part, o_pll,
-      o_stats, o_pitmp, o_mwork, o_counter, o_pstat, o_tA, total;
+      o_stats, o_pitmp, o_mwork, o_counter, o_pstat, o_tA, o_split, total;
   bool exact = false;  // exact E[log W | y] (tangent table o_tA)
 };
 
@@ -140,6 +167,10 @@ int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, i
   pl->o_counter = take(64);
   pl->o_pstat = take(4 * sizeof(int));
   pl->o_tA = take((size_t)pl->G * N * es);  // used with the exact nu step only
+  pl->kmax = max_split(pl->total_pairs, N);
+  pl->o_split = take(pl->kmax > 1 ? (size_t)pl->total_pairs * pl->kmax * split_part_width(q) *
+                                        sizeof(double)
+                                  : 0);
   pl->total = off;
   return CFUST_OK;
 }
@@ -180,6 +211,19 @@ void launch_bpair_e(const BPlan& pl, const BatchDev& b, char* base, const BArgs&
                     hipStream_t st, const Shape& sh, unsigned int total, int n_cu) {
   int waves = sh.wps * 4 * n_cu;
   int blocks = std::max(1, waves / sh.wpb);
+  if (sh.split > 1) {
+    const int K = sh.split;
+    double* parts = (double*)(base + pl.o_split);
+    bpart_kernel<T, Q, EXACT><<<blocks, 64 * sh.wpb, 0, st>>>(
+        b, a.y, a.mu, (const double*)(base + pl.o_comp), (const T*)(base + pl.o_sA),
+        (const T*)(base + pl.o_sB), (const T*)(base + pl.o_rsB), (const T*)(base + pl.o_uT),
+        (const T*)(base + pl.o_ubT), pl.N, K, parts, (unsigned int*)(base + pl.o_counter),
+        total * (unsigned int)K, sh.chunk, EXACT ? (const T*)(base + pl.o_tA) : nullptr);
+    bfinish_kernel<T, Q, EXACT><<<(total + 3) / 4, 256, 0, st>>>(
+        b, a.y, a.mu, (const double*)(base + pl.o_comp), pl.N, K, parts,
+        (double*)(base + pl.o_pair), total);
+    return;
+  }
   bpair_kernel<T, Q, EXACT><<<blocks, 64 * sh.wpb, 0, st>>>(
       b, a.y, a.mu, (const double*)(base + pl.o_comp), (const T*)(base + pl.o_sA),
       (const T*)(base + pl.o_sB), (const T*)(base + pl.o_rsB), (const T*)(base + pl.o_uT),
@@ -247,22 +291,29 @@ void batched_iteration(const BPlan& pl, const BatchDev& b, char* base, const BAr
                                      (double*)(base + pl.o_mwork));
 }
 
-// Autotuner: times the persistent pair kernel of every candidate shape on the
-// first pairs of the batch (about 1/8 of the work, at least one full wave of
-// fetches) after one warm-up launch, and keeps the fastest.
+// Autotuner: times the pair kernels of every candidate shape that the batch
+// allows (waves per pair up to pl.kmax) after one warm-up launch, and keeps
+// the fastest.  Large batches are timed on their first pairs (about 1/8 of
+// the work, at least 8192 pairs); a batch small enough to be offered split
+// shapes is timed whole, since the point of splitting is how the last
+// pairs of a launch share the chip.
 template <typename T>
 LastCfg autotune(const BPlan& pl, const BatchDev& b, char* base, const BArgs& a, hipStream_t st,
                  int n_cu) {
   LastCfg best;
   best.ms = 1e300;
-  unsigned int sub = (unsigned int)std::min<int64_t>(pl.total_pairs,
-                                                     std::max<int64_t>(pl.total_pairs / 8, 8192));
+  best.N = pl.N;
+  unsigned int sub =
+      pl.kmax > 1 ? (unsigned int)pl.total_pairs
+                  : (unsigned int)std::min<int64_t>(pl.total_pairs,
+                                                    std::max<int64_t>(pl.total_pairs / 8, 8192));
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   launch_bprepare<T>(pl, b, base, a, st);
   launch_bpair_q<T>(pl, b, base, a, st, kShapes[0], sub, n_cu);
   for (int s = 0; s < kNumShapes; ++s) {
+    if (kShapes[s].split > pl.kmax) continue;
     (void)hipEventRecord(e0, st);
     launch_bpair_q<T>(pl, b, base, a, st, kShapes[s], sub, n_cu);
     (void)hipEventRecord(e1, st);
@@ -309,11 +360,12 @@ int run_batched(const BPlan& pl, char* base, const BArgs& a, hipStream_t st, con
   // launch shape
   LastCfg cfg;
   const int tile = o ? o->tile : 0;
+  cfg.N = pl.N;
   if (tile > 0) {
-    if (tile > kNumShapes) return CFUST_EINVAL;
+    if (tile > kNumShapes || kShapes[tile - 1].split > pl.kmax) return CFUST_EINVAL;
     cfg.s = kShapes[tile - 1];
   } else {
-    TuneKey key{pl.q, pl.N, pl.prec};
+    TuneKey key{pl.q, pl.N, pl.prec, pl.kmax};
     bool found = false;
     {
       std::lock_guard<std::mutex> lk(g_mu);
@@ -603,11 +655,24 @@ extern "C" int cfust_batched_workspace_size(int p, int q, int n_problems, const 
 }
 
 extern "C" int cfust_batched_config(int* waves_per_block, int* chunk, int* waves_per_simd,
-                                    double* tuned_ms) {
+                                    int* waves_per_pair, int* points_per_wave, double* tuned_ms) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (waves_per_block) *waves_per_block = g_last.s.wpb;
   if (chunk) *chunk = g_last.s.chunk;
   if (waves_per_simd) *waves_per_simd = g_last.s.wps;
+  if (waves_per_pair) *waves_per_pair = g_last.s.split;
+  if (points_per_wave) *points_per_wave = g_last.N / g_last.s.split;
   if (tuned_ms) *tuned_ms = g_last.ms;
   return kNumShapes;
+}
+
+extern "C" int cfust_batched_shape(int index, int* waves_per_block, int* chunk,
+                                   int* waves_per_simd, int* waves_per_pair) {
+  if (index < 0 || index >= kNumShapes) return CFUST_EINVAL;
+  const Shape& s = kShapes[index];
+  if (waves_per_block) *waves_per_block = s.wpb;
+  if (chunk) *chunk = s.chunk;
+  if (waves_per_simd) *waves_per_simd = s.wps;
+  if (waves_per_pair) *waves_per_pair = s.split;
+  return CFUST_OK;
 }

@@ -160,6 +160,86 @@ void bpair_kernel(BatchDev b, const double* __restrict__ y,
   }
 }
 
+// The same index space with each pair's QMC points spread over K waves, for
+// batches with too few pairs to keep every SIMD busy to the end: item
+// w = t K + s is slice s of pair t, the points s 64 + lane + i 64 K of both
+// integrals.  bpart_kernel pulls items from *counter and writes each item's
+// exponent-aligned sums to parts[w][part_width]; bfinish_kernel (one wave
+// per pair) combines a pair's K records in the order s = 0..K-1 and
+// assembles the pair record as bpair_kernel does.  The results differ from
+// K = 1 only in the order of the sums.
+template <typename T, int Q, bool EXACT = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bpair_occupancy<T, Q>())))
+void bpart_kernel(BatchDev b, const double* __restrict__ y, const double* __restrict__ mu,
+                  const double* __restrict__ comp, const T* __restrict__ sA,
+                  const T* __restrict__ sB, const T* __restrict__ rsB,
+                  const T* __restrict__ uT, const T* __restrict__ ubT, int N, int K,
+                  double* __restrict__ parts, unsigned int* counter, unsigned int total_items,
+                  int chunk, const T* __restrict__ tA) {
+  constexpr int PW = part_width<Q, true, EXACT>();
+  const int lane = threadIdx.x & 63;
+  const CompLayout cl(b.p, Q);
+  for (;;) {
+    unsigned int base = 0;
+    if (lane == 0) base = atomicAdd(counter, (unsigned int)chunk);
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (base >= total_items) break;
+    const unsigned int end = min(total_items, base + (unsigned int)chunk);
+    for (unsigned int w = base; w < end; ++w) {
+      const unsigned int t = w / (unsigned int)K;
+      const int s = (int)(w - t * (unsigned int)K);
+      const int k = find_slot(b.pair_off, b.P, (int64_t)t);
+      if (!b.active[k]) continue;
+      const int c0 = b.g_off[k], g = b.g_off[k + 1] - c0;
+      const int64_t local = (int64_t)t - b.pair_off[k];
+      const int64_t j = local / g;
+      const int c = c0 + (int)(local - j * g);
+      double out;
+      const bool ok = kOk == pair_eval<T, Q, true, EXACT, false, 1>(
+                                 y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
+                                 comp + (size_t)c * cl.stride, sA + (size_t)c * N,
+                                 sB + (size_t)c * N, rsB + (size_t)c * N, uT, ubT, N, lane, &out,
+                                 EXACT ? tA + (size_t)c * N : nullptr, nullptr,
+                                 parts + (size_t)w * PW, 64 * s, 64 * K, K);
+      if (!ok && lane == 0) fail_problem(b, k, kENonFinite, -1);
+    }
+  }
+}
+
+template <typename T, int Q, bool EXACT = false>
+__global__ __launch_bounds__(256) void bfinish_kernel(BatchDev b, const double* __restrict__ y,
+                                                      const double* __restrict__ mu,
+                                                      const double* __restrict__ comp, int N,
+                                                      int K, const double* __restrict__ parts,
+                                                      double* __restrict__ pairbuf,
+                                                      unsigned int total) {
+  constexpr int PW = part_width<Q, true, EXACT>();
+  constexpr int RW = record_width<Q, true>();
+  static_assert(RW <= 64, "one record entry per lane");
+  const int lane = threadIdx.x & 63;
+  const unsigned int t =
+      blockIdx.x * 4u + (unsigned int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= total) return;
+  const int k = find_slot(b.pair_off, b.P, (int64_t)t);
+  if (!b.active[k]) return;
+  const CompLayout cl(b.p, Q);
+  const int c0 = b.g_off[k], g = b.g_off[k + 1] - c0;
+  const int64_t local = (int64_t)t - b.pair_off[k];
+  const int64_t j = local / g;
+  const int c = c0 + (int)(local - j * g);
+  double out;
+  const bool ok = kOk == pair_eval<T, Q, true, EXACT, false, 2>(
+                             y + (b.n_off[k] + j) * b.p, b.p, mu + (size_t)c * b.p,
+                             comp + (size_t)c * cl.stride, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, N, lane, &out, nullptr, nullptr,
+                             const_cast<double*>(parts) + (size_t)t * K * PW, 0, 64, K);
+  if (!ok) {
+    if (lane == 0) fail_problem(b, k, kENonFinite, -1);
+    return;
+  }
+  if (lane < RW) pairbuf[(size_t)t * b.W + lane] = out;
+}
+
 // statistics blocks of all problems: block x of problem k covers
 // observations [(x - blk_off[k]) per_blk[k], ...) of that problem
 __global__ __launch_bounds__(256) void bstats_kernel(BatchDev b, const double* __restrict__ y,

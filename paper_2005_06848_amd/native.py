@@ -116,9 +116,11 @@ def _lib():
         L.cfust_em_fit_multistart.restype = i
         L.cfust_batched_workspace_size.argtypes = [i, i, i, P, P, i, i, i, ctypes.POINTER(sz)]
         L.cfust_batched_workspace_size.restype = i
-        L.cfust_batched_config.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
-                                           ctypes.POINTER(d)]
+        ip = ctypes.POINTER(i)
+        L.cfust_batched_config.argtypes = [ip, ip, ip, ip, ip, ctypes.POINTER(d)]
         L.cfust_batched_config.restype = i
+        L.cfust_batched_shape.argtypes = [i, ip, ip, ip, ip]
+        L.cfust_batched_shape.restype = i
         L.cfust_ghk_batch.argtypes = [i, i64, P, P, P, P, i, ctypes.POINTER(Opts), P]
         L.cfust_ghk_batch.restype = i
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -442,11 +444,25 @@ def cfust_em_fit_multistart(y, starts, u, burn_in=0, max_iter=100, tol=1e-6, **o
 
 
 def cfust_batched_config():
-    w, c, s = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    w, c, s, k, ppw = (ctypes.c_int(0) for _ in range(5))
     ms = ctypes.c_double(0)
-    n = _lib().cfust_batched_config(ctypes.byref(w), ctypes.byref(c), ctypes.byref(s), ctypes.byref(ms))
-    return dict(waves_per_block=w.value, chunk=c.value, waves_per_simd=s.value, tuned_ms=ms.value,
+    n = _lib().cfust_batched_config(ctypes.byref(w), ctypes.byref(c), ctypes.byref(s),
+                                    ctypes.byref(k), ctypes.byref(ppw), ctypes.byref(ms))
+    return dict(waves_per_block=w.value, chunk=c.value, waves_per_simd=s.value,
+                waves_per_pair=k.value, points_per_wave=ppw.value, tuned_ms=ms.value,
                 n_candidates=n)
+
+
+def cfust_batched_shape(index):
+    """Candidate launch shape `index` of the batched form (tile = index + 1),
+    or None outside the table."""
+    w, c, s, k = (ctypes.c_int(0) for _ in range(4))
+    rc = _lib().cfust_batched_shape(int(index), ctypes.byref(w), ctypes.byref(c), ctypes.byref(s),
+                                    ctypes.byref(k))
+    if rc != OK:
+        return None
+    return dict(waves_per_block=w.value, chunk=c.value, waves_per_simd=s.value,
+                waves_per_pair=k.value)
 
 
 def cfust_ghk_batch(h, R, dof, u, **opt):

@@ -69,3 +69,44 @@ def test_product_path_does_not_import_oracle():
         if name.endswith(".py"):
             text = open(os.path.join(ROOT, "paper_2005_06848_amd", name)).read()
             assert "import oracle" not in text and "from oracle" not in text, name
+
+
+def test_batched_shape_table_and_split_workspace(libpath):
+    """The batched form's candidate shapes (host only) include several waves
+    per pair, and a batch small enough to be offered them gets a workspace
+    with room for the K slice records of every pair."""
+    from paper_2005_06848_amd import native
+    shapes = []
+    k = 0
+    while True:
+        s = native.cfust_batched_shape(k)
+        if s is None:
+            break
+        shapes.append(s)
+        k += 1
+    assert len(shapes) == native.cfust_batched_config()["n_candidates"]
+    assert native.cfust_batched_shape(-1) is None
+    splits = {s["waves_per_pair"] for s in shapes}
+    assert splits == {1, 2, 4, 8}
+    assert all(s["waves_per_block"] in (1, 2, 4) and s["chunk"] >= 1 for s in shapes)
+    L = ctypes.CDLL(libpath)
+    L.cfust_batched_workspace_size.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 2 + \
+        [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_size_t)]
+
+    def ws(n_list, g_list, N):
+        P = len(n_list)
+        n_arr = (ctypes.c_int64 * P)(*n_list)
+        g_arr = (ctypes.c_int * P)(*g_list)
+        out = ctypes.c_size_t(0)
+        assert L.cfust_batched_workspace_size(5, 5, P, n_arr, g_arr, N, 1, 10,
+                                              ctypes.byref(out)) == 0
+        return out.value
+    pw = 5 + 5 + 15  # slice record, q = 5
+    small = [300] * 8
+    pairs = sum(small) * 2
+    # N = 2048 allows K = 8, N = 1024 K = 4, N = 256 no split
+    d8 = ws(small, [2] * 8, 2048) - ws(small, [2] * 8, 1024)
+    assert d8 >= pairs * 8 * pw * 8 - pairs * 4 * pw * 8
+    big = [40000, 30000]  # 70000 x 1 pairs >= 65536: one wave per pair
+    g1 = [1, 1]
+    assert ws(big, g1, 2048) - ws(big, g1, 1024) < pairs * 8 * pw * 8

@@ -260,3 +260,103 @@ def test_batched_workload4_two_full_size_starts_vs_oracle(dev):
                                   want=("tau",))["tau"].cpu().numpy().argmax(1)
                for pp in (fitted[k], ref)]
         assert np.array_equal(lab[0], lab[1])
+
+
+def _tile(native, K, wpb=1, chunk=1, wps=4):
+    """opts.tile of the candidate shape with these fields."""
+    k = 0
+    while True:
+        s = native.cfust_batched_shape(k)
+        assert s is not None, (K, wpb, chunk, wps)
+        if (s["waves_per_pair"], s["waves_per_block"], s["chunk"], s["waves_per_simd"]) == \
+                (K, wpb, chunk, wps):
+            return k + 1
+        k += 1
+
+
+def test_batched_split_pairs_match_oracle(dev, orc):
+    """Several waves per pair in the batched form (each of a pair's K waves
+    integrates N / K of its points; bpart_kernel + bfinish_kernel): K = 1,
+    2, 4, 8 pinned through opts.tile, FP64, 3 EM iterations of 3 problems,
+    each against the oracle at the FP64 bar, and the split runs against
+    K = 1 to summation-order rounding.  The exact nu step at K = 4, FP32 at
+    K = 4 against FP32 at K = 1, graph against eager, and a poisoned
+    problem at K = 4."""
+    from paper_2005_06848_amd import native
+    import parity
+    probs, u = small_batch(3, 23, p=4, q=3, n_lo=80, n_hi=140, N=2048)
+    y, par, n, g = concat(probs)
+    keys = ("pi", "mu", "Sigma", "Delta", "nu")
+    off = np.concatenate([[0], np.cumsum(g)])
+    yd, ud = T(y, dev), T(u, dev)
+    P = lambda: {k: T(v, dev) for k, v in par.items()}
+    refs = [orc.em_fit(c["y"], c["params"], u, max_iter=3, tol=0.0) for c in probs]
+    runs = {}
+    for K in (1, 2, 4, 8):
+        print(f"[gpu] batched split K={K} fp64", flush=True)
+        fit, trace, n_iter, status = native.cfust_em_fit_batched(
+            yd, n, g, P(), ud, max_iter=3, tol=0.0, precision="fp64", tile=_tile(native, K))
+        assert np.all(status == 0), (K, status)
+        cfg = native.cfust_batched_config()
+        assert cfg["waves_per_pair"] == K and cfg["points_per_wave"] == 2048 // K
+        for k in range(3):
+            np.testing.assert_allclose(trace[k, :4], refs[k]["trace"], rtol=1e-10)
+            got = {kk: fit[kk].cpu().numpy()[off[k]:off[k + 1]] for kk in keys}
+            err = parity.params_rel_err(got, refs[k])
+            assert max(err.values()) < 1e-9, (K, k, err)
+        runs[K] = (fit, trace)
+    for K in (2, 4, 8):
+        np.testing.assert_allclose(runs[K][1], runs[1][1], rtol=1e-12)
+    print("[gpu] batched split K=4 exact nu", flush=True)
+    fit, trace, n_iter, status = native.cfust_em_fit_batched(
+        yd, n, g, P(), ud, max_iter=2, tol=0.0, nu_mode="exact", tile=_tile(native, 4))
+    assert np.all(status == 0), status
+    for k, c in enumerate(probs[:2]):
+        ref = orc.em_fit(c["y"], c["params"], u, max_iter=2, tol=0.0, nu_mode=orc.NU_EXACT)
+        np.testing.assert_allclose(trace[k, :3], ref["trace"], rtol=1e-10)
+        got = {kk: fit[kk].cpu().numpy()[off[k]:off[k + 1]] for kk in keys}
+        assert max(parity.params_rel_err(got, ref).values()) < 1e-9, k
+    print("[gpu] batched split K=4 fp32 vs K=1, graph vs eager", flush=True)
+    f1, t1, _, s1 = native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=3, tol=0.0,
+                                                precision="fp32", tile=_tile(native, 1))
+    f4, t4, _, s4 = native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=3, tol=0.0,
+                                                precision="fp32", tile=_tile(native, 4))
+    f4e, t4e, _, s4e = native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=3, tol=0.0,
+                                                   precision="fp32", tile=_tile(native, 4),
+                                                   graph=False)
+    assert np.all(s1 == 0) and np.all(s4 == 0) and np.all(s4e == 0)
+    np.testing.assert_allclose(t4, t1, rtol=1e-6)
+    np.testing.assert_array_equal(t4, t4e)
+    for key in keys:
+        np.testing.assert_array_equal(f4[key].cpu().numpy(), f4e[key].cpu().numpy())
+    print("[gpu] batched split K=4 poisoned problem", flush=True)
+    yb = y.copy()
+    yb[n[0] + 3, 1] = np.nan  # an observation of problem 1
+    fb, tb, _, sb = native.cfust_em_fit_batched(T(yb, dev), n, g, P(), ud, max_iter=3, tol=0.0,
+                                                precision="fp64", tile=_tile(native, 4))
+    assert sb[1] == native.ENONFINITE and sb[0] == 0 and sb[2] == 0, sb
+    np.testing.assert_array_equal(tb[[0, 2]], runs[4][1][[0, 2]])
+
+
+def test_batched_split_limits_and_autotune(dev):
+    """A shape with more waves per pair than the batch allows is rejected
+    (N = 512 allows K <= 2), and the autotuner's choice for a small batch
+    reports K and N / K points per wave; its result equals the same shape
+    pinned through opts.tile, bit for bit."""
+    from paper_2005_06848_amd import native
+    probs, u = small_batch(3, 29, p=4, q=3, n_lo=80, n_hi=140, N=512)
+    y, par, n, g = concat(probs)
+    yd, ud = T(y, dev), T(u, dev)
+    P = lambda: {k: T(v, dev) for k, v in par.items()}
+    with pytest.raises(native.CfustError):
+        native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=1, tol=0.0, tile=_tile(native, 4))
+    print("[gpu] batched autotune, small batch", flush=True)
+    fa, ta, _, sa = native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=2, tol=0.0)
+    cfg = native.cfust_batched_config()
+    assert np.all(sa == 0)
+    assert cfg["waves_per_pair"] in (1, 2) and cfg["points_per_wave"] == 512 // cfg["waves_per_pair"]
+    assert cfg["tuned_ms"] > 0
+    tile = _tile(native, cfg["waves_per_pair"], cfg["waves_per_block"], cfg["chunk"],
+                 cfg["waves_per_simd"])
+    fp, tp, _, sp = native.cfust_em_fit_batched(yd, n, g, P(), ud, max_iter=2, tol=0.0, tile=tile)
+    np.testing.assert_array_equal(ta, tp)
