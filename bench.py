@@ -392,8 +392,11 @@ def batched_form(args, native, torch, np, inputs, dev):
     iterations and autotuned launch shape; compared with fitting the same
     starts one after another through the single-problem entry point."""
     if args.no_batched_large:
-        return {"small_problems": batched_small(args, native, torch, np, inputs, dev),
-                "paper_size_problems": batched_paper_size(args, native, torch, np, inputs, dev)}
+        res = {}
+        if not args.no_batched_small:
+            res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
+        res["paper_size_problems"] = batched_paper_size(args, native, torch, np, inputs, dev)
+        return res
     print("[bench] batched: generating 64 starts", file=sys.stderr, flush=True)
     probs = inputs.batched_problems(64)
     u = inputs.qmc_points(4096, 5)
@@ -442,7 +445,8 @@ def batched_form(args, native, torch, np, inputs, dev):
         res["sequential_kernel_seconds"] = round(kern, 3)
         res["sequential_host_us_per_iteration"] = round(1e6 * (ts - kern) / seq_iters, 1)
         res["sequential_kernel_ms_per_iteration"] = round(1e3 * kern / seq_iters, 3)
-    res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
+    if not args.no_batched_small:
+        res["small_problems"] = batched_small(args, native, torch, np, inputs, dev)
     res["paper_size_problems"] = batched_paper_size(args, native, torch, np, inputs, dev)
     return res
 
@@ -643,6 +647,8 @@ def parse():
                     help="skip the surrogate-form leg (n=1000000, p=q=6, g=4, N=8192)")
     ap.add_argument("--no-batched-large", action="store_true",
                     help="batched leg: only the 256 small problems, not the 64 starts")
+    ap.add_argument("--no-batched-small", action="store_true",
+                    help="batched leg: skip the 256 small problems (n 150-500)")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the 50-iteration EM fit of the benchmark workload")
     ap.add_argument("--surrogate-em", action="store_true",

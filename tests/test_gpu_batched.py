@@ -99,19 +99,22 @@ def test_batched_fp32_q5_matches_oracle(dev, orc):
     from paper_2005_06848_amd import native
     probs, u = small_batch(3, 11, p=5, q=5, n_lo=200, n_hi=300, N=1024)
     y, par, n, g = concat(probs)
-    print("[gpu] batched fp32 q=5 3 problems", flush=True)
-    fit, trace, n_iter, status = native.cfust_em_fit_batched(
-        T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()}, T(u, dev), max_iter=2, tol=0.0,
-        precision="fp32")
-    assert np.all(status == 0), status
-    fitted = split({k: v.cpu().numpy() for k, v in fit.items() if k in par}, g)
-    for k, c in enumerate(probs):
-        ref = orc.em_fit(c["y"], c["params"], u, max_iter=2, tol=0.0)
-        assert abs(trace[k, 0] / ref["trace"][0] - 1) <= 1e-7, (k, trace[k, 0], ref["trace"][0])
-        np.testing.assert_allclose(trace[k, :3], ref["trace"], rtol=1e-6)
-        for key in ("pi", "mu", "Sigma", "Delta", "nu"):
-            r = ref[key]
-            assert np.max(np.abs(fitted[k][key] - r)) <= 1e-4 * max(np.max(np.abs(r)), 1e-300), (k, key)
+    refs = [orc.em_fit(c["y"], c["params"], u, max_iter=2, tol=0.0) for c in probs]
+    # the autotuned shape, and one wave per pair pinned (the persistent
+    # kernel with its values parked in LDS across integral B)
+    for tile in (0, _tile(native, 1)):
+        print(f"[gpu] batched fp32 q=5 3 problems tile={tile}", flush=True)
+        fit, trace, n_iter, status = native.cfust_em_fit_batched(
+            T(y, dev), n, g, {k: T(v, dev) for k, v in par.items()}, T(u, dev), max_iter=2,
+            tol=0.0, precision="fp32", tile=tile)
+        assert np.all(status == 0), status
+        fitted = split({k: v.cpu().numpy() for k, v in fit.items() if k in par}, g)
+        for k, ref in enumerate(refs):
+            assert abs(trace[k, 0] / ref["trace"][0] - 1) <= 1e-7, (k, trace[k, 0], ref["trace"][0])
+            np.testing.assert_allclose(trace[k, :3], ref["trace"], rtol=1e-6)
+            for key in ("pi", "mu", "Sigma", "Delta", "nu"):
+                r = ref[key]
+                assert np.max(np.abs(fitted[k][key] - r)) <= 1e-4 * max(np.max(np.abs(r)), 1e-300), (k, key)
 
 def test_batched_graph_equals_eager_and_single(dev):
     """Graph and eager batched runs agree bit for bit.  At N = 256 a
