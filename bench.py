@@ -475,11 +475,10 @@ def batched_paper_size(args, native, torch, np, inputs, dev):
                                                                tol=0.0, precision="fp32",
                                                                tile=tile)
         torch.cuda.synchronize()
-        assert int((status != 0).sum()) == 0
-        return time.perf_counter() - t0, trace
+        return time.perf_counter() - t0, trace, int((status != 0).sum())
 
     native.cfust_em_fit_batched(y, n, g, par, u, max_iter=1, tol=0.0, precision="fp32")
-    ta, trace_a = fit(0)
+    ta, trace_a, failed = fit(0)
     shape = native.cfust_batched_config()
     one_wave = {}
     k = 0
@@ -491,14 +490,17 @@ def batched_paper_size(args, native, torch, np, inputs, dev):
             one_wave[k + 1] = fit(k + 1)
         k += 1
     best = min(one_wave, key=lambda t: one_wave[t][0])
-    t1, trace_1 = one_wave[best]
+    t1, trace_1, failed_1 = one_wave[best]
     pairs = sum(n[k] * g[k] for k in range(len(n)))
+    d = np.abs(trace_a[:, it] / trace_1[:, it] - 1)
+    rel_diff = float(d[np.isfinite(d)].max()) if np.isfinite(d).any() else None
     return {"workload": "32 starts, n=202, g~U{2..6}, p=q=5, N=4096, fp32 integrand, 50 iterations",
             "pairs_per_iteration": pairs, "seconds": round(ta, 4), "launch_shape": shape,
             "one_wave_per_pair_best_seconds": round(t1, 4),
             "one_wave_per_pair_best_shape": native.cfust_batched_shape(best - 1),
-            "speedup_of_tuned_split": round(t1 / ta, 3),
-            "final_loglik_rel_diff_vs_one_wave": float(np.max(np.abs(trace_a[:, it] / trace_1[:, it] - 1)))}
+            "speedup_of_tuned_split": round(t1 / ta, 3), "failed": failed,
+            "failed_one_wave": failed_1,
+            "final_loglik_rel_diff_vs_one_wave": rel_diff}
 
 
 def batched_small(args, native, torch, np, inputs, dev):
