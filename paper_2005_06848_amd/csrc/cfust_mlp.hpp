@@ -212,18 +212,24 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const bf16* __restrict__
 // bf16 tile, overwritten layer by layer after a barrier); weights are read
 // k-contiguous from global memory (L2-resident, [out][in] layout).  Wave w
 // owns output columns [w N/4, (w+1) N/4) of every layer and all the block's
-// rows, as RT x (N/64) tiles of v_mfma_f32_16x16x32_bf16 (gfx950): lane l
-// supplies A[l%16][8(l/16) .. +7] and B[8(l/16) .. +7][l%16] and receives
-// D[4(l/16) + i][l%16], i = 0..3.  A wave's weight loads are shared by its
-// RT row tiles, so more rows per block mean fewer L2 bytes per MFMA.  HBM
-// traffic is the input rows (bf16) and the fp32 outputs only.  Rows at or
-// past `rows` are zero on input and never stored.
+// rows.  Each 16 x 16 output tile is one v_mfma_f32_16x16x32_bf16 (gfx950)
+// per 32 inputs with the weights as the A operand and the activations as B,
+// so the tile comes out transposed (features x rows): lane l supplies
+// W[c0 + l%16][k0 + 8(l/16) .. +7] and H[r0 + l%16][k0 + 8(l/16) .. +7] and
+// receives the four consecutive features c0 + 4(l/16) + t, t = 0..3, of row
+// r0 + l%16.  Bias, SiLU and the bf16 rounding then end in one 8-byte LDS
+// store per tile and lane (one 16-byte store of fp32 outputs in the last
+// layer).  A wave's weight loads are shared by its RT row tiles and are
+// issued one 32-input step ahead of the MFMAs that use them.  HBM traffic is
+// the input rows (bf16) and the fp32 outputs only.  Rows at or past `rows`
+// are zero on input and never stored.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
 constexpr int kFusedLd = kMlpHid + 8;  // LDS row pitch (528 bytes)
 // row tiles per block: 64 rows.  128 rows (half the L2 weight bytes per
-// MFMA, half the blocks per CU) made the n = 1e6 network E-step 13% slower;
-// the kernel is bound by latency, not by L2.
+// MFMA, half the blocks per CU) made the n = 1e6 network E-step 13% slower
+// in the first version of this kernel.
 constexpr int kInferRT = 4;
 
 template <int K, int N, bool LAST, int RT>
@@ -231,52 +237,74 @@ __device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* _
                                             const float* __restrict__ b, float* __restrict__ P,
                                             int64_t row0, int64_t rows, int lane, int w) {
   constexpr int CT = N / 64;  // 16-column tiles per wave
+  constexpr int KS = K / 32;  // 32-input steps
   const int colbase = w * (N / 4);
   const int r16 = lane & 15, kg = lane >> 4;
-  float4_t acc[RT][CT];
+  // bias of this lane's four features in each column tile
+  float4_t bias[CT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int j = 0; j < CT; ++j)
+    bias[j] = *reinterpret_cast<const float4_t*>(b + colbase + 16 * j + 4 * kg);
+  float4_t acc[CT][RT];
 #pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < CT; ++j)
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8_t a[RT], bw[CT];
+    for (int i = 0; i < RT; ++i) acc[j][i] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const bf16* wrow = W + (size_t)(colbase + r16) * K + 8 * kg;
+  bf16x8_t bw[CT];
 #pragma unroll
-    for (int j = 0; j < CT; ++j)
-      bw[j] = *reinterpret_cast<const bf16x8_t*>(W + (size_t)(colbase + 16 * j + r16) * K + k0 +
-                                                 8 * kg);
+  for (int j = 0; j < CT; ++j) bw[j] = *reinterpret_cast<const bf16x8_t*>(wrow + (size_t)16 * j * K);
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k0 = 32 * s;
+    // next step's weights in flight while this step's MFMAs run
+    bf16x8_t nw[CT];
+    if (s + 1 < KS) {
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+        nw[j] = *reinterpret_cast<const bf16x8_t*>(wrow + (size_t)16 * j * K + k0 + 32);
+    }
+    bf16x8_t a[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
       a[i] = *reinterpret_cast<const bf16x8_t*>(Hs + (16 * i + r16) * kFusedLd + k0 + 8 * kg);
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < CT; ++j)
 #pragma unroll
-      for (int j = 0; j < CT; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < RT; ++i)
+        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], a[i], acc[j][i], 0, 0, 0);
+    if (s + 1 < KS) {
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bw[j] = nw[j];
+    }
   }
   __syncthreads();  // every wave has read this layer's input
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int j = 0; j < CT; ++j) {
+    const int col = colbase + 16 * j + 4 * kg;
 #pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      const int col = colbase + 16 * j + r16;
-      const float bias = b[col];
+    for (int i = 0; i < RT; ++i) {
+      const int row = 16 * i + r16;
+      const float4_t z = acc[j][i] + bias[j];
+      if (LAST) {
+        if (row0 + row < rows)
+          *reinterpret_cast<float4_t*>(P + (size_t)(row0 + row) * kMlpPad + col) = z;
+      } else {
+        ushort4_t h;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int row = 16 * i + 4 * kg + t;
-        const float z = acc[i][j][t] + bias;
-        if (LAST) {
-          if (row0 + row < rows) P[(size_t)(row0 + row) * kMlpPad + col] = z;
-        } else {
-          Hs[row * kFusedLd + col] = f2bf(z * sigmoid_f(z));
-        }
+        for (int t = 0; t < 4; ++t) h[t] = f2bf(z[t] * sigmoid_f(z[t]));
+        *reinterpret_cast<ushort4_t*>(Hs + row * kFusedLd + col) = h;
       }
     }
+  }
   __syncthreads();
 }
 
+// Three resident waves per SIMD (139 VGPRs, no AGPRs): 779 against 876 us
+// per 2^20 rows for the compiler's two (78 VGPRs + 96 AGPRs); four waves
+// spill 24 B/lane and measured the same as three.
 template <int RT>
-__global__ __launch_bounds__(256) void mlp_infer_kernel(const bf16* __restrict__ X, int64_t rows,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mlp_infer_kernel(const bf16* __restrict__ X, int64_t rows,
                                                         const bf16* __restrict__ wb,
                                                         const float* __restrict__ params,
                                                         float* __restrict__ P) {
