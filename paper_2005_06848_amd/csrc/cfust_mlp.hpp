@@ -227,10 +227,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const bf16* __restrict__
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short ushort4_t __attribute__((ext_vector_type(4)));
 constexpr int kFusedLd = kMlpHid + 8;  // LDS row pitch (528 bytes)
-// row tiles per block: 64 rows.  128 rows (half the L2 weight bytes per
-// MFMA, half the blocks per CU) made the n = 1e6 network E-step 13% slower
-// in the first version of this kernel.
-constexpr int kInferRT = 4;
+// row tiles per block: 128 rows, which halves the L2 weight bytes per MFMA
+// against 64 rows (710 against 775 us per 2^20 rows, bit-identical outputs;
+// in the first version of this kernel 128 rows had been 13% slower).
+constexpr int kInferRT = 8;
 
 template <int K, int N, bool LAST, int RT>
 __device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* __restrict__ W,
@@ -300,11 +300,12 @@ __device__ __forceinline__ void fused_layer(bf16* __restrict__ Hs, const bf16* _
   __syncthreads();
 }
 
-// Three resident waves per SIMD (139 VGPRs, no AGPRs): 779 against 876 us
-// per 2^20 rows for the compiler's two (78 VGPRs + 96 AGPRs); four waves
-// spill 24 B/lane and measured the same as three.
+// Two resident waves per SIMD at 128 rows per block (256 VGPRs, 16 B/lane
+// of spill outside the MFMA loop; the LDS tile of 67.6 KB allows two blocks
+// per CU).  At 64 rows three waves (139 VGPRs) took 779 us per 2^20 rows
+// against 876 us for the compiler's two; four spilled and measured the same.
 template <int RT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mlp_infer_kernel(const bf16* __restrict__ X, int64_t rows,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void mlp_infer_kernel(const bf16* __restrict__ X, int64_t rows,
                                                         const bf16* __restrict__ wb,
                                                         const float* __restrict__ params,
                                                         float* __restrict__ P) {
