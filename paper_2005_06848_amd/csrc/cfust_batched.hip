@@ -104,7 +104,7 @@ int make_bplan(int P, int p, int q, const int64_t* n_obs, const int* g, int N, i
     if (n_obs[k] < 1 || g[k] < 1 || g[k] > kMaxG) return CFUST_EINVAL;
     gmax = std::max(gmax, g[k]);
   }
-  size_t per_obs = (size_t)(gmax * pl->W + gmax + p + 1) * sizeof(double);
+  size_t per_obs = (size_t)stats_lds_per_obs(p, gmax, pl->W) * sizeof(double);
   int tile = (int)((48 * 1024) / per_obs);
   pl->tile = tile < 1 ? 1 : (tile > 16 ? 16 : tile);
   pl->lds_bytes = per_obs * pl->tile;

@@ -90,7 +90,7 @@ Plan make_plan(int64_t n, int p, int q, int g, int N, int prec, int64_t check_m)
   pl.S = sl.S;
   pl.GS = g * sl.S;
   pl.stride = CompLayout(p, q).stride;
-  size_t per_obs = (size_t)(g * pl.W + g + p + 1) * sizeof(double);
+  size_t per_obs = (size_t)stats_lds_per_obs(p, g, pl.W) * sizeof(double);
   int tile = (int)((48 * 1024) / per_obs);
   pl.tile = tile < 1 ? 1 : (tile > 16 ? 16 : tile);
   const int64_t per = stats_per_block(n, pl.tile);

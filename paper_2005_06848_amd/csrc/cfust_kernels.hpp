@@ -1243,9 +1243,20 @@ __global__ void chi_list_kernel(const double* __restrict__ dofs, int nd,
 // ---------------------------------------------------------------------------
 constexpr int kStatsPerBlock = 2048;  // statistic entries per block (256 threads x 8)
 
+// LDS doubles per observation of a statistics tile: g factor rows of
+// 1 + W + p (a constant 1, the pair record, r = y_j - mu_i), g
+// responsibilities, the y row and the log-density.
+__host__ __device__ constexpr int stats_lds_per_obs(int p, int g, int W) {
+  return g * (1 + W + p) + g + p + 1;
+}
+
 // Body of one statistics block over observations [j0, j1) of one problem.
 // partial_row: this block's GS partial sums; ll_slot: its log-likelihood part.
-// ebase selects which 2048 statistic entries this block owns.
+// ebase selects which 2048 statistic entries this block owns.  Every partial
+// sum is tau times a product of at most three factors of the pair's factor
+// row (a7: s1 = tau, s2 = tau e2, s3 = tau e2 r, s4 = tau e3, s5 = tau e4,
+// s6 = tau r e3^T, s7 = tau e2 r r^T, s8 = tau (e1 - e2)), so each thread
+// keeps three row offsets per entry and accumulates without branching.
 __device__ __forceinline__ void stats_body(
     const double* __restrict__ y, int64_t n, int p, int q, int g, const double* __restrict__ mu,
     const double* __restrict__ pairbuf, int W, int64_t j0, int64_t j1, int tile, int with_stats,
@@ -1256,80 +1267,112 @@ __device__ __forceinline__ void stats_body(
   const int tid = threadIdx.x;
   const StatLayout sl(p, q);
   const int GS = g * sl.S;
-  // LDS: tile records [tile][g][W], taus [tile][g], y tile [tile][p], ll [tile]
-  double* recs = sm;
-  double* taus = recs + tile * g * W;
+  const int FW = 1 + W + p;  // factor row: 1 | record[W] | r[p]
+  // LDS: factor rows [tile][g][FW], taus [tile][g], y tile [tile][p], ll [tile]
+  double* F = sm;
+  double* taus = F + tile * g * FW;
   double* ys = taus + tile * g;
   double* lls = ys + tile * p;
   constexpr int kPer = kStatsPerBlock / 256;
   double acc[kPer];
-  int kind[kPer], ia[kPer], xa[kPer], xb[kPer];
+  int ia[kPer], f1[kPer], f2[kPer], f3[kPer];
+  bool live[kPer];
+  const int R0 = 1, Rr = 1 + W;  // row offsets of record[0] and of r[0]
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     acc[e] = 0.0;
-    int idx = ebase + tid + e * 256;
-    kind[e] = -1;
-    if (idx < GS && with_stats) {
-      int i = idx / sl.S;
-      int s = idx - i * sl.S;
+    const int idx = ebase + tid + e * 256;
+    live[e] = idx < GS && with_stats;
+    ia[e] = 0;
+    f1[e] = f2[e] = f3[e] = 0;
+    if (live[e]) {
+      const int i = idx / sl.S;
+      const int s = idx - i * sl.S;
       ia[e] = i;
-      xa[e] = 0;
-      xb[e] = 0;
-      if (s == sl.s1) kind[e] = 1;
-      else if (s == sl.s2) kind[e] = 2;
-      else if (s < sl.s4) { kind[e] = 3; xa[e] = s - sl.s3; }
-      else if (s < sl.s5) { kind[e] = 4; xa[e] = s - sl.s4; }
-      else if (s < sl.s6) {
-        kind[e] = 5;
+      if (s == sl.s1) {
+      } else if (s == sl.s2) {
+        f1[e] = R0 + 1;
+      } else if (s < sl.s4) {
+        f1[e] = R0 + 1;
+        f2[e] = Rr + (s - sl.s3);
+      } else if (s < sl.s5) {
+        f1[e] = R0 + 3 + (s - sl.s4);
+      } else if (s < sl.s6) {
         int t = s - sl.s5, a = 0;
         while (t >= q - a) { t -= q - a; ++a; }
-        xa[e] = a;
-        xb[e] = a + t;
+        f1[e] = R0 + 3 + q + tri_index(a, a + t, q);
       } else if (s < sl.s7) {
-        kind[e] = 6;
-        xa[e] = (s - sl.s6) / q;
-        xb[e] = (s - sl.s6) % q;
+        f1[e] = Rr + (s - sl.s6) / q;
+        f2[e] = R0 + 3 + (s - sl.s6) % q;
       } else if (s < sl.s8) {
-        kind[e] = 7;
         int t = s - sl.s7, a = 0;
         while (t >= p - a) { t -= p - a; ++a; }
-        xa[e] = a;
-        xb[e] = a + t;
+        f1[e] = R0 + 1;
+        f2[e] = Rr + a;
+        f3[e] = Rr + a + t;
       } else {
-        kind[e] = 8;
+        f1[e] = R0 + 2;
       }
     }
   }
   double ll_acc = 0.0;
   for (int64_t t0 = j0; t0 < j1 && ok; t0 += tile) {
     const int nt = (int)min((int64_t)tile, j1 - t0);
-    for (int x = tid; x < nt * g * W; x += 256) recs[x] = pairbuf[t0 * g * W + x];
+    // records into their factor rows, several loads in flight per thread
+    {
+      constexpr int kStage = 8;
+      const int count = nt * g * W;
+      const double* src = pairbuf + t0 * g * W;
+      for (int base = 0; base < count; base += 256 * kStage) {
+        double v[kStage];
+#pragma unroll
+        for (int c = 0; c < kStage; ++c) {
+          const int x = base + c * 256 + tid;
+          v[c] = x < count ? src[x] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kStage; ++c) {
+          const int x = base + c * 256 + tid;
+          if (x < count) {
+            const int k = x / W;
+            F[k * FW + R0 + (x - k * W)] = v[c];
+          }
+        }
+      }
+    }
     for (int x = tid; x < nt * p; x += 256) ys[x] = y[t0 * p + x];
     __syncthreads();
+    // the rest of each factor row: the constant 1 and r = y_j - mu_i
+    for (int x = tid; x < nt * g * (p + 1); x += 256) {
+      const int k = x / (p + 1), a = x - k * (p + 1);
+      const int jx = k / g, i = k - jx * g;
+      F[k * FW + (a == p ? 0 : Rr + a)] = a == p ? 1.0 : ys[jx * p + a] - mu[i * p + a];
+    }
     if (tid < nt) {
-      const double* rj = recs + tid * g * W;
+      const double* rj = F + tid * g * FW + R0;
       double M = -INFINITY;
-      for (int i = 0; i < g; ++i) M = fmax(M, rj[i * W]);
+      for (int i = 0; i < g; ++i) M = fmax(M, rj[i * FW]);
       double ssum = 0.0;
-      for (int i = 0; i < g; ++i) ssum += exp(rj[i * W] - M);
+      for (int i = 0; i < g; ++i) ssum += exp(rj[i * FW] - M);
       double lf = M + log(ssum);
       lls[tid] = lf;
       const int64_t jj = t0 + tid;
       for (int i = 0; i < g; ++i) {
-        double ta = exp(rj[i * W] - lf);
+        const double* ri = rj + i * FW;
+        double ta = exp(ri[0] - lf);
         taus[tid * g + i] = ta;
         const int64_t ji = jj * g + i;
         if (!writer) continue;
         if (tau_out) tau_out[ji] = ta;
-        if (logf_out) logf_out[ji] = rj[i * W];
-        if (e2_out) e2_out[ji] = rj[i * W + 1];
-        if (e1_out) e1_out[ji] = rj[i * W + 1] + rj[i * W + 2];
+        if (logf_out) logf_out[ji] = ri[0];
+        if (e2_out) e2_out[ji] = ri[1];
+        if (e1_out) e1_out[ji] = ri[1] + ri[2];
         if (e3_out)
-          for (int k = 0; k < q; ++k) e3_out[ji * q + k] = rj[i * W + 3 + k];
+          for (int k = 0; k < q; ++k) e3_out[ji * q + k] = ri[3 + k];
         if (e4_out)
           for (int a = 0; a < q; ++a)
             for (int b = 0; b < q; ++b)
-              e4_out[(ji * q + a) * q + b] = rj[i * W + 3 + q + tri_index(min(a, b), max(a, b), q)];
+              e4_out[(ji * q + a) * q + b] = ri[3 + q + tri_index(min(a, b), max(a, b), q)];
       }
     }
     __syncthreads();
@@ -1337,30 +1380,18 @@ __device__ __forceinline__ void stats_body(
       for (int x = 0; x < nt; ++x) ll_acc += lls[x];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      if (kind[e] < 0) continue;
+      if (!live[e]) continue;
       const int i = ia[e];
-      const double* mui = mu + i * p;
       double a_acc = acc[e];
+#pragma unroll 1
       for (int x = 0; x < nt; ++x) {
         const double ta = taus[x * g + i];
-        const double* rec = recs + (x * g + i) * W;
-        const double* yx = ys + x * p;
-        double val;
+        const double* f = F + (x * g + i) * FW;
+        const double val = ta * f[f1[e]] * f[f2[e]] * f[f3[e]];
         // a pair whose responsibility underflows to zero adds nothing (the
         // limit of tau e as tau -> 0): its GHK ratio T_B/T_A may be beyond
         // the double range, and 0 * inf would poison the sums
-        if (ta == 0.0) continue;
-        switch (kind[e]) {
-          case 1: val = ta; break;
-          case 2: val = ta * rec[1]; break;
-          case 3: val = ta * rec[1] * (yx[xa[e]] - mui[xa[e]]); break;
-          case 4: val = ta * rec[3 + xa[e]]; break;
-          case 5: val = ta * rec[3 + q + tri_index(xa[e], xb[e], q)]; break;
-          case 6: val = ta * (yx[xa[e]] - mui[xa[e]]) * rec[3 + xb[e]]; break;
-          case 7: val = ta * rec[1] * (yx[xa[e]] - mui[xa[e]]) * (yx[xb[e]] - mui[xb[e]]); break;
-          default: val = ta * rec[2]; break;
-        }
-        a_acc += val;
+        a_acc = ta == 0.0 ? a_acc : a_acc + val;
       }
       acc[e] = a_acc;
     }
@@ -1369,7 +1400,7 @@ __device__ __forceinline__ void stats_body(
   if (with_stats) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e)
-      if (kind[e] >= 0) partial_row[ebase + tid + e * 256] = acc[e];
+      if (live[e]) partial_row[ebase + tid + e * 256] = acc[e];
   }
   if (tid == 0 && writer) *ll_slot = ll_acc;
 }
