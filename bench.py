@@ -49,10 +49,7 @@ HBM_PEAK_GBS = 8000.0
 # Phi^-1 50, an exp-scaled accumulation 20), reported beside it.
 NOMINAL_COSTS = {"phi": 40, "phiinv": 50, "acc": 20}
 # measured per precision; "sources" is the digest of the kernel sources they
-# apply to (the model falls back to NOMINAL when it differs).  They were taken
-# on sources a586ea317c7806bb; the sources changed since only in the
-# statistics kernel, and the gfx950 code of every pair kernel and of the
-# diagnostic kernel compiles identically.
+# were measured on (the model falls back to NOMINAL when it differs).
 # FP64: Phi 99 (45 FMA, 5 MUL, 3 ADD, 1 TRANS), coordinate step 191, so
 # Phi^-1 191 - 99 - 1 = 91, accumulation 5 (4 ADD, 1 MUL).  FP32: Phi 41,
 # step 72, Phi^-1 30, accumulation 2 (its FP64 add and scale).
@@ -64,12 +61,11 @@ MEASURED_COSTS = {"sources": "3dd56fa4769c78c8",
 # WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
 # plain elementwise copy of known size), with the digest of the kernel
 # sources they were taken on: `traffic` is null once the sources differ.
-# FETCH_SIZE 3358.33 KiB x 1.99977 + WRITE_SIZE 7968.75 KiB x 0.99996 (the
-# copy probe, 262144 KiB each way, read 131087 and 262154): the writes are
-# the pair records alone, the reads y, the tables once per XCD and the
-# component blocks.  Taken on sources a586ea317c7806bb, whose pair-kernel code
-# is identical to that of the sources named here.
-PAIR_KERNEL_COUNTERS = {"sources": "3dd56fa4769c78c8", "traffic": 15036762}
+# FETCH_SIZE 3362.33 KiB x 1.99976 + WRITE_SIZE 7968.75 KiB x 0.99999 (the
+# copy probe, 262144 KiB each way, read 131087.88 and 262145.62): the writes
+# are the pair records alone, the reads y, the tables once per XCD and the
+# component blocks.
+PAIR_KERNEL_COUNTERS = {"sources": "3dd56fa4769c78c8", "traffic": 15045174}
 
 
 # the sources the pair kernels, their launches and the diagnostic
