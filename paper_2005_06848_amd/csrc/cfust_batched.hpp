@@ -9,6 +9,9 @@
 // Work decomposition: pairs of all problems form one index space
 // [0, sum_k n_k g_k); a persistent pair kernel pulls chunks of it from an
 // atomic counter, so problems of uneven size share the GPU without a tail.
+// For small batches the autotuner may split every pair's QMC points over K
+// waves (bpart_kernel over the index space of (pair, slice) items, then
+// bfinish_kernel per pair).
 #pragma once
 #include "cfust_kernels.hpp"
 
